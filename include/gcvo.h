@@ -1,0 +1,198 @@
+/*
+ * gcvo.h - C ABI of the MI355X (gfx950) Generalized-CVO registration library.
+ *
+ * The library solves the registration problem of the paper's Sec. "Classical
+ * RKHS loss functions" and Sec. "Generalized CVO": given a target cloud X and a
+ * source cloud Z, find the pose T in SE(3) that maximises
+ *
+ *     f(T) = sum_{i,j} k(x_i, T^{-1} z_j)                        eq. (rkhs_loss)
+ *     k(x, z) = sigma2 * exp(-1/2 (x - z)^T Sigma(x, z)^{-1} (x - z))   eq. (kernel)
+ *     Sigma(x_i, z_j) = Sigma(x_i; X) + R^T Sigma(z_j; Z) R          eq. (covariance)
+ *
+ * with per-point covariances from the n nearest points (eq. (covariance)), an
+ * eigenvalue bound per point (Remark 1), and Riemannian Gauss-Newton steps
+ * T <- T exp([-H_GN^{-1} g]^) (Algorithm 1, eq. (gn_update)), where g is the
+ * gradient of Lemma 1 and H_GN the approximate Hessian of eq. (hessian_gn) plus
+ * the connection term of eq. (connection_se3).
+ *
+ * Readings of what the paper leaves open, used throughout:
+ *   - Length scale: the per-point covariance is (ell^2 / 2) * S(p) where S(p)
+ *     has its largest eigenvalue normalised to 1 and the other two floored at
+ *     eig_ratio_min (rho); rho = 1 gives CVO's isotropic kernel (Remark 3).
+ *   - Cutoff: only pairs with ||x_i - T^{-1} z_j||^2 <= (cutoff_scale * ell)^2
+ *     enter the sums (the truncated double sum is the definition).
+ *   - The covariances are frozen at the current rotation for each step
+ *     (Remark 2); g is the gradient with the covariances frozen.
+ *   - Annealing: ell_{s+1} = max(anneal_factor * ell_s, length_scale_min); a
+ *     non-final stage ends when ||xi||_1 < stage_tol or after
+ *     max_iters_per_stage iterations; the final stage runs to ||xi||_1 < tol.
+ *   - Damping: if the Gauss-Newton step is not an ascent direction or H_GN is
+ *     numerically singular, the connection term is dropped and
+ *     (H_main - lambda * ||diag H_main||_2 * I) is used, lambda = 1e-6 * 10^m,
+ *     m = 0..6.
+ *
+ * Conventions.  Poses are row-major 4x4 double, T p = R p + t; twists are
+ * (omega, v), rotation first, with right perturbation T exp(xi^) (Notation
+ * section).  The result satisfies x ~ T^{-1} z: if the target was generated as
+ * x = G p from the source surface p, the expected answer is T = G^{-1}.
+ *
+ * Memory.  Point clouds are caller-owned DEVICE memory, float32, array of
+ * structures [n][3].  Shapes are caller-owned DEVICE memory, float32, structure
+ * of arrays [6][n] in the order (xx, xy, xz, yy, yz, zz).  Poses, parameters and
+ * info structs are HOST memory unless stated otherwise.  Scratch memory is a
+ * caller-provided DEVICE workspace of at least the size the matching
+ * *_workspace_size function returns, aligned to 256 bytes; the library never
+ * allocates device memory in these calls and never frees caller memory.
+ * Pinned host memory for completion flags is allocated once per process.
+ *
+ * Streams.  `stream` is a hipStream_t (NULL = the default stream).  All device
+ * work is enqueued on it.  gcvo_register, gcvo_eval_fgh and the info/T outputs
+ * of gcvo_register_batch are complete when the call returns (the call waits on
+ * the stream); gcvo_point_shapes returns without waiting.
+ *
+ * Errors.  Every function returns 0 (GCVO_OK) or a negative GCVO_ERR_* code;
+ * no exception or abort crosses the ABI.  On error, pose outputs are left
+ * untouched.  Not converging within max_iters is not an error: info.converged
+ * is 0.  Calls are reentrant; two calls that share a workspace must not overlap.
+ *
+ * Determinism.  Reductions use a fixed order and no floating-point atomics, so
+ * repeated calls on the same device and inputs give bitwise identical results.
+ */
+#ifndef GCVO_H
+#define GCVO_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GCVO_OK 0
+#define GCVO_ERR_INVALID (-1)        /* null pointer, bad size, non-finite input, T not in SE(3), bad parameter */
+#define GCVO_ERR_TOO_FEW_POINTS (-2) /* a cloud has fewer points than knn                                        */
+#define GCVO_ERR_NO_PAIRS (-3)       /* no (target, source) pair within the cutoff at some iteration            */
+#define GCVO_ERR_SINGULAR (-4)       /* the damped Gauss-Newton system could not be solved                      */
+#define GCVO_ERR_WORKSPACE (-5)      /* workspace NULL, too small or misaligned                                 */
+#define GCVO_ERR_HIP (-6)            /* a HIP runtime call failed                                               */
+#define GCVO_ERR_CAPACITY (-7)       /* a size exceeds the library's limits (see GCVO_MAX_*)                    */
+
+#define GCVO_PRECISION_FP32 0 /* pair terms in FP32, FP32 per-block sums, compensated cross-block sums, FP64 solve */
+#define GCVO_PRECISION_FP64 1 /* the same kernels instantiated in FP64 throughout                                  */
+
+#define GCVO_MAX_KNN 16
+#define GCVO_MAX_STAGES 16
+#define GCVO_MAX_POINTS (1LL << 26) /* per cloud */
+
+typedef struct gcvo_params {
+    double length_scale;      /* ell of the first stage, metres (> 0)                                   */
+    double length_scale_min;  /* ell of the final stage (0 < min <= length_scale); == length_scale: fixed */
+    double anneal_factor;     /* alpha in (0, 1]; must be < 1 when min < length_scale                    */
+    double cutoff_scale;      /* pair cutoff radius = cutoff_scale * ell (> 0; 3 in the paper's setups)  */
+    int knn;                  /* n nearest points per covariance, self included, 2..GCVO_MAX_KNN (10)    */
+    double eig_ratio_min;     /* rho in (0, 1]: floor of lambda / lambda_max per point (Remark 1)         */
+    double sigma2;            /* kernel amplitude sigma^2 (> 0; 1)                                       */
+    int max_iters;            /* total Gauss-Newton iterations over all stages (>= 1)                    */
+    int max_iters_per_stage;  /* iterations before a non-final stage is ended (>= 1)                     */
+    double tol;               /* final-stage stop: ||xi||_1 < tol (> 0; 1e-6)                            */
+    double stage_tol;         /* non-final stage stop: ||xi||_1 < stage_tol (> 0; 1e-4)                  */
+    int precision;            /* GCVO_PRECISION_FP32 (default) or GCVO_PRECISION_FP64                    */
+} gcvo_params;
+
+typedef struct gcvo_info {
+    int status;              /* mirrors the return value                                    */
+    int converged;           /* 1 when the final stage reached ||xi||_1 < tol               */
+    int iters;               /* Gauss-Newton iterations performed                           */
+    int stages;              /* length-scale stages entered                                 */
+    long long pairs_last;    /* pairs within the cutoff at the last iteration               */
+    double f;                /* objective at the last evaluated pose                        */
+    double g[6];             /* gradient (omega, v) at the last evaluated pose              */
+    double xi_l1;            /* ||xi||_1 of the last step                                   */
+    int stage_iters[GCVO_MAX_STAGES]; /* iterations spent in each stage                     */
+} gcvo_info;
+
+/* Fills p with the defaults named above (ell = 0.3 fixed, cutoff 3, knn 10,
+ * rho 0.01, sigma2 1, 30 iterations, tol 1e-6, stage_tol 1e-4, FP32). */
+void gcvo_default_params(gcvo_params *p);
+
+/* Bytes of device workspace gcvo_register needs for clouds of these sizes and
+ * these parameters; 0 if the arguments are invalid. */
+size_t gcvo_workspace_size(long long n_tgt, long long n_src, const gcvo_params *p);
+
+/*
+ * Registers one pair: Algorithm 1 with Gauss-Newton steps and length-scale
+ * annealing, starting at T_init (host, 4x4; NULL = identity).  Computes the
+ * per-point covariance shapes of both clouds (eq. (covariance), Remark 1) on
+ * the device, builds the target cell lists for every stage, then iterates.
+ * tgt_xyz / src_xyz: device float32 [n][3].  T_out (host, 4x4) receives the
+ * pose; info (host, may be NULL) the run summary.  Waits on `stream`.
+ */
+int gcvo_register(const float *tgt_xyz, long long n_tgt, const float *src_xyz, long long n_src,
+                  const double *T_init, const gcvo_params *p, double *T_out, gcvo_info *info,
+                  void *workspace, size_t workspace_bytes, void *stream);
+
+/* Bytes of device workspace gcvo_register_batch needs for n_pairs pairs whose
+ * largest target / source clouds are max_tgt / max_src points and whose total
+ * point counts are sum_tgt / sum_src; 0 if invalid. */
+size_t gcvo_batch_workspace_size(int n_pairs, long long sum_tgt, long long sum_src, long long max_tgt,
+                                 long long max_src, const gcvo_params *p);
+
+/*
+ * Registers n_pairs independent pairs in one pass over the device.  Pair k's
+ * target is tgt_xyz[tgt_off[k] .. tgt_off[k+1]) and its source
+ * src_xyz[src_off[k] .. src_off[k+1]) (device float32 [*][3]); the offsets are
+ * HOST int64 arrays of n_pairs + 1 entries.  T_init: host [n_pairs][16] or NULL
+ * (identity).  p: host array of n_pairs parameter sets, or one set shared by all
+ * pairs when shared_params != 0.  T_out: host [n_pairs][16]; info: host
+ * [n_pairs] or NULL.  A pair that fails (for example with no pairs in reach)
+ * reports its own status in info[k].status and keeps T_out[k] = T_init[k]; the
+ * call returns the first failing pair's code only for argument errors, HIP
+ * errors and workspace errors.  Waits on `stream`.
+ */
+int gcvo_register_batch(int n_pairs, const float *tgt_xyz, const long long *tgt_off, const float *src_xyz,
+                        const long long *src_off, const double *T_init, const gcvo_params *p,
+                        int shared_params, double *T_out, gcvo_info *info, void *workspace,
+                        size_t workspace_bytes, void *stream);
+
+/* Bytes of device workspace gcvo_eval_fgh needs; 0 if invalid. */
+size_t gcvo_eval_workspace_size(long long n_tgt, long long n_src);
+
+/*
+ * One evaluation of Algorithm 1's body without the step: at pose T (host 4x4),
+ * with the given shapes (device float32 SoA [6][n], covariance = (ell^2/2) *
+ * shape), returns f (eq. (rkhs_loss)), the gradient g = (g_omega, g_v) of
+ * Lemma 1 and the Gauss-Newton Hessian H (host, row-major 6x6) =
+ * -sum f J^T Sigma^{-1} J + C(g) (eq. (hessian_gn), eq. (connection_se3)),
+ * summed over pairs within `cutoff` metres; n_pairs (host, may be NULL)
+ * receives their number.  precision selects the FP32 or FP64 kernels.
+ * Waits on `stream`.
+ */
+int gcvo_eval_fgh(const float *tgt_xyz, const float *tgt_shape6, long long n_tgt, const float *src_xyz,
+                  const float *src_shape6, long long n_src, const double *T, double length_scale,
+                  double cutoff, double sigma2, int precision, double *f, double *g, double *H,
+                  long long *n_pairs, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Bytes of device workspace gcvo_point_shapes needs; 0 if invalid. */
+size_t gcvo_shapes_workspace_size(long long n);
+
+/*
+ * Per-point covariance shapes of one cloud (eq. (covariance) with Remark 1's
+ * bound): for each point p, the knn nearest points of the cloud including p
+ * (ties: smaller index first), M = 1/(knn-1) sum (q-p)(q-p)^T, eigenvalues
+ * l1 >= l2 >= l3, S = U diag(1, max(l2/l1, rho), max(l3/l1, rho)) U^T, or S = I
+ * when l1 is zero.  xyz: device float32 [n][3]; shape6_out: device float32
+ * [6][n].  Does not wait on `stream`.
+ */
+int gcvo_point_shapes(const float *xyz, long long n, int knn, double rho, float *shape6_out,
+                      void *workspace, size_t workspace_bytes, void *stream);
+
+/* Static text for a status code. */
+const char *gcvo_strerror(int status);
+
+/* ABI version of this header (major * 100 + minor). */
+int gcvo_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GCVO_H */

@@ -1,0 +1,614 @@
+/*
+ * FP64 CPU oracle for Generalized-CVO registration.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the correctness reference that the
+ * GPU library is judged against.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load it; the product path never does.  It
+ * shares no code, header, table or helper with the GPU library.
+ *
+ * Everything here is the plain definition, written for a reader to check against
+ * the paper by eye:
+ *   - per-point covariance from the n nearest points (Sec. "Anisotropic
+ *     covariance", eq. (kernel)/(covariance)) with the eigenvalue bound of
+ *     Remark 1, found by brute-force distance ranking;
+ *   - the objective f(T) = sum_ij k(x_i, T^{-1} z_j) (eq. (rkhs_loss)) as a
+ *     literal double loop over all (i, j), restricted to pairs within the cutoff;
+ *   - the Riemannian gradient of Lemma 1 (eq. (gradient));
+ *   - the Gauss-Newton Hessian -sum f J^T Sigma^{-1} J (eq. (hessian_gn)) plus
+ *     the connection term of eq. (connection_se3);
+ *   - the exact frozen-covariance derivative of the gradient (the first, second
+ *     and fourth terms of eq. (direction_derivative_gradf)) for derivative tests
+ *     and for the exact-Hessian (Newton) variant;
+ *   - the update T <- T exp(xi^) of eq. (gn_update) and Algorithm 1's loop.
+ *
+ * Readings of points the paper leaves open (length scale, eigenvalue floor,
+ * cutoff, damping, annealing schedule) are the ones stated in the project's
+ * design notes; each is marked "reading:" below.
+ *
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared.  Contraction is off
+ * so that every product and sum rounds exactly as written.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_OK 0
+#define ORC_ERR_INVALID (-1)
+#define ORC_ERR_TOO_FEW_POINTS (-2)
+#define ORC_ERR_NO_PAIRS (-3)
+#define ORC_ERR_SINGULAR (-4)
+
+/* ------------------------------------------------------------------------ */
+/* Small dense linear algebra, row-major.                                   */
+/* ------------------------------------------------------------------------ */
+
+/* a^ : the 3x3 skew matrix with (a^) b = a x b. */
+static void hat3(const double a[3], double A[9]) {
+    A[0] = 0.0;   A[1] = -a[2]; A[2] = a[1];
+    A[3] = a[2];  A[4] = 0.0;   A[5] = -a[0];
+    A[6] = -a[1]; A[7] = a[0];  A[8] = 0.0;
+}
+
+/* C[n x m] = A[n x k] * B[k x m] */
+static void matmul(const double *A, const double *B, double *C, int n, int k, int m) {
+    for (int r = 0; r < n; ++r)
+        for (int c = 0; c < m; ++c) {
+            double s = 0.0;
+            for (int q = 0; q < k; ++q) s += A[r * k + q] * B[q * m + c];
+            C[r * m + c] = s;
+        }
+}
+
+static void transpose(const double *A, double *At, int n, int m) {
+    for (int r = 0; r < n; ++r)
+        for (int c = 0; c < m; ++c) At[c * n + r] = A[r * m + c];
+}
+
+/* Inverse of a 3x3 matrix by Gauss-Jordan elimination with partial pivoting.
+ * Returns 0 when a pivot is exactly zero. */
+static int inv3(const double A[9], double Ainv[9]) {
+    double M[3][6];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 6; ++c) M[r][c] = (c < 3) ? A[r * 3 + c] : (c - 3 == r ? 1.0 : 0.0);
+    for (int col = 0; col < 3; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < 3; ++r)
+            if (fabs(M[r][col]) > fabs(M[piv][col])) piv = r;
+        if (M[piv][col] == 0.0) return 0;
+        if (piv != col)
+            for (int c = 0; c < 6; ++c) { double t = M[col][c]; M[col][c] = M[piv][c]; M[piv][c] = t; }
+        double p = M[col][col];
+        for (int c = 0; c < 6; ++c) M[col][c] /= p;
+        for (int r = 0; r < 3; ++r) {
+            if (r == col) continue;
+            double fct = M[r][col];
+            for (int c = 0; c < 6; ++c) M[r][c] -= fct * M[col][c];
+        }
+    }
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) Ainv[r * 3 + c] = M[r][c + 3];
+    return 1;
+}
+
+/* Solve A x = b for a general n x n system (n <= 6) by Gaussian elimination with
+ * partial pivoting.  Fails (returns 0) when a pivot falls below tiny * max|A|. */
+static int solve_lu(const double *A, const double *b, double *x, int n, double tiny) {
+    double M[6][7];
+    double amax = 0.0;
+    for (int r = 0; r < n; ++r) {
+        for (int c = 0; c < n; ++c) {
+            M[r][c] = A[r * n + c];
+            if (fabs(M[r][c]) > amax) amax = fabs(M[r][c]);
+        }
+        M[r][n] = b[r];
+    }
+    if (!(amax > 0.0) || !isfinite(amax)) return 0;
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+            if (fabs(M[r][col]) > fabs(M[piv][col])) piv = r;
+        if (!(fabs(M[piv][col]) >= tiny * amax)) return 0;
+        if (piv != col)
+            for (int c = 0; c <= n; ++c) { double t = M[col][c]; M[col][c] = M[piv][c]; M[piv][c] = t; }
+        for (int r = col + 1; r < n; ++r) {
+            double fct = M[r][col] / M[col][col];
+            for (int c = col; c <= n; ++c) M[r][c] -= fct * M[col][c];
+        }
+    }
+    for (int r = n - 1; r >= 0; --r) {
+        double s = M[r][n];
+        for (int c = r + 1; c < n; ++c) s -= M[r][c] * x[c];
+        x[r] = s / M[r][r];
+    }
+    return 1;
+}
+
+/* Classical Jacobi eigen-decomposition of a symmetric 3x3 matrix: repeatedly
+ * annihilate the largest off-diagonal entry with a plane rotation.  Eigenvalues
+ * are returned in descending order, eigenvectors as the matching columns of V. */
+static void jacobi_eig3(const double Ain[9], double lam[3], double V[9]) {
+    double A[9];
+    memcpy(A, Ain, sizeof A);
+    for (int i = 0; i < 9; ++i) V[i] = (i % 4 == 0) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        int p = 0, q = 1;
+        double big = fabs(A[1]);
+        if (fabs(A[2]) > big) { big = fabs(A[2]); p = 0; q = 2; }
+        if (fabs(A[5]) > big) { big = fabs(A[5]); p = 1; q = 2; }
+        double scale = fabs(A[0]) + fabs(A[4]) + fabs(A[8]);
+        if (big == 0.0 || big <= 1e-300 || big < 1e-18 * scale) break;
+        double app = A[p * 3 + p], aqq = A[q * 3 + q], apq = A[p * 3 + q];
+        double theta = (aqq - app) / (2.0 * apq);
+        double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        /* A <- J^T A J with J the rotation in the (p, q) plane. */
+        for (int k = 0; k < 3; ++k) {
+            double akp = A[k * 3 + p], akq = A[k * 3 + q];
+            A[k * 3 + p] = c * akp - s * akq;
+            A[k * 3 + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < 3; ++k) {
+            double apk = A[p * 3 + k], aqk = A[q * 3 + k];
+            A[p * 3 + k] = c * apk - s * aqk;
+            A[q * 3 + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < 3; ++k) {
+            double vkp = V[k * 3 + p], vkq = V[k * 3 + q];
+            V[k * 3 + p] = c * vkp - s * vkq;
+            V[k * 3 + q] = s * vkp + c * vkq;
+        }
+    }
+    double d[3] = {A[0], A[4], A[8]};
+    int order[3] = {0, 1, 2};
+    for (int a = 0; a < 3; ++a)
+        for (int b = a + 1; b < 3; ++b)
+            if (d[order[b]] > d[order[a]]) { int t = order[a]; order[a] = order[b]; order[b] = t; }
+    double Vs[9];
+    for (int k = 0; k < 3; ++k) {
+        lam[k] = d[order[k]];
+        for (int r = 0; r < 3; ++r) Vs[r * 3 + k] = V[r * 3 + order[k]];
+    }
+    memcpy(V, Vs, sizeof Vs);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Per-point covariance shapes (eq. (covariance), Remark 1).                */
+/* ------------------------------------------------------------------------ */
+
+/* Indices of the k nearest points of P to P[p] (P[p] itself included), ranked
+ * by squared Euclidean distance, ties broken by the smaller index. */
+static void knn_one(const double *P, long n, long p, int k, long *out, double *dist) {
+    int have = 0;
+    const double px = P[3 * p], py = P[3 * p + 1], pz = P[3 * p + 2];
+    for (long q = 0; q < n; ++q) {
+        double dx = P[3 * q] - px, dy = P[3 * q + 1] - py, dz = P[3 * q + 2] - pz;
+        double d = dx * dx + dy * dy + dz * dz;
+        /* Is (d, q) lexicographically smaller than the current k-th entry? */
+        if (have == k && !(d < dist[k - 1] || (d == dist[k - 1] && q < out[k - 1]))) continue;
+        int pos = (have < k) ? have++ : k - 1;
+        while (pos > 0 && (d < dist[pos - 1] || (d == dist[pos - 1] && q < out[pos - 1]))) {
+            dist[pos] = dist[pos - 1];
+            out[pos] = out[pos - 1];
+            --pos;
+        }
+        dist[pos] = d;
+        out[pos] = q;
+    }
+}
+
+int orc_knn(const double *P, long n, int k, long *out) {
+    if (!P || !out || n < 0 || k < 1 || k > 64) return ORC_ERR_INVALID;
+    if (n < k) return ORC_ERR_TOO_FEW_POINTS;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long p = 0; p < n; ++p) {
+        double dist[64];
+        knn_one(P, n, p, k, out + p * k, dist);
+    }
+    return ORC_OK;
+}
+
+/* Shape of one point from its neighbour list: M = 1/(k-1) sum (q-p)(q-p)^T
+ * centred at p (eq. (covariance)); eigenvalues l1 >= l2 >= l3;
+ * reading: S = U diag(1, max(l2/l1, rho), max(l3/l1, rho)) U^T (Remark 1's
+ * bound, applied per point with the largest mode normalised to one), and
+ * S = I when l1 <= 1e-300 (all neighbours coincide).  Output order
+ * (xx, xy, xz, yy, yz, zz). */
+static void shape_from_neighbours(const double *P, long p, const long *nb, int k, double rho,
+                                  double S6[6]) {
+    double M[9] = {0};
+    for (int a = 0; a < k; ++a) {
+        const double *q = P + 3 * nb[a];
+        double d[3] = {q[0] - P[3 * p], q[1] - P[3 * p + 1], q[2] - P[3 * p + 2]};
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) M[r * 3 + c] += d[r] * d[c];
+    }
+    for (int i = 0; i < 9; ++i) M[i] /= (double)(k - 1);
+    double lam[3], U[9];
+    jacobi_eig3(M, lam, U);
+    double S[9];
+    if (!(lam[0] > 1e-300)) {
+        for (int i = 0; i < 9; ++i) S[i] = (i % 4 == 0) ? 1.0 : 0.0;
+    } else {
+        double w[3] = {1.0, lam[1] / lam[0], lam[2] / lam[0]};
+        for (int m = 1; m < 3; ++m) if (w[m] < rho) w[m] = rho;
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) {
+                double s = 0.0;
+                for (int m = 0; m < 3; ++m) s += U[r * 3 + m] * w[m] * U[c * 3 + m];
+                S[r * 3 + c] = s;
+            }
+    }
+    S6[0] = S[0]; S6[1] = S[1]; S6[2] = S[2]; S6[3] = S[4]; S6[4] = S[5]; S6[5] = S[8];
+}
+
+int orc_point_shapes(const double *P, long n, int k, double rho, double *S6) {
+    if (!P || !S6 || n < 0 || k < 2 || k > 64 || !(rho > 0.0) || rho > 1.0) return ORC_ERR_INVALID;
+    if (n < k) return ORC_ERR_TOO_FEW_POINTS;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long p = 0; p < n; ++p) {
+        long nb[64];
+        double dist[64];
+        knn_one(P, n, p, k, nb, dist);
+        shape_from_neighbours(P, p, nb, k, rho, S6 + 6 * p);
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Objective, gradient and Hessians at a pose (literal double sum).         */
+/* ------------------------------------------------------------------------ */
+
+static void shape6_to_mat(const double s[6], double S[9]) {
+    S[0] = s[0]; S[1] = s[1]; S[2] = s[2];
+    S[3] = s[1]; S[4] = s[3]; S[5] = s[4];
+    S[6] = s[2]; S[7] = s[4]; S[8] = s[5];
+}
+
+/*
+ * Sums over every pair (i, j) with ||x_i - y_j||^2 <= cutoff^2, y_j = R^T (z_j - t):
+ *   Sigma_ij = (ell^2 / 2) * (S_i + Rs^T S_j Rs)      reading of eq. (covariance)
+ *            with the length scale folded in and Rs the rotation the covariances
+ *            are frozen at (Rs = R unless R_shape is given; Remark 2);
+ *   f_ij     = sigma2 * exp(-1/2 r^T Sigma_ij^{-1} r), r = x_i - y_j   (eq. (kernel))
+ *   J_j      = [ -y_j^ , I ]                                        (eq. (f_ij_J_j))
+ *   f       += f_ij
+ *   g       += -f_ij J_j^T Sigma^{-1} r                              (Lemma 1)
+ *   Hmain   += -f_ij J_j^T Sigma^{-1} J_j                            (eq. (hessian_gn))
+ *   T1      += f_ij (J^T u)(J^T u)^T, u = Sigma^{-1} r    (product rule on f_ij)
+ *   T2      += -f_ij [ u^ J_j ; 0 ]                       (derivative of J_j)
+ * cutoff <= 0 means no cutoff.  T1/T2 may be NULL.  The loop runs j-outer; each
+ * source point's slice is summed into its own slot and the slots are added in
+ * j order, so the result does not depend on the thread count.
+ */
+int orc_eval(const double *X, const double *SX, long nx, const double *Z, const double *SZ, long nz,
+             const double T[16], const double *R_shape, double ell, double cutoff, double sigma2,
+             double *f_out, double g_out[6], double Hmain_out[36], double *T1_out, double *T2_out,
+             long long *npairs_out) {
+    if (!X || !SX || !Z || !SZ || !T || nx < 0 || nz < 0 || !(ell > 0.0) || !f_out || !g_out ||
+        !Hmain_out)
+        return ORC_ERR_INVALID;
+    const int want_t = (T1_out != NULL) || (T2_out != NULL);
+    const int stride = 1 + 6 + 36 + (want_t ? 72 : 0);
+    double *slot = (double *)calloc((size_t)(nz > 0 ? nz : 1) * stride, sizeof(double));
+    long long *pcount = (long long *)calloc((size_t)(nz > 0 ? nz : 1), sizeof(long long));
+    if (!slot || !pcount) { free(slot); free(pcount); return ORC_ERR_INVALID; }
+    double R[9], t[3], Rs[9];
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) R[r * 3 + c] = T[r * 4 + c];
+        t[r] = T[r * 4 + 3];
+    }
+    memcpy(Rs, R_shape ? R_shape : R, sizeof Rs);
+    double Rst[9];
+    transpose(Rs, Rst, 3, 3);
+    const double half_l2 = 0.5 * ell * ell;
+    const double rc2 = (cutoff > 0.0) ? cutoff * cutoff : INFINITY;
+
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long j = 0; j < nz; ++j) {
+        double *acc = slot + (size_t)j * stride;
+        double zt[3] = {Z[3 * j] - t[0], Z[3 * j + 1] - t[1], Z[3 * j + 2] - t[2]};
+        double y[3];
+        for (int r = 0; r < 3; ++r) y[r] = R[0 * 3 + r] * zt[0] + R[1 * 3 + r] * zt[1] + R[2 * 3 + r] * zt[2];
+        double Sj[9], tmp[9], SjR[9];
+        shape6_to_mat(SZ + 6 * j, Sj);
+        matmul(Rst, Sj, tmp, 3, 3, 3);
+        matmul(tmp, Rs, SjR, 3, 3, 3);
+        double J[18], Jt[18], yh[9];
+        hat3(y, yh);
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) {
+                J[r * 6 + c] = -yh[r * 3 + c];
+                J[r * 6 + 3 + c] = (r == c) ? 1.0 : 0.0;
+            }
+        transpose(J, Jt, 3, 6);
+        for (long i = 0; i < nx; ++i) {
+            double r3[3] = {X[3 * i] - y[0], X[3 * i + 1] - y[1], X[3 * i + 2] - y[2]};
+            double d2 = r3[0] * r3[0] + r3[1] * r3[1] + r3[2] * r3[2];
+            if (!(d2 <= rc2)) continue;
+            double Si[9], Sig[9], Sinv[9];
+            shape6_to_mat(SX + 6 * i, Si);
+            for (int a = 0; a < 9; ++a) Sig[a] = half_l2 * (Si[a] + SjR[a]);
+            if (!inv3(Sig, Sinv)) continue;
+            double u[3];
+            matmul(Sinv, r3, u, 3, 3, 1);
+            double quad = r3[0] * u[0] + r3[1] * u[1] + r3[2] * u[2];
+            double fij = sigma2 * exp(-0.5 * quad);
+            double Jtu[6], SinvJ[18], JtSJ[36];
+            matmul(Jt, u, Jtu, 6, 3, 1);
+            matmul(Sinv, J, SinvJ, 3, 3, 6);
+            matmul(Jt, SinvJ, JtSJ, 6, 3, 6);
+            acc[0] += fij;
+            for (int a = 0; a < 6; ++a) acc[1 + a] += -fij * Jtu[a];
+            for (int a = 0; a < 36; ++a) acc[7 + a] += -fij * JtSJ[a];
+            if (want_t) {
+                double *t1 = acc + 43, *t2 = acc + 79;
+                for (int a = 0; a < 6; ++a)
+                    for (int b = 0; b < 6; ++b) t1[a * 6 + b] += fij * Jtu[a] * Jtu[b];
+                double uh[9], uhJ[18];
+                hat3(u, uh);
+                matmul(uh, J, uhJ, 3, 3, 6);
+                for (int a = 0; a < 18; ++a) t2[a] += -fij * uhJ[a];
+            }
+            pcount[j] += 1;
+        }
+    }
+
+    double f = 0.0, g[6] = {0}, H[36] = {0}, T1[36] = {0}, T2[36] = {0};
+    long long np = 0;
+    for (long j = 0; j < nz; ++j) {
+        const double *acc = slot + (size_t)j * stride;
+        f += acc[0];
+        for (int a = 0; a < 6; ++a) g[a] += acc[1 + a];
+        for (int a = 0; a < 36; ++a) H[a] += acc[7 + a];
+        if (want_t) {
+            for (int a = 0; a < 36; ++a) T1[a] += acc[43 + a];
+            for (int a = 0; a < 18; ++a) T2[a] += acc[79 + a];
+        }
+        np += pcount[j];
+    }
+    free(slot);
+    free(pcount);
+    *f_out = f;
+    memcpy(g_out, g, sizeof g);
+    memcpy(Hmain_out, H, sizeof H);
+    if (T1_out) memcpy(T1_out, T1, sizeof T1);
+    if (T2_out) memcpy(T2_out, T2, sizeof T2);
+    if (npairs_out) *npairs_out = np;
+    return ORC_OK;
+}
+
+/* Connection term of eq. (connection_se3): Gamma^v(xi, grad f) = C(g) xi with
+ * C(g) = [[ -1/2 g_w^, 0 ], [ -g_v^, 0 ]]. */
+void orc_connection(const double g[6], double C[36]) {
+    double gw[9], gv[9];
+    hat3(g, gw);
+    hat3(g + 3, gv);
+    memset(C, 0, 36 * sizeof(double));
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            C[r * 6 + c] = -0.5 * gw[r * 3 + c];
+            C[(r + 3) * 6 + c] = -gv[r * 3 + c];
+        }
+}
+
+/* exp(xi^) for xi = (w, v): closed form R = I + A W + B W^2, t = (I + B W + C W^2) v
+ * with A = sin(th)/th, B = (1-cos th)/th^2, C = (th - sin th)/th^3.  B is
+ * evaluated as (1/2) (sin(th/2)/(th/2))^2, which has no cancellation; A and B
+ * use their Taylor series below th = 1e-5 and C below th = 1e-2, where the
+ * closed form of C cancels. */
+void orc_se3_exp(const double xi[6], double T[16]) {
+    double th2 = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2];
+    double th = sqrt(th2);
+    double A, B, Cc;
+    if (th < 1e-5) {
+        A = 1.0 - th2 / 6.0 + th2 * th2 / 120.0;
+        B = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
+    } else {
+        double h = sin(0.5 * th) / (0.5 * th);
+        A = sin(th) / th;
+        B = 0.5 * h * h;
+    }
+    if (th < 1e-2)
+        Cc = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0 - th2 * th2 * th2 / 362880.0;
+    else
+        Cc = (th - sin(th)) / (th2 * th);
+    double W[9], W2[9];
+    hat3(xi, W);
+    matmul(W, W, W2, 3, 3, 3);
+    double R[9], V[9];
+    for (int a = 0; a < 9; ++a) {
+        double I = (a % 4 == 0) ? 1.0 : 0.0;
+        R[a] = I + A * W[a] + B * W2[a];
+        V[a] = I + B * W[a] + Cc * W2[a];
+    }
+    double tv[3];
+    matmul(V, xi + 3, tv, 3, 3, 1);
+    memset(T, 0, 16 * sizeof(double));
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) T[r * 4 + c] = R[r * 3 + c];
+        T[r * 4 + 3] = tv[r];
+    }
+    T[15] = 1.0;
+}
+
+/*
+ * Step of eq. (gn_update): xi = -H^{-1} g with H = Hmain + C(g) (or, for the
+ * exact-Hessian variant, H = T1 + T2 + Hmain + C(g), passed in as H).
+ * Reading of the damping the paper leaves open:
+ *   1. g == 0 => xi = 0.
+ *   2. Solve H xi = -g by partial-pivoting elimination; accept when no pivot is
+ *      below 1e-12 * max|H| and g . xi > 0 (an ascent direction).
+ *   3. Otherwise drop C(g) and solve (Hmain - lambda * ||diag Hmain||_2 * I) xi = -g
+ *      for lambda = 1e-6 * 10^m, m = 0..6, accepting the first that passes the
+ *      same test.  Hmain is negative semi-definite, so this succeeds unless
+ *      Hmain vanishes.
+ *   4. Otherwise ORC_ERR_SINGULAR.
+ * *damped receives 0 (plain), m + 1 (damped at attempt m).
+ */
+int orc_solve_step(const double H[36], const double Hmain[36], const double g[6], double xi[6],
+                   int *damped) {
+    double mg[6];
+    int zero = 1;
+    for (int a = 0; a < 6; ++a) {
+        mg[a] = -g[a];
+        if (g[a] != 0.0) zero = 0;
+    }
+    if (damped) *damped = 0;
+    if (zero) {
+        memset(xi, 0, 6 * sizeof(double));
+        return ORC_OK;
+    }
+    double x[6];
+    if (solve_lu(H, mg, x, 6, 1e-12)) {
+        double gx = 0.0;
+        for (int a = 0; a < 6; ++a) gx += g[a] * x[a];
+        if (gx > 0.0) {
+            memcpy(xi, x, sizeof x);
+            return ORC_OK;
+        }
+    }
+    double dn = 0.0;
+    for (int a = 0; a < 6; ++a) dn += Hmain[a * 7] * Hmain[a * 7];
+    dn = sqrt(dn);
+    double lam = 1e-6;
+    for (int m = 0; m <= 6; ++m, lam *= 10.0) {
+        double Hd[36];
+        memcpy(Hd, Hmain, sizeof Hd);
+        for (int a = 0; a < 6; ++a) Hd[a * 7] -= lam * dn;
+        if (solve_lu(Hd, mg, x, 6, 1e-12)) {
+            double gx = 0.0;
+            for (int a = 0; a < 6; ++a) gx += g[a] * x[a];
+            if (gx > 0.0) {
+                memcpy(xi, x, sizeof x);
+                if (damped) *damped = m + 1;
+                return ORC_OK;
+            }
+        }
+    }
+    return ORC_ERR_SINGULAR;
+}
+
+static int pose_is_rigid(const double T[16]) {
+    for (int a = 0; a < 16; ++a) if (!isfinite(T[a])) return 0;
+    if (fabs(T[12]) > 1e-6 || fabs(T[13]) > 1e-6 || fabs(T[14]) > 1e-6 || fabs(T[15] - 1.0) > 1e-6)
+        return 0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) s += T[k * 4 + a] * T[k * 4 + b];
+            if (fabs(s - (a == b ? 1.0 : 0.0)) > 1e-6) return 0;
+        }
+    double det = T[0] * (T[5] * T[10] - T[6] * T[9]) - T[1] * (T[4] * T[10] - T[6] * T[8]) +
+                 T[2] * (T[4] * T[9] - T[5] * T[8]);
+    return fabs(det - 1.0) <= 1e-6;
+}
+
+/*
+ * Algorithm 1 with the Gauss-Newton update (or the exact frozen-covariance
+ * Hessian when newton != 0), from T_init, with the length-scale annealing the
+ * paper sketches for Sigma (reading):
+ *   stage s uses ell_s; ell_0 = ell, ell_{s+1} = max(alpha * ell_s, ell_min);
+ *   a non-final stage ends when ||xi||_1 < stage_tol or after
+ *   max_iters_per_stage iterations; the final stage (ell_s == ell_min) runs
+ *   until ||xi||_1 < tol; every stage counts toward max_iters in total.
+ * Each iteration: transform Z by T^{-1}, freeze Sigma_ij at the current R
+ * (Remark 2), evaluate f, g and the Hessian, step, retract T <- T exp(xi^).
+ * SX/SZ may be NULL, in which case the shapes are computed with (knn, rho).
+ * info[] receives: 0 status, 1 converged, 2 iterations, 3 stages used, 4 f,
+ * 5..10 g, 11 ||xi||_1 of the last step, 12 pairs at the last iteration,
+ * 13 damped steps, 14..29 iterations per stage (up to 16 stages).
+ * On error T_out is left untouched.
+ */
+int orc_register(const double *X, const double *SXin, long nx, const double *Z, const double *SZin,
+                 long nz, const double T_init[16], double ell, double ell_min, double alpha,
+                 double cutoff_scale, int knn, double rho, double sigma2, int max_iters,
+                 int max_iters_per_stage, double tol, double stage_tol, int newton,
+                 double T_out[16], double info[32]) {
+    for (int a = 0; a < 32; ++a) info[a] = 0.0;
+    if (!X || !Z || !T_init || !T_out || nx < 0 || nz < 0 || !(ell > 0.0) || !(ell_min > 0.0) ||
+        ell_min > ell || !(alpha > 0.0) || alpha > 1.0 || !(cutoff_scale > 0.0) || max_iters < 1 ||
+        max_iters_per_stage < 1 || !(tol > 0.0) || !pose_is_rigid(T_init)) {
+        info[0] = ORC_ERR_INVALID;
+        return ORC_ERR_INVALID;
+    }
+    if (alpha == 1.0 && ell_min < ell) {
+        info[0] = ORC_ERR_INVALID;
+        return ORC_ERR_INVALID;
+    }
+    double *SX = NULL, *SZ = NULL;
+    int st = ORC_OK;
+    if (!SXin || !SZin) {
+        if (nx < knn || nz < knn) { info[0] = ORC_ERR_TOO_FEW_POINTS; return ORC_ERR_TOO_FEW_POINTS; }
+        SX = (double *)malloc(sizeof(double) * 6 * (size_t)(nx > 0 ? nx : 1));
+        SZ = (double *)malloc(sizeof(double) * 6 * (size_t)(nz > 0 ? nz : 1));
+        if (!SX || !SZ) { free(SX); free(SZ); info[0] = ORC_ERR_INVALID; return ORC_ERR_INVALID; }
+        st = orc_point_shapes(X, nx, knn, rho, SX);
+        if (st == ORC_OK) st = orc_point_shapes(Z, nz, knn, rho, SZ);
+        if (st != ORC_OK) { free(SX); free(SZ); info[0] = st; return st; }
+    }
+    const double *sx = SXin ? SXin : SX, *sz = SZin ? SZin : SZ;
+
+    double T[16];
+    memcpy(T, T_init, sizeof T);
+    double cur_ell = ell;
+    int stage = 0, stage_it = 0, it = 0, converged = 0, damped_steps = 0;
+    double f = 0.0, g[6] = {0}, xi_l1 = INFINITY;
+    long long np = 0;
+    while (it < max_iters) {
+        double Hm[36], T1[36], T2[36], C[36], H[36];
+        st = orc_eval(X, sx, nx, Z, sz, nz, T, NULL, cur_ell, cutoff_scale * cur_ell, sigma2, &f, g, Hm,
+                      newton ? T1 : NULL, newton ? T2 : NULL, &np);
+        if (st != ORC_OK) break;
+        if (np == 0) { st = ORC_ERR_NO_PAIRS; break; }
+        orc_connection(g, C);
+        for (int a = 0; a < 36; ++a) H[a] = Hm[a] + C[a] + (newton ? T1[a] + T2[a] : 0.0);
+        double xi[6];
+        int dmp = 0;
+        st = orc_solve_step(H, Hm, g, xi, &dmp);
+        if (st != ORC_OK) break;
+        if (dmp) ++damped_steps;
+        double E[16], Tn[16];
+        orc_se3_exp(xi, E);
+        matmul(T, E, Tn, 4, 4, 4);
+        memcpy(T, Tn, sizeof T);
+        xi_l1 = 0.0;
+        for (int a = 0; a < 6; ++a) xi_l1 += fabs(xi[a]);
+        ++it;
+        ++stage_it;
+        if (stage < 16) info[14 + stage] = stage_it;
+        const int final_stage = !(cur_ell > ell_min);
+        if (final_stage) {
+            if (xi_l1 < tol) { converged = 1; break; }
+        } else if (xi_l1 < stage_tol || stage_it >= max_iters_per_stage) {
+            cur_ell = alpha * cur_ell;
+            if (cur_ell < ell_min) cur_ell = ell_min;
+            ++stage;
+            stage_it = 0;
+        }
+    }
+    free(SX);
+    free(SZ);
+    info[0] = st;
+    if (st != ORC_OK) return st;
+    memcpy(T_out, T, sizeof T);
+    info[1] = converged;
+    info[2] = it;
+    info[3] = stage + 1;
+    info[4] = f;
+    for (int a = 0; a < 6; ++a) info[5 + a] = g[a];
+    info[11] = xi_l1;
+    info[12] = (double)np;
+    info[13] = damped_steps;
+    return ORC_OK;
+}
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

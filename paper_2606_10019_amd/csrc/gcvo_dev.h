@@ -1,0 +1,148 @@
+// Internal device/host structures of the gfx950 G-CVO library.
+//
+// Work is described by small POD descriptors that live in device memory inside
+// the caller's workspace: one PairDev per registration problem, one SortJob per
+// (cloud, uniform grid) binning, one BlockTask per 256-point block of the
+// per-iteration pair kernel.  A single registration is a batch of one.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gcvo.h"
+
+namespace gcvo {
+
+constexpr int kBlock = 256;           // threads of point-parallel kernels (4 waves)
+constexpr int kSortThreads = 1024;    // threads of the one-block-per-job radix sort
+constexpr int kMaxStages = GCVO_MAX_STAGES;
+constexpr int kMaxKnn = GCVO_MAX_KNN;
+constexpr int kNumSums = 28;          // f, g (6), upper triangle of H_main (21)
+constexpr int kPartialStride = 32;    // floats per block partial: 28 sums + pair count + pad
+constexpr float kCellMargin = 1.001f; // pair-grid cell edge = margin * cutoff (see Grid)
+
+// Uniform grid over an axis-aligned box.  Cell of a point p along axis d is
+// clamp(floor((p_d - lo_d) * inv_h), 0, n_d - 1); cells are numbered x-fastest.
+// For the pair grid the edge h is at least 1.001 * cutoff, so two points within
+// the cutoff always fall in cells whose indices differ by at most one per axis
+// even after FP32 rounding of the cell computation.
+struct Grid {
+    float lo[3];
+    float h;
+    float inv_h;
+    int n[3];
+    int ncells;
+    int key_bits;   // bits needed to hold ncells - 1 (radix passes = ceil(bits / 8))
+    int pad[2];
+};
+
+// Sort of one cloud's points into one grid: keys, a stable LSD radix sort of
+// (key, index), and cell_start[c] = first sorted position of cell c
+// (cell_start[ncells] = n), so cell c holds sorted positions
+// [cell_start[c], cell_start[c + 1]).
+struct SortJob {
+    const float *x, *y, *z;   // SoA coordinates the grid is built over
+    int n;
+    int max_cells;            // capacity of cell_start minus one
+    Grid *grid;               // written by the setup kernel
+    uint32_t *keys, *keys_tmp, *idx, *idx_tmp;   // idx: sorted position -> point index
+    int *cell_start;
+    int pair;                 // owning pair
+    int kind;                 // kJobKnnTarget, kJobKnnSource or kJobStage + stage
+    int want_shapes;          // kNN jobs: 1 = compute shapes into shape_out
+    int pad;
+    float *shape_out;         // SoA [6][n], original point order
+};
+
+constexpr int kJobKnnTarget = 0;
+constexpr int kJobKnnSource = 1;
+constexpr int kJobStage = 2;
+
+// Per-pair solver state, FP64, owned by the device for the whole solve.
+struct State {
+    double T[16];          // current pose in the recentred frame (row-major 4x4)
+    double f, g[6], H[36]; // last evaluation (H = H_GN incl. connection term)
+    double xi[6];
+    double xi_l1;
+    long long pairs_last;
+    int iter, stage, stage_iter, done, status, converged, damped;
+    int stage_iters[kMaxStages];
+    unsigned int counter;  // blocks of the current iteration that finished
+    int pad;
+};
+
+// Everything one registration problem needs on the device.
+struct PairDev {
+    // caller inputs
+    const float *tgt_xyz, *src_xyz;   // AoS [n][3]
+    int n_t, n_s;
+    // solver parameters
+    double ell[kMaxStages];
+    int n_stages;
+    int knn;
+    double rho, cutoff_scale, sigma2, tol, stage_tol;
+    int max_iters, max_per_stage;
+    double T_init[16];                // caller frame
+    // derived on device
+    double centre[3];                 // target centroid, subtracted before the FP32 cast
+    double sum_t[3];                  // FP64 coordinate sums of the target
+    float lo_t[3], hi_t[3], lo_s[3], hi_s[3];   // bounding boxes of the original coordinates
+    int nonfinite;                    // 1 if any input coordinate is NaN or Inf
+    // workspace arrays
+    float *t_orig, *s_orig;           // SoA [3][n] original coordinates (kNN grids)
+    float *t_rec, *s_rec;             // SoA [3][n] recentred coordinates
+    float *t_shape, *s_shape;         // SoA [6][n] shapes, original point order
+    float *s_sorted;                  // SoA [9][n_s] recentred xyz + shape, source grid order
+    float *t_sorted[kMaxStages];      // SoA [9][n_t] recentred xyz + shape, stage grid order
+    int *t_cells[kMaxStages];         // cell_start of each stage grid
+    Grid *t_grid[kMaxStages];
+    SortJob *job_knn_t, *job_knn_s, *job_stage0;   // job_stage0[s] for s < n_stages
+    State *st;
+    float *partials;                  // [n_blocks][kPartialStride]
+    int n_blocks;                     // 256-point blocks of the source cloud
+    int first_block;                  // index of the pair's first BlockTask
+    int shapes_given;                 // 1: t_shape / s_shape are caller memory (eval path)
+    int eval_only;                    // 1: stop after one evaluation, no step
+};
+
+struct BlockTask {   // one block of the pair kernel: a pair and a 256-point slice of its source
+    int pair;
+    int block;       // block index within the pair
+};
+
+// ---------------------------------------------------------------- wave helpers
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// ---------------------------------------------------------------- host launchers
+
+// Enqueue the per-registration preparation: bounds and centroid, grids, SoA
+// copies, cell keys, radix sorts, kNN shapes and the sorted per-stage arrays.
+hipError_t launch_prepare(PairDev *pairs_dev, int n_pairs, int max_n, SortJob *jobs_dev, int n_jobs,
+                          int max_job_n, hipStream_t s);
+// Enqueue n_iters Gauss-Newton iterations (each a no-op for pairs already done).
+hipError_t launch_iterations(PairDev *pairs_dev, BlockTask *tasks_dev, int n_tasks, int n_iters,
+                             int precision, hipStream_t s);
+// Count pairs not yet done into *active (device int).
+hipError_t launch_count_active(PairDev *pairs_dev, int n_pairs, int *active, hipStream_t s);
+
+}  // namespace gcvo

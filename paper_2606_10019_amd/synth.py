@@ -1,0 +1,293 @@
+"""Seeded synthetic point-cloud pairs for registration tests and benchmarks.
+
+This module only builds inputs: surfaces, ray casts, voxel grids and the
+ground-truth rigid motion of each pair.  It holds none of the registration
+method's arithmetic (no kernels, no covariances, no gradients), so both the
+GPU path and the CPU oracle can consume its output without sharing code.
+
+Every generator is a pure function of ``(config, instance)``: instance ``i`` of
+configuration ``c`` draws from ``numpy.random.default_rng(1_000_003 * c + i)``
+in a fixed order.  Clouds are returned as C-contiguous float32 ``[n, 3]``
+arrays; the float64 view of those exact values is what the oracle receives.
+
+Pose convention (Notation section of the paper): a pose T acts on points as
+``T p = R p + t`` and the objective compares target points x_i with
+``T^{-1} z_j``.  When the target is generated as ``x = G p`` from the same
+surface as the source ``z = p``, the registration should return ``T = G^{-1}``.
+Each pair records ``G`` and ``T_true = G^{-1}``; truth is informational, the
+accuracy gate compares the GPU against the oracle.
+"""
+from __future__ import annotations
+
+import hashlib
+from dataclasses import dataclass, field
+
+import numpy as np
+from scipy.spatial.transform import Rotation
+
+SEED_STRIDE = 1_000_003
+
+
+def rng_for(config: int, instance: int) -> np.random.Generator:
+    return np.random.default_rng(SEED_STRIDE * config + instance)
+
+
+def rigid(R: np.ndarray, t) -> np.ndarray:
+    T = np.eye(4)
+    T[:3, :3] = R
+    T[:3, 3] = np.asarray(t, dtype=np.float64)
+    return T
+
+
+def transform_points(T: np.ndarray, P: np.ndarray) -> np.ndarray:
+    return P @ T[:3, :3].T + T[:3, 3]
+
+
+def random_unit(rng: np.random.Generator) -> np.ndarray:
+    while True:
+        v = rng.normal(size=3)
+        n = np.linalg.norm(v)
+        if n > 1e-12:
+            return v / n
+
+
+def rotation_about(axis: np.ndarray, angle_rad: float) -> np.ndarray:
+    return Rotation.from_rotvec(np.asarray(axis, dtype=np.float64) * angle_rad).as_matrix()
+
+
+def cloud_digest(*arrays: np.ndarray) -> str:
+    h = hashlib.sha256()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()[:16]
+
+
+def voxel_centroids(P: np.ndarray, voxel: float) -> np.ndarray:
+    """Replace the points of every occupied voxel by their centroid (float64).
+
+    Output order is the lexicographic order of the integer voxel keys, so it is
+    deterministic for a given input.
+    """
+    keys = np.floor(P / voxel).astype(np.int64)
+    uniq, inv = np.unique(keys, axis=0, return_inverse=True)
+    inv = inv.reshape(-1)
+    cnt = np.bincount(inv, minlength=len(uniq)).astype(np.float64)
+    out = np.empty((len(uniq), 3))
+    for d in range(3):
+        out[:, d] = np.bincount(inv, weights=P[:, d], minlength=len(uniq)) / cnt
+    return out
+
+
+@dataclass
+class PairSpec:
+    """One registration problem: target X, source Z and its solver settings."""
+    name: str
+    target: np.ndarray          # float32 [n_x, 3]
+    source: np.ndarray          # float32 [n_z, 3]
+    G: np.ndarray               # float64 4x4 generator motion
+    length_scale: float
+    length_scale_min: float
+    anneal_factor: float = 0.5
+    cutoff_scale: float = 3.0
+    knn: int = 10
+    eig_ratio_min: float = 0.01
+    sigma2: float = 1.0
+    max_iters: int = 30
+    max_iters_per_stage: int = 30
+    tol: float = 1e-6
+    stage_tol: float = 1e-4
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def T_true(self) -> np.ndarray:
+        return np.linalg.inv(self.G)
+
+    def digest(self) -> str:
+        return cloud_digest(self.target, self.source)
+
+    def params(self) -> dict:
+        return dict(length_scale=self.length_scale, length_scale_min=self.length_scale_min,
+                    anneal_factor=self.anneal_factor, cutoff_scale=self.cutoff_scale,
+                    knn=self.knn, eig_ratio_min=self.eig_ratio_min, sigma2=self.sigma2,
+                    max_iters=self.max_iters, max_iters_per_stage=self.max_iters_per_stage,
+                    tol=self.tol, stage_tol=self.stage_tol)
+
+
+# --------------------------------------------------------------------------
+# Configuration 1: three orthogonal 4x4 m planes and a 1 m hemisphere cap.
+# --------------------------------------------------------------------------
+
+def _sample_planes_and_cap(rng: np.random.Generator, n: int, noise: float) -> np.ndarray:
+    plane_area = 16.0
+    cap_area = 2.0 * np.pi * 1.0 ** 2
+    areas = np.array([plane_area, plane_area, plane_area, cap_area])
+    which = rng.choice(4, size=n, p=areas / areas.sum())
+    u = rng.uniform(0.0, 4.0, size=n)
+    v = rng.uniform(0.0, 4.0, size=n)
+    zc = rng.uniform(0.0, 1.0, size=n)            # uniform height => uniform on the sphere
+    phi = rng.uniform(0.0, 2.0 * np.pi, size=n)
+    P = np.empty((n, 3))
+    m = which == 0
+    P[m] = np.stack([u[m], v[m], np.zeros(m.sum())], 1)      # z = 0
+    m = which == 1
+    P[m] = np.stack([u[m], np.zeros(m.sum()), v[m]], 1)      # y = 0
+    m = which == 2
+    P[m] = np.stack([np.zeros(m.sum()), u[m], v[m]], 1)      # x = 0
+    m = which == 3
+    rho = np.sqrt(np.maximum(0.0, 1.0 - zc[m] ** 2))
+    P[m] = np.stack([2.0 + rho * np.cos(phi[m]), 2.0 + rho * np.sin(phi[m]), zc[m]], 1)
+    return P + rng.normal(0.0, noise, size=P.shape)
+
+
+def make_config1(instance: int = 0, n: int = 2000, noise: float = 0.01,
+                 angle_deg: float = 5.0, trans_m: float = 0.2) -> PairSpec:
+    rng = rng_for(1, instance)
+    src = _sample_planes_and_cap(rng, n, noise)
+    tgt_p = _sample_planes_and_cap(rng, n, noise)
+    G = rigid(rotation_about(random_unit(rng), np.deg2rad(angle_deg)), trans_m * random_unit(rng))
+    tgt = transform_points(G, tgt_p)
+    return PairSpec(name=f"c1_planes_cap_{instance}", target=np.ascontiguousarray(tgt, np.float32),
+                    source=np.ascontiguousarray(src, np.float32), G=G,
+                    length_scale=0.3, length_scale_min=0.3, max_iters=30, max_iters_per_stage=30)
+
+
+# --------------------------------------------------------------------------
+# Configuration 2: spinning 64 x 1024 LiDAR over a ground plane with boxes
+# and vertical cylinders, voxel-downsampled at 0.3 m.
+# --------------------------------------------------------------------------
+
+@dataclass
+class LidarScene:
+    box_lo: np.ndarray   # [nb, 3]
+    box_hi: np.ndarray   # [nb, 3]
+    cyl_c: np.ndarray    # [nc, 2]
+    cyl_r: np.ndarray    # [nc]
+    cyl_h: np.ndarray    # [nc]
+
+
+def _annulus(rng, r0, r1):
+    r = np.sqrt(rng.uniform(r0 * r0, r1 * r1))
+    a = rng.uniform(0.0, 2.0 * np.pi)
+    return np.array([r * np.cos(a), r * np.sin(a)])
+
+
+def make_lidar_scene(rng: np.random.Generator, keep_clear: np.ndarray,
+                     n_boxes: int = 40, n_cyl: int = 30) -> LidarScene:
+    """Boxes rest on z = 0 with sides U[1, 10] m and centres in a 5-60 m annulus;
+    cylinders have r U[0.2, 0.5] m, height U[2, 6] m, centres at 3-50 m.
+    Objects whose footprint comes within 2 m of a sensor position in
+    ``keep_clear`` ([k, 2] xy) are redrawn, so no sensor sits inside a solid."""
+    lo, hi = [], []
+    while len(lo) < n_boxes:
+        side = rng.uniform(1.0, 10.0, size=3)
+        c = _annulus(rng, 5.0, 60.0)
+        blo = np.array([c[0] - side[0] / 2, c[1] - side[1] / 2, 0.0])
+        bhi = np.array([c[0] + side[0] / 2, c[1] + side[1] / 2, side[2]])
+        d = np.maximum(0.0, np.maximum(blo[None, :2] - keep_clear, keep_clear - bhi[None, :2]))
+        if np.min(np.linalg.norm(d, axis=1)) < 2.0:
+            continue
+        lo.append(blo)
+        hi.append(bhi)
+    cc, cr, ch = [], [], []
+    while len(cc) < n_cyl:
+        r = rng.uniform(0.2, 0.5)
+        h = rng.uniform(2.0, 6.0)
+        c = _annulus(rng, 3.0, 50.0)
+        if np.min(np.linalg.norm(keep_clear - c[None], axis=1)) - r < 2.0:
+            continue
+        cc.append(c)
+        cr.append(r)
+        ch.append(h)
+    return LidarScene(np.array(lo), np.array(hi), np.array(cc), np.array(cr), np.array(ch))
+
+
+def raycast(scene: LidarScene, origin: np.ndarray, dirs: np.ndarray) -> np.ndarray:
+    """Distance to the nearest hit along each unit ray (inf when nothing is hit)."""
+    n = len(dirs)
+    best = np.full(n, np.inf)
+    dz = dirs[:, 2]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        tg = np.where(dz < -1e-12, -origin[2] / dz, np.inf)
+    best = np.minimum(best, np.where(tg > 0, tg, np.inf))
+    inv = np.where(np.abs(dirs) > 1e-15, 1.0 / np.where(np.abs(dirs) > 1e-15, dirs, 1.0), np.inf)
+    for lo, hi in zip(scene.box_lo, scene.box_hi):
+        with np.errstate(invalid="ignore"):
+            t0 = (lo[None] - origin[None]) * inv
+            t1 = (hi[None] - origin[None]) * inv
+        # Rays parallel to a slab: inside it => (-inf, inf), outside => empty.
+        par = ~np.isfinite(inv)
+        inside = (origin[None] >= lo[None]) & (origin[None] <= hi[None])
+        t0 = np.where(par, np.where(inside, -np.inf, np.inf), t0)
+        t1 = np.where(par, np.where(inside, np.inf, -np.inf), t1)
+        tn = np.max(np.minimum(t0, t1), axis=1)
+        tf = np.min(np.maximum(t0, t1), axis=1)
+        hit = (tf >= tn) & (tf > 0)
+        th = np.where(tn > 0, tn, tf)
+        best = np.where(hit & (th < best), th, best)
+    ox, oy, oz = origin
+    dx, dy = dirs[:, 0], dirs[:, 1]
+    a = dx * dx + dy * dy
+    for c, r, h in zip(scene.cyl_c, scene.cyl_r, scene.cyl_h):
+        px, py = ox - c[0], oy - c[1]
+        b = 2.0 * (px * dx + py * dy)
+        cq = px * px + py * py - r * r
+        disc = b * b - 4.0 * a * cq
+        ok = (disc >= 0) & (a > 1e-15)
+        sq = np.sqrt(np.where(ok, disc, 0.0))
+        with np.errstate(divide="ignore", invalid="ignore"):
+            t_in = np.where(ok, (-b - sq) / (2.0 * a), np.inf)
+        zh = oz + t_in * dz
+        side_hit = ok & (t_in > 0) & (zh >= 0) & (zh <= h)
+        best = np.where(side_hit & (t_in < best), t_in, best)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            tc = np.where(np.abs(dz) > 1e-12, (h - oz) / dz, np.inf)
+        xc = ox + tc * dx - c[0]
+        yc = oy + tc * dy - c[1]
+        cap_hit = (tc > 0) & (xc * xc + yc * yc <= r * r)
+        best = np.where(cap_hit & (tc < best), tc, best)
+    return best
+
+
+def lidar_directions(n_rings: int = 64, n_az: int = 1024, elev_lo: float = -25.0,
+                     elev_hi: float = 3.0) -> np.ndarray:
+    el = np.deg2rad(np.linspace(elev_lo, elev_hi, n_rings))
+    az = 2.0 * np.pi * np.arange(n_az) / n_az
+    E, A = np.meshgrid(el, az, indexing="ij")
+    return np.stack([np.cos(E) * np.cos(A), np.cos(E) * np.sin(A), np.sin(E)], -1).reshape(-1, 3)
+
+
+def lidar_scan(scene: LidarScene, pose: np.ndarray, rng: np.random.Generator,
+               range_noise: float = 0.02, max_range: float = 80.0) -> np.ndarray:
+    """Points of one spin in the sensor frame (float64, before voxelisation)."""
+    d_s = lidar_directions()
+    d_w = d_s @ pose[:3, :3].T
+    t = raycast(scene, pose[:3, 3], d_w)
+    t = t + rng.normal(0.0, range_noise, size=t.shape)
+    keep = np.isfinite(t) & (t > 0.0) & (t <= max_range)
+    return d_s[keep] * t[keep, None]
+
+
+def make_config2(instance: int = 0, voxel: float = 0.3, forward_m: float = 1.0,
+                 yaw_deg: float = 2.0, sensor_height: float = 1.8) -> PairSpec:
+    """LiDAR frame-to-frame pair: X = scan 1, Z = scan 2 taken after the ego
+    motion M (forward along the sensor x axis, then yaw).  Expected T = M^{-1}."""
+    rng = rng_for(2, instance)
+    S1 = rigid(np.eye(3), [0.0, 0.0, sensor_height])
+    M = rigid(rotation_about(np.array([0.0, 0.0, 1.0]), np.deg2rad(yaw_deg)), [forward_m, 0.0, 0.0])
+    S2 = S1 @ M
+    scene = make_lidar_scene(rng, np.array([S1[:2, 3], S2[:2, 3]]))
+    x = voxel_centroids(lidar_scan(scene, S1, rng), voxel)
+    z = voxel_centroids(lidar_scan(scene, S2, rng), voxel)
+    # G maps the source surface into the target frame: x = M z for a static point.
+    return PairSpec(name=f"c2_lidar_{instance}", target=np.ascontiguousarray(x, np.float32),
+                    source=np.ascontiguousarray(z, np.float32), G=M,
+                    length_scale=1.0, length_scale_min=0.1, anneal_factor=0.5,
+                    eig_ratio_min=0.1, max_iters=200, max_iters_per_stage=60,
+                    extra=dict(voxel=voxel))
+
+
+CONFIGS = {1: make_config1, 2: make_config2}
+
+
+def make_pair(config: int, instance: int = 0) -> PairSpec:
+    return CONFIGS[config](instance)
