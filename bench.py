@@ -1,0 +1,155 @@
+"""Benchmark of the G-CVO hot path on one MI355X.
+
+A step is one complete registration of a synthetic LiDAR frame pair (64-ring x
+1024-azimuth scan of a ground plane with 40 boxes and 30 cylinders, voxelised
+at 0.3 m, second scan after 1 m forward and 2 deg yaw; length scale annealed
+1.0 -> 0.1 m): per-point covariance shapes of both clouds, cell lists for every
+stage, and all Gauss-Newton iterations to convergence.  Inputs are resident in
+device memory before the timed region; poses are on the host when it ends.
+
+value = registrations/s counting only registrations whose pose lies within
+1e-3 deg / 1e-5 m of the FP64 oracle's fixed point for the same input.
+
+roofline: the pair kernel (transform, pair terms, per-point finish, block
+reduction, last-block solve), FP32 VALU bound.  A second pass over the same
+steps brackets every launch of that kernel with HIP events on the stream it runs
+on; algorithmic FLOP = 76 per pair within the cutoff + 230 per source point.
+
+cpu_baseline: the FP64 oracle, as it stands, registering one of the same pairs
+on the host's cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOP_PER_PAIR = 76
+FLOP_PER_SOURCE_POINT = 230
+FP32_VALU_PEAK_TFLOPS = 157.3
+N_INSTANCES = 4
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); a registration runs on a single "
+              "device and this build has no multi-GPU path.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2606_10019_amd import gcvo, synth
+    from tests.posemetrics import rot_err_deg, trans_err_m
+
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_poses.json")))
+    dev = torch.device("cuda:0")
+    specs, clouds, refs, params = [], [], [], []
+    for i in range(N_INSTANCES):
+        s = synth.make_config2(i)
+        g = golden[s.name]
+        assert g["digest"] == s.digest(), f"input drift for {s.name}"
+        specs.append(s)
+        clouds.append((torch.from_numpy(s.target).to(dev), torch.from_numpy(s.source).to(dev)))
+        refs.append(np.array(g["T_ref"]).reshape(4, 4))
+        params.append(gcvo.params_from_spec(s))
+    need = max(gcvo.gcvo_workspace_size(len(s.target), len(s.source), p) for s, p in zip(specs, params))
+    ws = gcvo.workspace(need, dev)
+    print(f"[bench] {N_INSTANCES} LiDAR pairs, {[len(s.target) for s in specs]} target points, "
+          f"workspace {need / 2**20:.1f} MiB", file=sys.stderr, flush=True)
+
+    def step(k):
+        i = k % N_INSTANCES
+        T, info = gcvo.gcvo_register(clouds[i][0], clouds[i][1], None, params[i], ws=ws)
+        return i, T, info
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    results = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        results.append(step(k))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    passed, errs, iters = 0, [], []
+    for i, T, info in results:
+        dr, dt = rot_err_deg(T, refs[i]), trans_err_m(T, refs[i])
+        errs.append((dr, dt))
+        iters.append(info["iters"])
+        if info["converged"] and dr <= 1e-3 and dt <= 1e-5:
+            passed += 1
+    print(f"[bench] timed {args.steps} registrations in {elapsed:.3f} s; {passed} within the gate; "
+          f"max err {max(e[0] for e in errs):.2e} deg {max(e[1] for e in errs):.2e} m", file=sys.stderr, flush=True)
+
+    # Roofline pass: the same steps with every pair-kernel launch bracketed by events.
+    gcvo.gcvo_profile_reset()
+    gcvo.gcvo_profile_enable(True)
+    for k in range(args.steps):
+        step(k)
+    torch.cuda.synchronize()
+    gcvo.gcvo_profile_enable(False)
+    prof = gcvo.gcvo_profile_read()
+    kernel_s = prof["pair_kernel_ms"] / 1e3
+    flop = FLOP_PER_PAIR * prof["pairs"] + FLOP_PER_SOURCE_POINT * prof["source_points"]
+    achieved = flop / kernel_s / 1e12 if kernel_s > 0 else 0.0
+    avg_launch_us = 1e6 * kernel_s / max(prof["launches"], 1)
+    pairs_per_s = prof["pairs"] / kernel_s if kernel_s > 0 else 0.0
+    print(f"[bench] pair kernel: {prof['launches']} launches, avg {avg_launch_us:.1f} us, "
+          f"{prof['pairs'] / max(prof['launches'], 1):.3g} pairs/launch, {pairs_per_s:.3g} pairs/s",
+          file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        s = specs[0]
+        tc = time.perf_counter()
+        r = O.register_spec(s)
+        dtc = time.perf_counter() - tc
+        cpu = {"value": 1.0 / dtc, "unit": "registrations/s", "cores": O.num_threads(), "kind": "oracle",
+               "sample": f"one full FP64 oracle registration of LiDAR pair {s.name} "
+                         f"({len(s.target)}/{len(s.source)} points, {r.iters} iterations, {dtc:.1f} s)"}
+
+    ms_per_step = 1e3 * elapsed / args.steps
+    out = {
+        "metric": "registrations/s at <=1e-3 deg/1e-5 m vs oracle",
+        "value": passed / elapsed,
+        "unit": "registrations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "lidar_pair_64x1024_voxel0.3_anneal1.0to0.1",
+                   "points_per_cloud": int(np.mean([len(s.target) for s in specs])),
+                   "instances": N_INSTANCES, "registrations_total": args.steps,
+                   "registrations_in_gate": passed, "mean_iterations": float(np.mean(iters)),
+                   "kernel_pairs_per_s": pairs_per_s,
+                   "pct_fp32_valu_peak": 100.0 * achieved / FP32_VALU_PEAK_TFLOPS},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "k_iterate<float>", "avg_launch_us": avg_launch_us,
+                     "launches": prof["launches"]},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -130,11 +130,10 @@ int gcvo_register(const float *tgt_xyz, long long n_tgt, const float *src_xyz, l
                   const double *T_init, const gcvo_params *p, double *T_out, gcvo_info *info,
                   void *workspace, size_t workspace_bytes, void *stream);
 
-/* Bytes of device workspace gcvo_register_batch needs for n_pairs pairs whose
- * largest target / source clouds are max_tgt / max_src points and whose total
- * point counts are sum_tgt / sum_src; 0 if invalid. */
-size_t gcvo_batch_workspace_size(int n_pairs, long long sum_tgt, long long sum_src, long long max_tgt,
-                                 long long max_src, const gcvo_params *p);
+/* Bytes of device workspace gcvo_register_batch needs for the same n_pairs,
+ * offsets and parameters (see gcvo_register_batch); 0 if invalid. */
+size_t gcvo_batch_workspace_size(int n_pairs, const long long *tgt_off, const long long *src_off,
+                                 const gcvo_params *p, int shared_params);
 
 /*
  * Registers n_pairs independent pairs in one pass over the device.  Pair k's
@@ -142,8 +141,8 @@ size_t gcvo_batch_workspace_size(int n_pairs, long long sum_tgt, long long sum_s
  * src_xyz[src_off[k] .. src_off[k+1]) (device float32 [*][3]); the offsets are
  * HOST int64 arrays of n_pairs + 1 entries.  T_init: host [n_pairs][16] or NULL
  * (identity).  p: host array of n_pairs parameter sets, or one set shared by all
- * pairs when shared_params != 0.  T_out: host [n_pairs][16]; info: host
- * [n_pairs] or NULL.  A pair that fails (for example with no pairs in reach)
+ * pairs when shared_params != 0; all pairs must use the same knn and precision.
+ * T_out: host [n_pairs][16]; info: host [n_pairs] or NULL.  A pair that fails (for example with no pairs in reach)
  * reports its own status in info[k].status and keeps T_out[k] = T_init[k]; the
  * call returns the first failing pair's code only for argument errors, HIP
  * errors and workspace errors.  Waits on `stream`.
@@ -184,6 +183,20 @@ size_t gcvo_shapes_workspace_size(long long n);
  */
 int gcvo_point_shapes(const float *xyz, long long n, int knn, double rho, float *shape6_out,
                       void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Measurement of the per-iteration pair kernel (process-wide counters, meant
+ * for benchmarks; calls that run while profiling is enabled must not overlap).
+ * When enabled, gcvo_register and gcvo_register_batch bracket every launch of
+ * the pair kernel with HIP events on the caller's stream and accumulate, over
+ * the launches in which at least one pair was still iterating: the summed
+ * kernel time (ms), the number of such launches, the number of (target,
+ * source) pairs evaluated within the cutoff, and the number of source points
+ * processed.  gcvo_profile_read copies the counters out (any pointer may be NULL).
+ */
+void gcvo_profile_enable(int on);
+void gcvo_profile_reset(void);
+void gcvo_profile_read(double *pair_kernel_ms, long long *launches, long long *pairs, long long *source_points);
 
 /* Static text for a status code. */
 const char *gcvo_strerror(int status);

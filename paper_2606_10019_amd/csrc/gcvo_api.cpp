@@ -1,0 +1,672 @@
+// Host side of the C ABI declared in include/gcvo.h.
+//
+// Every entry point lays its device data out in the caller's workspace with a
+// bump allocator (a sizing pass with no base pointer gives *_workspace_size),
+// uploads the POD descriptors of gcvo_dev.h in one copy, enqueues the
+// preparation kernels and then the Gauss-Newton iterations in chunks.  While a
+// chunk runs, the host waits on the previous chunk's "pairs still active" count
+// (copied to pinned host memory), so the device never idles between chunks and
+// at most one chunk of no-op launches follows convergence.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "gcvo_dev.h"
+
+using namespace gcvo;
+
+namespace {
+
+constexpr int kChunk = 4;   // iterations enqueued per poll
+
+struct Arena {
+    char *base;
+    size_t off = 0;
+    explicit Arena(void *b) : base(static_cast<char *>(b)) {}
+    template <class T>
+    T *take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+// Length-scale schedule: ell_0 = ell, ell_{s+1} = max(alpha ell_s, ell_min) until ell_min.
+int stage_schedule(const gcvo_params &p, double ells[kMaxStages]) {
+    double l = p.length_scale;
+    int n = 0;
+    for (;;) {
+        if (n >= kMaxStages) return -1;
+        ells[n++] = l;
+        if (!(l > p.length_scale_min)) break;
+        l = std::max(p.anneal_factor * l, p.length_scale_min);
+    }
+    return n;
+}
+
+bool params_ok(const gcvo_params *p) {
+    if (!p) return false;
+    auto pos = [](double v) { return std::isfinite(v) && v > 0.0; };
+    if (!pos(p->length_scale) || !pos(p->length_scale_min) || p->length_scale_min > p->length_scale) return false;
+    if (!(p->anneal_factor > 0.0 && p->anneal_factor <= 1.0)) return false;
+    if (p->length_scale_min < p->length_scale && !(p->anneal_factor < 1.0)) return false;
+    if (!pos(p->cutoff_scale) || !pos(p->sigma2) || !pos(p->tol) || !pos(p->stage_tol)) return false;
+    if (p->knn < 2 || p->knn > kMaxKnn) return false;
+    if (!(p->eig_ratio_min > 0.0 && p->eig_ratio_min <= 1.0)) return false;
+    if (p->max_iters < 1 || p->max_iters_per_stage < 1) return false;
+    if (p->precision != GCVO_PRECISION_FP32 && p->precision != GCVO_PRECISION_FP64) return false;
+    double e[kMaxStages];
+    return stage_schedule(*p, e) > 0;
+}
+
+bool pose_ok(const double *T) {
+    if (!T) return true;
+    for (int a = 0; a < 16; ++a)
+        if (!std::isfinite(T[a])) return false;
+    if (std::fabs(T[12]) > 1e-6 || std::fabs(T[13]) > 1e-6 || std::fabs(T[14]) > 1e-6 ||
+        std::fabs(T[15] - 1.0) > 1e-6)
+        return false;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) s += T[4 * k + a] * T[4 * k + b];
+            if (std::fabs(s - (a == b ? 1.0 : 0.0)) > 1e-6) return false;
+        }
+    const double det = T[0] * (T[5] * T[10] - T[6] * T[9]) - T[1] * (T[4] * T[10] - T[6] * T[8]) +
+                       T[2] * (T[4] * T[9] - T[5] * T[8]);
+    return std::fabs(det - 1.0) <= 1e-6;
+}
+
+enum class Mode { Register, Eval, Shapes };
+
+struct PairInput {
+    const float *tgt, *src;
+    long long n_t, n_s;
+    gcvo_params p;
+    double T0[16];
+    const float *tgt_shape = nullptr, *src_shape = nullptr;   // Eval
+    float *shape_out = nullptr;                               // Shapes
+    double eval_ell = 0.0, eval_cutoff = 0.0;                 // Eval
+};
+
+struct Plan {
+    size_t bytes = 0;
+    std::vector<PairDev> pairs;
+    std::vector<SortJob> jobs;
+    std::vector<BlockTask> tasks;
+    PairDev *d_pairs = nullptr;
+    SortJob *d_jobs = nullptr;
+    BlockTask *d_tasks = nullptr;
+    int *d_active = nullptr;
+    char *desc_begin = nullptr;
+    size_t desc_bytes = 0;
+    int max_n = 0, max_job_n = 0;
+};
+
+// Lays out (base == nullptr: sizes) every device array of a batch.
+void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &pl) {
+    Arena A(base);
+    const int np = (int)in.size();
+    // job count and task count first (descriptor block is contiguous)
+    int n_jobs = 0, n_tasks = 0;
+    std::vector<int> nst(np);
+    std::vector<double> ells((size_t)np * kMaxStages);
+    for (int k = 0; k < np; ++k) {
+        if (mode == Mode::Register) {
+            nst[k] = stage_schedule(in[k].p, &ells[(size_t)k * kMaxStages]);
+            n_jobs += 2 + nst[k];
+        } else if (mode == Mode::Eval) {
+            nst[k] = 1;
+            ells[(size_t)k * kMaxStages] = in[k].eval_ell;
+            n_jobs += 2;
+        } else {
+            nst[k] = 0;
+            n_jobs += 1;
+        }
+        if (mode != Mode::Shapes) n_tasks += (int)((in[k].n_s + kBlock - 1) / kBlock);
+    }
+    pl.d_pairs = A.take<PairDev>(np);
+    pl.desc_begin = reinterpret_cast<char *>(pl.d_pairs);
+    size_t desc_start = A.off - sizeof(PairDev) * np;
+    pl.d_jobs = A.take<SortJob>(std::max(n_jobs, 1));
+    pl.d_tasks = A.take<BlockTask>(std::max(n_tasks, 1));
+    pl.desc_bytes = A.off - desc_start;
+    pl.d_active = A.take<int>(1);
+    if (base) {
+        pl.pairs.assign(np, PairDev{});
+        pl.jobs.assign(std::max(n_jobs, 1), SortJob{});
+        pl.tasks.assign(std::max(n_tasks, 1), BlockTask{});
+    }
+    int job = 0, task = 0;
+    pl.max_n = pl.max_job_n = 0;
+    for (int k = 0; k < np; ++k) {
+        const PairInput &I = in[k];
+        const int nt = (int)I.n_t, ns = (int)I.n_s;
+        pl.max_n = std::max(pl.max_n, std::max(nt, ns));
+        PairDev P{};
+        P.tgt_xyz = I.tgt;
+        P.src_xyz = I.src;
+        P.n_t = nt;
+        P.n_s = ns;
+        P.n_stages = nst[k];
+        for (int s = 0; s < nst[k]; ++s) P.ell[s] = ells[(size_t)k * kMaxStages + s];
+        P.knn = I.p.knn;
+        P.rho = I.p.eig_ratio_min;
+        P.cutoff_scale = (mode == Mode::Eval) ? I.eval_cutoff / I.eval_ell : I.p.cutoff_scale;
+        P.sigma2 = I.p.sigma2;
+        P.tol = I.p.tol;
+        P.stage_tol = I.p.stage_tol;
+        P.max_iters = I.p.max_iters;
+        P.max_per_stage = I.p.max_iters_per_stage;
+        std::memcpy(P.T_init, I.T0, sizeof P.T_init);
+        P.t_orig = A.take<float>(3 * (size_t)nt);
+        P.s_orig = A.take<float>(3 * (size_t)ns);
+        P.t_rec = A.take<float>(3 * (size_t)nt);
+        P.s_rec = A.take<float>(3 * (size_t)ns);
+        if (mode == Mode::Eval) {
+            P.t_shape = const_cast<float *>(I.tgt_shape);
+            P.s_shape = const_cast<float *>(I.src_shape);
+            P.shapes_given = 1;
+            P.eval_only = 1;
+        } else if (mode == Mode::Register) {
+            P.t_shape = A.take<float>(6 * (size_t)nt);
+            P.s_shape = A.take<float>(6 * (size_t)ns);
+        }
+        if (mode != Mode::Shapes) P.s_sorted = A.take<float>(kSortedRows * (size_t)ns);
+        P.st = A.take<State>(1);
+        P.iter_pairs = A.take<long long>((size_t)std::max(I.p.max_iters, 1));
+        P.n_blocks = (ns + kBlock - 1) / kBlock;
+        P.first_block = task;
+        P.partials = A.take<float>((size_t)std::max(P.n_blocks, 1) * kPartialStride * 2);
+        auto make_job = [&](int kind, int n, const float *x, int max_cells) {
+            SortJob J{};
+            J.x = x;
+            J.y = x ? x + n : nullptr;
+            J.z = x ? x + 2 * (size_t)n : nullptr;
+            J.n = n;
+            J.max_cells = max_cells;
+            J.grid = A.take<Grid>(1);
+            J.keys = A.take<uint32_t>(n);
+            J.keys_tmp = A.take<uint32_t>(n);
+            J.idx = A.take<uint32_t>(n);
+            J.idx_tmp = A.take<uint32_t>(n);
+            J.cell_start = A.take<int>((size_t)max_cells + 1);
+            J.pair = k;
+            J.kind = kind;
+            pl.max_job_n = std::max(pl.max_job_n, n);
+            return J;
+        };
+        const int knn_cells_t = 4 * nt + 64, knn_cells_s = 4 * ns + 64, stage_cells = 16 * nt + 64;
+        if (mode == Mode::Register || mode == Mode::Shapes) {
+            SortJob J = make_job(kJobKnnTarget, nt, P.t_orig, knn_cells_t);
+            J.want_shapes = 1;
+            J.shape_out = (mode == Mode::Shapes) ? I.shape_out : P.t_shape;
+            P.job_knn_t = pl.d_jobs + job;
+            if (base) pl.jobs[job] = J;
+            ++job;
+        }
+        if (mode != Mode::Shapes) {
+            SortJob J = make_job(kJobKnnSource, ns, P.s_orig, knn_cells_s);
+            J.want_shapes = (mode == Mode::Register) ? 1 : 0;
+            J.shape_out = P.s_shape;
+            P.job_knn_s = pl.d_jobs + job;
+            if (base) pl.jobs[job] = J;
+            ++job;
+            P.job_stage0 = pl.d_jobs + job;
+            for (int s = 0; s < nst[k]; ++s) {
+                SortJob Js = make_job(kJobStage + s, nt, P.t_rec, stage_cells);
+                P.t_sorted[s] = A.take<float>(kSortedRows * (size_t)nt);
+                P.t_cells[s] = Js.cell_start;
+                P.t_grid[s] = Js.grid;
+                if (base) pl.jobs[job] = Js;
+                ++job;
+            }
+            for (int b = 0; b < P.n_blocks; ++b) {
+                if (base) pl.tasks[task] = BlockTask{k, b};
+                ++task;
+            }
+        }
+        if (base) pl.pairs[k] = P;
+    }
+    pl.bytes = A.off + 256;
+}
+
+// Process-wide pair-kernel measurement (see gcvo_profile_enable).
+struct Profile {
+    bool on = false;
+    double ms = 0.0;
+    long long launches = 0, pairs = 0, points = 0;
+    std::vector<hipEvent_t> ev;   // grown on demand, kept for the process
+};
+Profile g_prof;
+
+hipEvent_t prof_event(size_t k) {
+    while (g_prof.ev.size() <= k) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        g_prof.ev.push_back(e);
+    }
+    return g_prof.ev[k];
+}
+
+struct Pinned {
+    int *flags = nullptr;
+    ~Pinned() = default;   // lives for the thread; released by the runtime at exit
+};
+
+int *pinned_flags() {
+    static thread_local Pinned p;
+    if (!p.flags) {
+        void *q = nullptr;
+        if (hipHostMalloc(&q, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess) return nullptr;
+        p.flags = static_cast<int *>(q);
+    }
+    return p.flags;
+}
+
+#define HIP_OK(expr)                                        \
+    do {                                                    \
+        if ((expr) != hipSuccess) return GCVO_ERR_HIP;      \
+    } while (0)
+
+int upload_and_prepare(Plan &pl, int knn, hipStream_t s) {
+    // descriptors are contiguous from d_pairs; copy the three host vectors into place
+    std::vector<char> blob(pl.desc_bytes, 0);
+    char *d0 = reinterpret_cast<char *>(pl.d_pairs);
+    std::memcpy(blob.data(), pl.pairs.data(), pl.pairs.size() * sizeof(PairDev));
+    std::memcpy(blob.data() + (reinterpret_cast<char *>(pl.d_jobs) - d0), pl.jobs.data(),
+                pl.jobs.size() * sizeof(SortJob));
+    std::memcpy(blob.data() + (reinterpret_cast<char *>(pl.d_tasks) - d0), pl.tasks.data(),
+                pl.tasks.size() * sizeof(BlockTask));
+    HIP_OK(hipMemcpyAsync(d0, blob.data(), pl.desc_bytes, hipMemcpyHostToDevice, s));
+    const int n_jobs = (int)pl.jobs.size();
+    HIP_OK(launch_prepare(pl.d_pairs, (int)pl.pairs.size(), pl.max_n, pl.d_jobs, n_jobs, pl.max_job_n, knn, s));
+    return GCVO_OK;
+}
+
+// After a profiled run: launches in which some pair iterated are the first
+// max_k(iterations of pair k) ones; their event-bracketed durations and the
+// pairs logged by the device are added to the counters.
+int profile_collect(Plan &pl, int launched, hipStream_t s) {
+    const int np = (int)pl.pairs.size();
+    int active = 0;
+    long long pairs = 0, points = 0;
+    for (int k = 0; k < np; ++k) {
+        State st;
+        if (hipMemcpy(&st, pl.pairs[k].st, sizeof st, hipMemcpyDeviceToHost) != hipSuccess) return GCVO_ERR_HIP;
+        const int it = std::min(st.iter + ((st.status != GCVO_OK) ? 1 : 0), pl.pairs[k].max_iters);
+        active = std::max(active, it);
+        if (it > 0) {
+            std::vector<long long> log(it);
+            if (hipMemcpy(log.data(), pl.pairs[k].iter_pairs, it * sizeof(long long), hipMemcpyDeviceToHost) !=
+                hipSuccess)
+                return GCVO_ERR_HIP;
+            for (long long v : log) pairs += v;
+            points += (long long)it * pl.pairs[k].n_s;
+        }
+    }
+    active = std::min(active, launched);
+    double ms = 0.0;
+    for (int i = 0; i < active; ++i) {
+        float e = 0.0f;
+        if (hipEventElapsedTime(&e, g_prof.ev[2 * i], g_prof.ev[2 * i + 1]) != hipSuccess) return GCVO_ERR_HIP;
+        ms += e;
+    }
+    (void)s;
+    g_prof.ms += ms;
+    g_prof.launches += active;
+    g_prof.pairs += pairs;
+    g_prof.points += points;
+    return GCVO_OK;
+}
+
+int run_iterations(Plan &pl, int max_iters, int precision, hipStream_t s) {
+    int *flags = pinned_flags();
+    if (!flags) return GCVO_ERR_HIP;
+    hipEvent_t ev[2];
+    HIP_OK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
+        hipEventDestroy(ev[0]);
+        return GCVO_ERR_HIP;
+    }
+    const int n_tasks = (int)pl.tasks.size();
+    const int np = (int)pl.pairs.size();
+    int launched = 0, slot = 0, rc = GCVO_OK;
+    bool pending[2] = {false, false};
+    auto enqueue = [&](int c) -> hipError_t {
+        if (!g_prof.on) return launch_iterations(pl.d_pairs, pl.d_tasks, n_tasks, c, precision, s);
+        for (int i = 0; i < c; ++i) {
+            hipEvent_t a = prof_event(2 * (size_t)(launched + i)), b = prof_event(2 * (size_t)(launched + i) + 1);
+            if (!a || !b) return hipErrorOutOfMemory;
+            hipError_t e = hipEventRecord(a, s);
+            if (e == hipSuccess) e = launch_iterations(pl.d_pairs, pl.d_tasks, n_tasks, 1, precision, s);
+            if (e == hipSuccess) e = hipEventRecord(b, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    while (launched < max_iters) {
+        const int c = std::min(kChunk, max_iters - launched);
+        if (enqueue(c) != hipSuccess ||
+            launch_count_active(pl.d_pairs, np, pl.d_active, s) != hipSuccess ||
+            hipMemcpyAsync(&flags[slot], pl.d_active, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipEventRecord(ev[slot], s) != hipSuccess) {
+            rc = GCVO_ERR_HIP;
+            break;
+        }
+        launched += c;
+        pending[slot] = true;
+        const int other = slot ^ 1;
+        if (pending[other]) {
+            if (hipEventSynchronize(ev[other]) != hipSuccess) {
+                rc = GCVO_ERR_HIP;
+                break;
+            }
+            pending[other] = false;
+            if (flags[other] == 0) break;
+        }
+        slot = other;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) rc = GCVO_ERR_HIP;
+    hipEventDestroy(ev[0]);
+    hipEventDestroy(ev[1]);
+    if (rc == GCVO_OK && g_prof.on) rc = profile_collect(pl, launched, s);
+    return rc;
+}
+
+void fill_info(const State &S, gcvo_info *info) {
+    if (!info) return;
+    std::memset(info, 0, sizeof *info);
+    info->status = S.status;
+    info->converged = S.converged;
+    info->iters = S.iter;
+    info->stages = S.stage + 1;
+    info->pairs_last = S.pairs_last;
+    info->f = S.f;
+    std::memcpy(info->g, S.g, sizeof info->g);
+    info->xi_l1 = S.xi_l1;
+    for (int s = 0; s < kMaxStages; ++s) info->stage_iters[s] = S.stage_iters[s];
+}
+
+bool ws_ok(void *ws, size_t ws_bytes, size_t need) {
+    return ws && (reinterpret_cast<uintptr_t>(ws) & 255u) == 0 && ws_bytes >= need;
+}
+
+int register_many(Mode mode, std::vector<PairInput> &in, double *T_out, gcvo_info *info, void *ws,
+                  size_t ws_bytes, hipStream_t s, int shared_knn, int precision, int max_iters) {
+    Plan sizing;
+    build_plan(nullptr, mode, in, sizing);
+    if (!ws_ok(ws, ws_bytes, sizing.bytes)) return GCVO_ERR_WORKSPACE;
+    Plan pl;
+    build_plan(ws, mode, in, pl);
+    int rc = upload_and_prepare(pl, shared_knn, s);
+    if (rc) return rc;
+    rc = run_iterations(pl, max_iters, precision, s);
+    if (rc) return rc;
+    const int np = (int)in.size();
+    std::vector<State> st(np);
+    for (int k = 0; k < np; ++k)
+        HIP_OK(hipMemcpyAsync(&st[k], pl.pairs[k].st, sizeof(State), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    int first_err = GCVO_OK;
+    for (int k = 0; k < np; ++k) {
+        if (st[k].status == GCVO_OK) std::memcpy(T_out + 16 * (size_t)k, st[k].T, 16 * sizeof(double));
+        else if (first_err == GCVO_OK) first_err = st[k].status;
+        if (info) fill_info(st[k], info + k);
+    }
+    return first_err;
+}
+
+const double kIdentity[16] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1};
+
+}  // namespace
+
+extern "C" {
+
+void gcvo_default_params(gcvo_params *p) {
+    if (!p) return;
+    p->length_scale = 0.3;
+    p->length_scale_min = 0.3;
+    p->anneal_factor = 0.5;
+    p->cutoff_scale = 3.0;
+    p->knn = 10;
+    p->eig_ratio_min = 0.01;
+    p->sigma2 = 1.0;
+    p->max_iters = 30;
+    p->max_iters_per_stage = 30;
+    p->tol = 1e-6;
+    p->stage_tol = 1e-4;
+    p->precision = GCVO_PRECISION_FP32;
+}
+
+int gcvo_abi_version(void) { return 100; }
+
+void gcvo_profile_enable(int on) { g_prof.on = on != 0; }
+
+void gcvo_profile_reset(void) {
+    g_prof.ms = 0.0;
+    g_prof.launches = g_prof.pairs = g_prof.points = 0;
+}
+
+void gcvo_profile_read(double *ms, long long *launches, long long *pairs, long long *points) {
+    if (ms) *ms = g_prof.ms;
+    if (launches) *launches = g_prof.launches;
+    if (pairs) *pairs = g_prof.pairs;
+    if (points) *points = g_prof.points;
+}
+
+const char *gcvo_strerror(int status) {
+    switch (status) {
+        case GCVO_OK: return "ok";
+        case GCVO_ERR_INVALID: return "invalid argument (null pointer, size, non-finite input, pose or parameter)";
+        case GCVO_ERR_TOO_FEW_POINTS: return "a cloud has fewer points than knn";
+        case GCVO_ERR_NO_PAIRS: return "no point pair within the cutoff";
+        case GCVO_ERR_SINGULAR: return "the damped Gauss-Newton system is singular";
+        case GCVO_ERR_WORKSPACE: return "workspace missing, too small or not 256-byte aligned";
+        case GCVO_ERR_HIP: return "HIP runtime error";
+        case GCVO_ERR_CAPACITY: return "size beyond the library limits";
+        default: return "unknown status";
+    }
+}
+
+size_t gcvo_workspace_size(long long n_tgt, long long n_src, const gcvo_params *p) {
+    if (!params_ok(p) || n_tgt < 1 || n_src < 1 || n_tgt > GCVO_MAX_POINTS || n_src > GCVO_MAX_POINTS) return 0;
+    std::vector<PairInput> in(1);
+    in[0] = PairInput{nullptr, nullptr, n_tgt, n_src, *p, {}};
+    Plan pl;
+    build_plan(nullptr, Mode::Register, in, pl);
+    return pl.bytes;
+}
+
+int gcvo_register(const float *tgt_xyz, long long n_tgt, const float *src_xyz, long long n_src,
+                  const double *T_init, const gcvo_params *p, double *T_out, gcvo_info *info, void *workspace,
+                  size_t workspace_bytes, void *stream) {
+    auto fail = [&](int st) {
+        if (info) {
+            std::memset(info, 0, sizeof *info);
+            info->status = st;
+        }
+        return st;
+    };
+    if (!tgt_xyz || !src_xyz || !T_out || !params_ok(p) || !pose_ok(T_init) || n_tgt < 0 || n_src < 0)
+        return fail(GCVO_ERR_INVALID);
+    if (n_tgt > GCVO_MAX_POINTS || n_src > GCVO_MAX_POINTS) return fail(GCVO_ERR_CAPACITY);
+    if (n_tgt < p->knn || n_src < p->knn) return fail(GCVO_ERR_TOO_FEW_POINTS);
+    std::vector<PairInput> in(1);
+    in[0] = PairInput{tgt_xyz, src_xyz, n_tgt, n_src, *p, {}};
+    std::memcpy(in[0].T0, T_init ? T_init : kIdentity, sizeof in[0].T0);
+    double T[16];
+    int rc = register_many(Mode::Register, in, T, info, workspace, workspace_bytes, (hipStream_t)stream, p->knn,
+                           p->precision, p->max_iters);
+    if (rc == GCVO_ERR_HIP || rc == GCVO_ERR_WORKSPACE) return fail(rc);   // info not filled by the run
+    if (rc != GCVO_OK) return rc;                                           // info holds the run's summary
+    std::memcpy(T_out, T, sizeof T);
+    return GCVO_OK;
+}
+
+size_t gcvo_batch_workspace_size(int n_pairs, const long long *tgt_off, const long long *src_off,
+                                 const gcvo_params *p, int shared_params) {
+    if (n_pairs < 1 || !tgt_off || !src_off || !p) return 0;
+    std::vector<PairInput> in;
+    for (int k = 0; k < n_pairs; ++k) {
+        const gcvo_params &pk = shared_params ? p[0] : p[k];
+        const long long nt = tgt_off[k + 1] - tgt_off[k], ns = src_off[k + 1] - src_off[k];
+        if (!params_ok(&pk) || nt < 0 || ns < 0 || nt > GCVO_MAX_POINTS || ns > GCVO_MAX_POINTS) return 0;
+        if (nt < pk.knn || ns < pk.knn) continue;   // such pairs are reported, not run
+        in.push_back(PairInput{nullptr, nullptr, nt, ns, pk, {}});
+    }
+    if (in.empty()) return 256;
+    Plan pl;
+    build_plan(nullptr, Mode::Register, in, pl);
+    return pl.bytes;
+}
+
+int gcvo_register_batch(int n_pairs, const float *tgt_xyz, const long long *tgt_off, const float *src_xyz,
+                        const long long *src_off, const double *T_init, const gcvo_params *p, int shared_params,
+                        double *T_out, gcvo_info *info, void *workspace, size_t workspace_bytes, void *stream) {
+    if (n_pairs < 1 || !tgt_xyz || !tgt_off || !src_xyz || !src_off || !p || !T_out) return GCVO_ERR_INVALID;
+    std::vector<PairInput> in(n_pairs);
+    int knn = p[0].knn, prec = p[0].precision, max_it = 0;
+    for (int k = 0; k < n_pairs; ++k) {
+        const gcvo_params &pk = shared_params ? p[0] : p[k];
+        if (!params_ok(&pk) || pk.knn != knn || pk.precision != prec) return GCVO_ERR_INVALID;
+        const long long nt = tgt_off[k + 1] - tgt_off[k], ns = src_off[k + 1] - src_off[k];
+        if (nt < 0 || ns < 0 || tgt_off[k] < 0 || src_off[k] < 0) return GCVO_ERR_INVALID;
+        if (nt > GCVO_MAX_POINTS || ns > GCVO_MAX_POINTS) return GCVO_ERR_CAPACITY;
+        const double *T0 = T_init ? T_init + 16 * (size_t)k : kIdentity;
+        if (!pose_ok(T0)) return GCVO_ERR_INVALID;
+        in[k] = PairInput{tgt_xyz + 3 * tgt_off[k], src_xyz + 3 * src_off[k], nt, ns, pk, {}};
+        std::memcpy(in[k].T0, T0, sizeof in[k].T0);
+        max_it = std::max(max_it, pk.max_iters);
+    }
+    // Pairs too small to register fail individually; the rest run.
+    std::vector<int> keep;
+    for (int k = 0; k < n_pairs; ++k) {
+        std::memcpy(T_out + 16 * (size_t)k, in[k].T0, 16 * sizeof(double));
+        if (in[k].n_t < knn || in[k].n_s < knn) {
+            if (info) {
+                std::memset(info + k, 0, sizeof(gcvo_info));
+                info[k].status = GCVO_ERR_TOO_FEW_POINTS;
+            }
+        } else {
+            keep.push_back(k);
+        }
+    }
+    if (keep.empty()) return GCVO_OK;
+    std::vector<PairInput> run;
+    for (int k : keep) run.push_back(in[k]);
+    std::vector<double> T(16 * run.size());
+    std::vector<gcvo_info> inf(run.size());
+    for (size_t r = 0; r < run.size(); ++r) std::memcpy(&T[16 * r], run[r].T0, 16 * sizeof(double));
+    int rc = register_many(Mode::Register, run, T.data(), inf.data(), workspace, workspace_bytes,
+                           (hipStream_t)stream, knn, prec, max_it);
+    if (rc == GCVO_ERR_HIP || rc == GCVO_ERR_WORKSPACE) return rc;
+    for (size_t r = 0; r < run.size(); ++r) {
+        const int k = keep[r];
+        if (inf[r].status == GCVO_OK) std::memcpy(T_out + 16 * (size_t)k, &T[16 * r], 16 * sizeof(double));
+        if (info) info[k] = inf[r];
+    }
+    return GCVO_OK;
+}
+
+size_t gcvo_eval_workspace_size(long long n_tgt, long long n_src) {
+    if (n_tgt < 0 || n_src < 0 || n_tgt > GCVO_MAX_POINTS || n_src > GCVO_MAX_POINTS) return 0;
+    std::vector<PairInput> in(1);
+    gcvo_params p;
+    gcvo_default_params(&p);
+    in[0] = PairInput{nullptr, nullptr, n_tgt, n_src, p, {}};
+    in[0].eval_ell = 1.0;
+    in[0].eval_cutoff = 3.0;
+    Plan pl;
+    build_plan(nullptr, Mode::Eval, in, pl);
+    return pl.bytes;
+}
+
+int gcvo_eval_fgh(const float *tgt_xyz, const float *tgt_shape6, long long n_tgt, const float *src_xyz,
+                  const float *src_shape6, long long n_src, const double *T, double length_scale, double cutoff,
+                  double sigma2, int precision, double *f, double *g, double *H, long long *n_pairs,
+                  void *workspace, size_t workspace_bytes, void *stream) {
+    if (!T || !f || !g || !H || n_tgt < 0 || n_src < 0) return GCVO_ERR_INVALID;
+    if ((n_tgt > 0 && (!tgt_xyz || !tgt_shape6)) || (n_src > 0 && (!src_xyz || !src_shape6))) return GCVO_ERR_INVALID;
+    if (!pose_ok(T) || !(std::isfinite(length_scale) && length_scale > 0.0) || !(cutoff > 0.0) ||
+        !(std::isfinite(sigma2) && sigma2 > 0.0))
+        return GCVO_ERR_INVALID;
+    if (precision != GCVO_PRECISION_FP32 && precision != GCVO_PRECISION_FP64) return GCVO_ERR_INVALID;
+    if (n_tgt > GCVO_MAX_POINTS || n_src > GCVO_MAX_POINTS) return GCVO_ERR_CAPACITY;
+    if (n_tgt == 0 || n_src == 0) {   // empty double sum
+        *f = 0.0;
+        std::memset(g, 0, 6 * sizeof(double));
+        std::memset(H, 0, 36 * sizeof(double));
+        if (n_pairs) *n_pairs = 0;
+        return GCVO_OK;
+    }
+    std::vector<PairInput> in(1);
+    gcvo_params p;
+    gcvo_default_params(&p);
+    p.sigma2 = sigma2;
+    p.precision = precision;
+    in[0] = PairInput{tgt_xyz, src_xyz, n_tgt, n_src, p, {}};
+    std::memcpy(in[0].T0, T, sizeof in[0].T0);
+    in[0].tgt_shape = tgt_shape6;
+    in[0].src_shape = src_shape6;
+    in[0].eval_ell = length_scale;
+    in[0].eval_cutoff = cutoff;
+    hipStream_t s = (hipStream_t)stream;
+    Plan sizing;
+    build_plan(nullptr, Mode::Eval, in, sizing);
+    if (!ws_ok(workspace, workspace_bytes, sizing.bytes)) return GCVO_ERR_WORKSPACE;
+    Plan pl;
+    build_plan(workspace, Mode::Eval, in, pl);
+    int rc = upload_and_prepare(pl, 0, s);
+    if (rc) return rc;
+    HIP_OK(launch_iterations(pl.d_pairs, pl.d_tasks, (int)pl.tasks.size(), 1, precision, s));
+    State st;
+    HIP_OK(hipMemcpyAsync(&st, pl.pairs[0].st, sizeof st, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (st.status != GCVO_OK) return st.status;
+    *f = st.f;
+    std::memcpy(g, st.g, 6 * sizeof(double));
+    std::memcpy(H, st.H, 36 * sizeof(double));
+    if (n_pairs) *n_pairs = st.pairs_last;
+    return GCVO_OK;
+}
+
+size_t gcvo_shapes_workspace_size(long long n) {
+    if (n < 1 || n > GCVO_MAX_POINTS) return 0;
+    std::vector<PairInput> in(1);
+    gcvo_params p;
+    gcvo_default_params(&p);
+    in[0] = PairInput{nullptr, nullptr, n, 0, p, {}};
+    Plan pl;
+    build_plan(nullptr, Mode::Shapes, in, pl);
+    return pl.bytes;
+}
+
+int gcvo_point_shapes(const float *xyz, long long n, int knn, double rho, float *shape6_out, void *workspace,
+                      size_t workspace_bytes, void *stream) {
+    if (!xyz || !shape6_out || n < 0 || knn < 2 || knn > kMaxKnn || !(rho > 0.0 && rho <= 1.0))
+        return GCVO_ERR_INVALID;
+    if (n > GCVO_MAX_POINTS) return GCVO_ERR_CAPACITY;
+    if (n < knn) return GCVO_ERR_TOO_FEW_POINTS;
+    std::vector<PairInput> in(1);
+    gcvo_params p;
+    gcvo_default_params(&p);
+    p.knn = knn;
+    p.eig_ratio_min = rho;
+    in[0] = PairInput{xyz, xyz, n, 0, p, {}};
+    std::memcpy(in[0].T0, kIdentity, sizeof in[0].T0);
+    in[0].shape_out = shape6_out;
+    hipStream_t s = (hipStream_t)stream;
+    Plan sizing;
+    build_plan(nullptr, Mode::Shapes, in, sizing);
+    if (!ws_ok(workspace, workspace_bytes, sizing.bytes)) return GCVO_ERR_WORKSPACE;
+    Plan pl;
+    build_plan(workspace, Mode::Shapes, in, pl);
+    return upload_and_prepare(pl, knn, s);
+}
+
+}  // extern "C"

@@ -20,6 +20,7 @@ constexpr int kMaxKnn = GCVO_MAX_KNN;
 constexpr int kNumSums = 28;          // f, g (6), upper triangle of H_main (21)
 constexpr int kPartialStride = 32;    // floats per block partial: 28 sums + pair count + pad
 constexpr float kCellMargin = 1.001f; // pair-grid cell edge = margin * cutoff (see Grid)
+constexpr int kSortedRows = 12;      // rows of the sorted per-point arrays (see PairDev)
 
 // Uniform grid over an axis-aligned box.  Cell of a point p along axis d is
 // clamp(floor((p_d - lo_d) * inv_h), 0, n_d - 1); cells are numbered x-fastest.
@@ -92,12 +93,16 @@ struct PairDev {
     float *t_orig, *s_orig;           // SoA [3][n] original coordinates (kNN grids)
     float *t_rec, *s_rec;             // SoA [3][n] recentred coordinates
     float *t_shape, *s_shape;         // SoA [6][n] shapes, original point order
-    float *s_sorted;                  // SoA [9][n_s] recentred xyz + shape, source grid order
-    float *t_sorted[kMaxStages];      // SoA [9][n_t] recentred xyz + shape, stage grid order
+    // Sorted SoA arrays [kSortedRows][n]: rows 0-2 recentred xyz (float32),
+    // rows 3-8 shape, rows 9-11 original xyz (read by the FP64 instantiation,
+    // which recentres exactly in FP64).
+    float *s_sorted;                  // source, in its own grid order
+    float *t_sorted[kMaxStages];      // target, in each stage grid's order
     int *t_cells[kMaxStages];         // cell_start of each stage grid
     Grid *t_grid[kMaxStages];
     SortJob *job_knn_t, *job_knn_s, *job_stage0;   // job_stage0[s] for s < n_stages
     State *st;
+    long long *iter_pairs;            // [max_iters] pairs within the cutoff at each iteration
     float *partials;                  // [n_blocks][kPartialStride]
     int n_blocks;                     // 256-point blocks of the source cloud
     int first_block;                  // index of the pair's first BlockTask
@@ -137,8 +142,9 @@ __device__ __forceinline__ float wave_max(float v) {
 
 // Enqueue the per-registration preparation: bounds and centroid, grids, SoA
 // copies, cell keys, radix sorts, kNN shapes and the sorted per-stage arrays.
+// knn selects the kNN kernel instantiation (0: no shapes are computed).
 hipError_t launch_prepare(PairDev *pairs_dev, int n_pairs, int max_n, SortJob *jobs_dev, int n_jobs,
-                          int max_job_n, hipStream_t s);
+                          int max_job_n, int knn, hipStream_t s);
 // Enqueue n_iters Gauss-Newton iterations (each a no-op for pairs already done).
 hipError_t launch_iterations(PairDev *pairs_dev, BlockTask *tasks_dev, int n_tasks, int n_iters,
                              int precision, hipStream_t s);

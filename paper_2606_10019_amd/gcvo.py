@@ -1,0 +1,326 @@
+"""Python binding of the gfx950 G-CVO library (``libgcvo.so``).
+
+Argument marshalling only: tensors are passed to the C ABI of
+``include/gcvo.h`` as raw device pointers with the current HIP stream, and
+every step of the computation runs in the library's kernels.  There is no CPU
+fallback: if the library is missing or fails to load, every call raises.
+
+Device tensors are torch CUDA (HIP) tensors: clouds float32 ``[n, 3]``
+contiguous, shapes float32 ``[6, n]`` (xx, xy, xz, yy, yz, zz).  Poses are
+float64 numpy ``4x4`` arrays on the host.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgcvo.so")
+
+GCVO_OK = 0
+GCVO_ERR_INVALID = -1
+GCVO_ERR_TOO_FEW_POINTS = -2
+GCVO_ERR_NO_PAIRS = -3
+GCVO_ERR_SINGULAR = -4
+GCVO_ERR_WORKSPACE = -5
+GCVO_ERR_HIP = -6
+GCVO_ERR_CAPACITY = -7
+GCVO_PRECISION_FP32 = 0
+GCVO_PRECISION_FP64 = 1
+GCVO_MAX_STAGES = 16
+
+EXPORTED = ["gcvo_default_params", "gcvo_workspace_size", "gcvo_register", "gcvo_batch_workspace_size",
+            "gcvo_register_batch", "gcvo_eval_workspace_size", "gcvo_eval_fgh", "gcvo_shapes_workspace_size",
+            "gcvo_point_shapes", "gcvo_strerror", "gcvo_abi_version", "gcvo_profile_enable",
+            "gcvo_profile_reset", "gcvo_profile_read"]
+
+
+class gcvo_params(ctypes.Structure):
+    _fields_ = [("length_scale", ctypes.c_double), ("length_scale_min", ctypes.c_double),
+                ("anneal_factor", ctypes.c_double), ("cutoff_scale", ctypes.c_double),
+                ("knn", ctypes.c_int), ("eig_ratio_min", ctypes.c_double), ("sigma2", ctypes.c_double),
+                ("max_iters", ctypes.c_int), ("max_iters_per_stage", ctypes.c_int),
+                ("tol", ctypes.c_double), ("stage_tol", ctypes.c_double), ("precision", ctypes.c_int)]
+
+
+class gcvo_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("converged", ctypes.c_int), ("iters", ctypes.c_int),
+                ("stages", ctypes.c_int), ("pairs_last", ctypes.c_longlong), ("f", ctypes.c_double),
+                ("g", ctypes.c_double * 6), ("xi_l1", ctypes.c_double),
+                ("stage_iters", ctypes.c_int * GCVO_MAX_STAGES)]
+
+    def to_dict(self) -> dict:
+        return dict(status=self.status, converged=bool(self.converged), iters=self.iters, stages=self.stages,
+                    pairs_last=self.pairs_last, f=self.f, g=list(self.g), xi_l1=self.xi_l1,
+                    stage_iters=list(self.stage_iters)[:max(self.stages, 0)])
+
+
+class GcvoError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {strerror(status)} ({status})")
+        self.status = status
+
+
+_P = ctypes.c_void_p
+_lib = None
+
+
+def load_library() -> ctypes.CDLL:
+    """Load libgcvo.so (built by ``__graft_entry__.build()``); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build the gfx950 library first (__graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    pp = ctypes.POINTER(gcvo_params)
+    L.gcvo_default_params.argtypes = [pp]
+    L.gcvo_default_params.restype = None
+    L.gcvo_workspace_size.argtypes = [ctypes.c_longlong, ctypes.c_longlong, pp]
+    L.gcvo_workspace_size.restype = ctypes.c_size_t
+    L.gcvo_register.argtypes = [_P, ctypes.c_longlong, _P, ctypes.c_longlong, _P, pp, _P,
+                                ctypes.POINTER(gcvo_info), _P, ctypes.c_size_t, _P]
+    L.gcvo_batch_workspace_size.argtypes = [ctypes.c_int, _P, _P, pp, ctypes.c_int]
+    L.gcvo_batch_workspace_size.restype = ctypes.c_size_t
+    L.gcvo_register_batch.argtypes = [ctypes.c_int, _P, _P, _P, _P, _P, pp, ctypes.c_int, _P,
+                                      ctypes.POINTER(gcvo_info), _P, ctypes.c_size_t, _P]
+    L.gcvo_eval_workspace_size.argtypes = [ctypes.c_longlong, ctypes.c_longlong]
+    L.gcvo_eval_workspace_size.restype = ctypes.c_size_t
+    L.gcvo_eval_fgh.argtypes = [_P, _P, ctypes.c_longlong, _P, _P, ctypes.c_longlong, _P, ctypes.c_double,
+                                ctypes.c_double, ctypes.c_double, ctypes.c_int, _P, _P, _P, _P, _P,
+                                ctypes.c_size_t, _P]
+    L.gcvo_shapes_workspace_size.argtypes = [ctypes.c_longlong]
+    L.gcvo_shapes_workspace_size.restype = ctypes.c_size_t
+    L.gcvo_point_shapes.argtypes = [_P, ctypes.c_longlong, ctypes.c_int, ctypes.c_double, _P, _P,
+                                    ctypes.c_size_t, _P]
+    L.gcvo_strerror.argtypes = [ctypes.c_int]
+    L.gcvo_strerror.restype = ctypes.c_char_p
+    L.gcvo_abi_version.argtypes = []
+    L.gcvo_profile_enable.argtypes = [ctypes.c_int]
+    L.gcvo_profile_enable.restype = None
+    L.gcvo_profile_reset.argtypes = []
+    L.gcvo_profile_reset.restype = None
+    L.gcvo_profile_read.argtypes = [_P, _P, _P, _P]
+    L.gcvo_profile_read.restype = None
+    _lib = L
+    return L
+
+
+def strerror(status: int) -> str:
+    return load_library().gcvo_strerror(int(status)).decode()
+
+
+def default_params(**overrides) -> gcvo_params:
+    p = gcvo_params()
+    load_library().gcvo_default_params(ctypes.byref(p))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def params_from_spec(spec, **overrides) -> gcvo_params:
+    """gcvo_params from a ``synth.PairSpec``'s solver settings."""
+    d = spec.params()
+    d.update(overrides)
+    return default_params(**d)
+
+
+# ----------------------------------------------------------------- device plumbing
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _cloud(t, name: str):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a torch CUDA tensor")
+    if t.dtype != torch.float32 or t.dim() != 2 or t.shape[1] != 3:
+        raise TypeError(f"{name} must be float32 [n, 3]")
+    return t.contiguous()
+
+
+def _shape6(t, n: int, name: str):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or tuple(t.shape) != (6, n):
+        raise TypeError(f"{name} must be a float32 CUDA tensor [6, {n}]")
+    return t.contiguous()
+
+
+def workspace(nbytes: int, device=None):
+    """A device byte buffer from torch's allocator (256-byte aligned)."""
+    torch = _torch()
+    buf = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device or "cuda")
+    off = (-buf.data_ptr()) % 256
+    return buf, buf.data_ptr() + off, int(nbytes)
+
+
+def _pose(T) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(T, dtype=np.float64).reshape(4, 4))
+    return a
+
+
+# ----------------------------------------------------------------- entry points
+
+def gcvo_workspace_size(n_tgt: int, n_src: int, params: gcvo_params) -> int:
+    return int(load_library().gcvo_workspace_size(n_tgt, n_src, ctypes.byref(params)))
+
+
+def gcvo_register(target, source, T_init=None, params: gcvo_params | None = None, ws=None, stream=None):
+    """Register one pair; returns (T float64 4x4, info dict).  Raises GcvoError."""
+    L = load_library()
+    target = _cloud(target, "target")
+    source = _cloud(source, "source")
+    p = params if params is not None else default_params()
+    T0 = None if T_init is None else _pose(T_init)
+    need = L.gcvo_workspace_size(target.shape[0], source.shape[0], ctypes.byref(p))
+    if ws is None:
+        holder, wptr, wbytes = workspace(max(need, 256), target.device)
+    else:
+        holder, wptr, wbytes = ws
+    T_out = np.zeros((4, 4))
+    info = gcvo_info()
+    st = L.gcvo_register(_ptr(target), target.shape[0], _ptr(source), source.shape[0],
+                         T0.ctypes.data_as(_P) if T0 is not None else None, ctypes.byref(p),
+                         T_out.ctypes.data_as(_P), ctypes.byref(info), ctypes.c_void_p(wptr), wbytes,
+                         _stream_handle(stream))
+    del holder
+    if st != GCVO_OK:
+        raise GcvoError(st, "gcvo_register")
+    return T_out, info.to_dict()
+
+
+def gcvo_batch_workspace_size(tgt_off, src_off, params) -> int:
+    L = load_library()
+    to = np.ascontiguousarray(tgt_off, dtype=np.int64)
+    so = np.ascontiguousarray(src_off, dtype=np.int64)
+    shared, parr = _param_array(params, len(to) - 1)
+    return int(L.gcvo_batch_workspace_size(len(to) - 1, to.ctypes.data_as(_P), so.ctypes.data_as(_P), parr, shared))
+
+
+def _param_array(params, n_pairs):
+    if isinstance(params, gcvo_params):
+        return 1, ctypes.pointer(params)
+    arr = (gcvo_params * n_pairs)(*params)
+    return 0, ctypes.cast(arr, ctypes.POINTER(gcvo_params))
+
+
+def gcvo_register_batch(targets, tgt_off, sources, src_off, T_init=None, params=None, ws=None, stream=None):
+    """Register len(tgt_off) - 1 pairs held in two concatenated clouds.
+
+    targets / sources: float32 CUDA [sum, 3]; tgt_off / src_off: int64 host
+    offsets.  Returns (T [n_pairs, 4, 4], list of info dicts).
+    """
+    L = load_library()
+    targets = _cloud(targets, "targets")
+    sources = _cloud(sources, "sources")
+    to = np.ascontiguousarray(tgt_off, dtype=np.int64)
+    so = np.ascontiguousarray(src_off, dtype=np.int64)
+    n_pairs = len(to) - 1
+    p = params if params is not None else default_params()
+    shared, parr = _param_array(p, n_pairs)
+    T0 = None if T_init is None else np.ascontiguousarray(np.asarray(T_init, np.float64).reshape(n_pairs, 16))
+    need = L.gcvo_batch_workspace_size(n_pairs, to.ctypes.data_as(_P), so.ctypes.data_as(_P), parr, shared)
+    if ws is None:
+        holder, wptr, wbytes = workspace(max(need, 256), targets.device)
+    else:
+        holder, wptr, wbytes = ws
+    T_out = np.zeros((n_pairs, 4, 4))
+    infos = (gcvo_info * n_pairs)()
+    st = L.gcvo_register_batch(n_pairs, _ptr(targets), to.ctypes.data_as(_P), _ptr(sources), so.ctypes.data_as(_P),
+                               T0.ctypes.data_as(_P) if T0 is not None else None, parr, shared,
+                               T_out.ctypes.data_as(_P), infos, ctypes.c_void_p(wptr), wbytes, _stream_handle(stream))
+    del holder
+    if st != GCVO_OK:
+        raise GcvoError(st, "gcvo_register_batch")
+    return T_out, [i.to_dict() for i in infos]
+
+
+@dataclass
+class EvalResult:
+    f: float
+    g: np.ndarray
+    H: np.ndarray
+    npairs: int
+
+
+def gcvo_eval_fgh(target, tgt_shape6, source, src_shape6, T, length_scale: float, cutoff: float,
+                  sigma2: float = 1.0, precision: int = GCVO_PRECISION_FP32, ws=None, stream=None) -> EvalResult:
+    L = load_library()
+    target = _cloud(target, "target")
+    source = _cloud(source, "source")
+    nt, ns = target.shape[0], source.shape[0]
+    ts = _shape6(tgt_shape6, nt, "tgt_shape6")
+    ss = _shape6(src_shape6, ns, "src_shape6")
+    Tm = _pose(T)
+    need = L.gcvo_eval_workspace_size(nt, ns)
+    if ws is None:
+        holder, wptr, wbytes = workspace(max(need, 256), target.device)
+    else:
+        holder, wptr, wbytes = ws
+    f = ctypes.c_double()
+    g = np.zeros(6)
+    H = np.zeros((6, 6))
+    npairs = ctypes.c_longlong()
+    st = L.gcvo_eval_fgh(_ptr(target), _ptr(ts), nt, _ptr(source), _ptr(ss), ns, Tm.ctypes.data_as(_P),
+                         float(length_scale), float(cutoff), float(sigma2), int(precision), ctypes.byref(f),
+                         g.ctypes.data_as(_P), H.ctypes.data_as(_P), ctypes.byref(npairs), ctypes.c_void_p(wptr),
+                         wbytes, _stream_handle(stream))
+    del holder
+    if st != GCVO_OK:
+        raise GcvoError(st, "gcvo_eval_fgh")
+    return EvalResult(f.value, g, H, npairs.value)
+
+
+def gcvo_point_shapes(xyz, knn: int = 10, rho: float = 0.01, ws=None, stream=None):
+    """Per-point shapes, float32 CUDA [6, n] (enqueued on the stream)."""
+    torch = _torch()
+    L = load_library()
+    xyz = _cloud(xyz, "xyz")
+    n = xyz.shape[0]
+    out = torch.empty((6, n), dtype=torch.float32, device=xyz.device)
+    need = L.gcvo_shapes_workspace_size(n)
+    if ws is None:
+        holder, wptr, wbytes = workspace(max(need, 256), xyz.device)
+    else:
+        holder, wptr, wbytes = ws
+    st = L.gcvo_point_shapes(_ptr(xyz), n, int(knn), float(rho), _ptr(out), ctypes.c_void_p(wptr), wbytes,
+                             _stream_handle(stream))
+    if st != GCVO_OK:
+        raise GcvoError(st, "gcvo_point_shapes")
+    # keep the workspace alive until the kernels have run
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    del holder
+    return out
+
+
+def gcvo_profile_enable(on: bool = True) -> None:
+    load_library().gcvo_profile_enable(int(bool(on)))
+
+
+def gcvo_profile_reset() -> None:
+    load_library().gcvo_profile_reset()
+
+
+def gcvo_profile_read() -> dict:
+    ms = ctypes.c_double()
+    launches, pairs, points = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_longlong()
+    load_library().gcvo_profile_read(ctypes.byref(ms), ctypes.byref(launches), ctypes.byref(pairs),
+                                     ctypes.byref(points))
+    return dict(pair_kernel_ms=ms.value, launches=launches.value, pairs=pairs.value, source_points=points.value)

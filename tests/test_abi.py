@@ -1,0 +1,90 @@
+"""Host-only checks of the C ABI: the library loads, exports every declared
+symbol, and its host-side sizing/validation functions behave (no GPU calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2606_10019_amd import gcvo
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "gcvo.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gcvo_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = gcvo.load_library()
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(names) == sorted(gcvo.EXPORTED)
+
+
+def test_struct_layouts_match_header():
+    # sizes implied by the header's field order on x86-64
+    assert ctypes.sizeof(gcvo.gcvo_params) == 8 * 4 + 8 + 8 * 2 + 8 + 8 * 2 + 8
+    assert ctypes.sizeof(gcvo.gcvo_info) == 4 * 4 + 8 + 8 + 48 + 8 + 4 * 16
+    assert gcvo.load_library().gcvo_abi_version() == 100
+
+
+def test_default_params_and_strerror():
+    p = gcvo.default_params()
+    assert p.length_scale == 0.3 and p.knn == 10 and p.cutoff_scale == 3.0 and p.max_iters == 30
+    for code in range(-7, 1):
+        assert gcvo.strerror(code)
+    assert "unknown" in gcvo.strerror(-99)
+
+
+def test_workspace_size_validation():
+    p = gcvo.default_params()
+    a = gcvo.gcvo_workspace_size(2000, 2000, p)
+    b = gcvo.gcvo_workspace_size(20000, 20000, p)
+    assert 0 < a < b
+    assert gcvo.gcvo_workspace_size(0, 10, p) == 0
+    bad = gcvo.default_params(knn=1)
+    assert gcvo.gcvo_workspace_size(100, 100, bad) == 0
+    bad = gcvo.default_params(length_scale_min=0.5)   # min above start
+    assert gcvo.gcvo_workspace_size(100, 100, bad) == 0
+    bad = gcvo.default_params(length_scale=1.0, length_scale_min=0.1, anneal_factor=1.0)
+    assert gcvo.gcvo_workspace_size(100, 100, bad) == 0
+    # annealing 1.0 -> 0.1 by halves: 5 stages need more space than one stage
+    ann = gcvo.default_params(length_scale=1.0, length_scale_min=0.1, anneal_factor=0.5)
+    assert gcvo.gcvo_workspace_size(2000, 2000, ann) > gcvo.gcvo_workspace_size(2000, 2000, gcvo.default_params(
+        length_scale=1.0, length_scale_min=1.0))
+    assert gcvo.load_library().gcvo_eval_workspace_size(100, 100) > 0
+    assert gcvo.load_library().gcvo_shapes_workspace_size(100) > 0
+    assert gcvo.load_library().gcvo_shapes_workspace_size(0) == 0
+
+
+def test_batch_workspace_covers_members():
+    import numpy as np
+    p = gcvo.default_params()
+    off = np.array([0, 1000, 3000, 3500], dtype=np.int64)
+    whole = gcvo.gcvo_batch_workspace_size(off, off, p)
+    assert whole > gcvo.gcvo_workspace_size(2000, 2000, p)
+
+
+def test_register_rejects_bad_arguments_without_gpu_work():
+    L = gcvo.load_library()
+    p = gcvo.default_params()
+    T = (ctypes.c_double * 16)()
+    info = gcvo.gcvo_info()
+    # null clouds
+    st = L.gcvo_register(None, 100, None, 100, None, ctypes.byref(p), T, ctypes.byref(info), None, 0, None)
+    assert st == gcvo.GCVO_ERR_INVALID and info.status == st
+    # a non-rigid initial pose is rejected before anything is enqueued
+    bad = (ctypes.c_double * 16)(*([2.0, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1]))
+    st = L.gcvo_register(ctypes.c_void_p(16), 100, ctypes.c_void_p(16), 100, bad, ctypes.byref(p), T,
+                         ctypes.byref(info), None, 0, None)
+    assert st == gcvo.GCVO_ERR_INVALID
+    # too few points for knn
+    st = L.gcvo_register(ctypes.c_void_p(16), 5, ctypes.c_void_p(16), 100, None, ctypes.byref(p), T,
+                         ctypes.byref(info), None, 0, None)
+    assert st == gcvo.GCVO_ERR_TOO_FEW_POINTS
+    assert all(v == 0.0 for v in T)   # pose output untouched

@@ -1,0 +1,188 @@
+"""GPU path vs the FP64 CPU oracle, through the C ABI (run on an MI355X).
+
+Inputs are the seeded synthetic pairs of ``paper_2606_10019_amd.synth``; expected
+poses come from ``tests/golden/oracle_poses.json`` (written by the oracle only)
+or from live oracle calls on the same float32 inputs.
+
+Tolerances.  Poses: the accuracy gate of the project, 1e-3 deg rotation and
+1e-5 m translation against the oracle's fixed point.  Single evaluations (f, g,
+H at a fixed pose with the oracle's shapes rounded to float32 on both sides):
+the GPU sums FP32 pair terms whose relative error is bounded by about
+kappa * eps32 with kappa <= 1/rho the condition number of the pair covariance,
+then block and compensated cross-block sums; 64 * eps32 / rho per unit of the
+quantity's natural scale (f, f/ell for g, max|H| for H) bounds that with margin.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from paper_2606_10019_amd import gcvo, synth  # noqa: E402
+from tests.posemetrics import rot_err_deg, trans_err_m  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_poses.json")))
+EPS32 = float(np.finfo(np.float32).eps)
+ROT_GATE_DEG, TRANS_GATE_M = 1e-3, 1e-5
+
+
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev())
+
+
+def note(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    spec = synth.make_config1(0)
+    SX = O.point_shapes(spec.target, 10, spec.eig_ratio_min)
+    SZ = O.point_shapes(spec.source, 10, spec.eig_ratio_min)
+    return spec, SX, SZ
+
+
+def test_point_shapes_match_oracle(c1):
+    spec, SX, _ = c1
+    note("point_shapes config1 target")
+    S = gcvo.gcvo_point_shapes(to_dev(spec.target), 10, spec.eig_ratio_min).cpu().numpy()
+    np.testing.assert_allclose(S.T, SX, atol=1e-6)
+
+
+def test_point_shapes_ragged_and_duplicates():
+    rng = np.random.default_rng(3)
+    P = rng.normal(size=(1037, 3)).astype(np.float32)
+    P[500:520] = P[499]                       # a cluster of exact duplicates (ties, zero covariance)
+    note("point_shapes ragged 1037 with duplicates")
+    S = gcvo.gcvo_point_shapes(to_dev(P), 12, 0.05).cpu().numpy()
+    ref = O.point_shapes(P.astype(np.float64), 12, 0.05)
+    np.testing.assert_allclose(S.T, ref, atol=1e-6)
+
+
+def _eval_both(spec, SX, SZ, T, ell, precision):
+    SXf, SZf = SX.astype(np.float32), SZ.astype(np.float32)
+    g = gcvo.gcvo_eval_fgh(to_dev(spec.target), to_dev(SXf.T), to_dev(spec.source), to_dev(SZf.T), T, ell,
+                           3 * ell, 1.0, precision)
+    o = O.evaluate(spec.target.astype(np.float64), SXf.astype(np.float64), spec.source.astype(np.float64),
+                   SZf.astype(np.float64), T, ell, 3 * ell)
+    return g, o
+
+
+@pytest.mark.parametrize("which", ["identity", "golden"])
+def test_eval_fgh_fp32_matches_oracle(c1, which):
+    spec, SX, SZ = c1
+    T = np.eye(4) if which == "identity" else np.array(GOLDEN[spec.name]["T_ref"]).reshape(4, 4)
+    note(f"eval_fgh fp32 config1 T={which}")
+    g, o = _eval_both(spec, SX, SZ, T, 0.3, gcvo.GCVO_PRECISION_FP32)
+    tol = 64 * EPS32 / spec.eig_ratio_min
+    note(f"f {g.f:.9g} vs {o.f:.9g}; pairs {g.npairs} vs {o.npairs}; "
+         f"|dg|/(f/ell) {np.max(np.abs(g.g - o.g)) / (o.f / 0.3):.2e}; "
+         f"|dH|/max|H| {np.max(np.abs(g.H - o.H_gn)) / np.max(np.abs(o.H_gn)):.2e}; tol {tol:.2e}")
+    assert abs(g.npairs - o.npairs) <= 2
+    assert abs(g.f - o.f) <= tol * o.f
+    assert np.max(np.abs(g.g - o.g)) <= tol * o.f / 0.3
+    assert np.max(np.abs(g.H - o.H_gn)) <= tol * np.max(np.abs(o.H_gn))
+
+
+def test_eval_fgh_fp64_matches_oracle_tightly(c1):
+    spec, SX, SZ = c1
+    T = np.array(GOLDEN[spec.name]["T_ref"]).reshape(4, 4)
+    note("eval_fgh fp64 config1")
+    g, o = _eval_both(spec, SX, SZ, T, 0.3, gcvo.GCVO_PRECISION_FP64)
+    assert g.npairs == o.npairs
+    assert abs(g.f - o.f) <= 1e-11 * o.f
+    assert np.max(np.abs(g.g - o.g)) <= 1e-11 * o.f / 0.3
+    assert np.max(np.abs(g.H - o.H_gn)) <= 1e-11 * np.max(np.abs(o.H_gn))
+
+
+def test_eval_fgh_empty_and_far():
+    note("eval_fgh empty / far apart")
+    P = to_dev(np.random.default_rng(1).normal(size=(50, 3)))
+    S = to_dev(np.tile([1.0, 0, 0, 1.0, 0, 1.0], (50, 1)).T)
+    e = gcvo.gcvo_eval_fgh(P[:0], S[:, :0], P, S, np.eye(4), 0.3, 0.9)
+    assert e.f == 0.0 and e.npairs == 0
+    far = np.eye(4)
+    far[0, 3] = 100.0
+    e = gcvo.gcvo_eval_fgh(P, S, P, S, far, 0.3, 0.9)
+    assert e.f == 0.0 and e.npairs == 0 and np.all(e.g == 0)
+
+
+@pytest.mark.parametrize("inst", [0, 1, 2, 3])
+def test_register_config1_matches_oracle(inst):
+    spec = synth.make_config1(inst)
+    ref = GOLDEN[spec.name]
+    assert spec.digest() == ref["digest"]
+    note(f"register config1 instance {inst}")
+    T, info = gcvo.gcvo_register(to_dev(spec.target), to_dev(spec.source), None, gcvo.params_from_spec(spec))
+    Tref = np.array(ref["T_ref"]).reshape(4, 4)
+    dr, dt = rot_err_deg(T, Tref), trans_err_m(T, Tref)
+    note(f"  iters {info['iters']} (oracle {ref['prod_iters']}) converged {info['converged']} "
+         f"err {dr:.2e} deg {dt:.2e} m")
+    assert info["converged"]
+    assert dr < ROT_GATE_DEG and dt < TRANS_GATE_M
+
+
+def test_register_config2_full_size_matches_oracle():
+    spec = synth.make_config2(0)
+    ref = GOLDEN[spec.name]
+    assert spec.digest() == ref["digest"]
+    note(f"register config2 instance 0 ({len(spec.target)} / {len(spec.source)} points)")
+    T, info = gcvo.gcvo_register(to_dev(spec.target), to_dev(spec.source), None, gcvo.params_from_spec(spec))
+    Tref = np.array(ref["T_ref"]).reshape(4, 4)
+    dr, dt = rot_err_deg(T, Tref), trans_err_m(T, Tref)
+    note(f"  iters {info['iters']} stages {info['stage_iters']} (oracle {ref['prod_stage_iters']}) "
+         f"err {dr:.2e} deg {dt:.2e} m")
+    assert info["converged"]
+    assert dr < ROT_GATE_DEG and dt < TRANS_GATE_M
+
+
+def test_register_is_bitwise_deterministic():
+    spec = synth.make_config1(2)
+    note("register determinism")
+    a, ia = gcvo.gcvo_register(to_dev(spec.target), to_dev(spec.source), None, gcvo.params_from_spec(spec))
+    b, ib = gcvo.gcvo_register(to_dev(spec.target), to_dev(spec.source), None, gcvo.params_from_spec(spec))
+    assert np.array_equal(a, b) and ia == ib
+
+
+def test_register_errors_leave_pose_untouched():
+    spec = synth.make_config1(0, n=300)
+    tgt, src = to_dev(spec.target), to_dev(spec.source)
+    note("register errors")
+    far = to_dev(spec.source + np.float32(100.0))
+    with pytest.raises(gcvo.GcvoError) as e:
+        gcvo.gcvo_register(tgt, far, None, gcvo.params_from_spec(spec))
+    assert e.value.status == gcvo.GCVO_ERR_NO_PAIRS
+    bad = spec.source.copy()
+    bad[7, 1] = np.nan
+    with pytest.raises(gcvo.GcvoError) as e:
+        gcvo.gcvo_register(tgt, to_dev(bad), None, gcvo.params_from_spec(spec))
+    assert e.value.status == gcvo.GCVO_ERR_INVALID
+    with pytest.raises(gcvo.GcvoError) as e:
+        gcvo.gcvo_register(tgt, src, None, gcvo.params_from_spec(spec), ws=gcvo.workspace(1024))
+    assert e.value.status == gcvo.GCVO_ERR_WORKSPACE
+
+
+def test_register_batch_matches_single_pairs():
+    specs = [synth.make_config1(i) for i in range(4)]
+    specs[2] = synth.make_config1(2, n=1500)    # uneven sizes
+    note("register_batch 4 config1 pairs")
+    tgt = np.concatenate([s.target for s in specs])
+    src = np.concatenate([s.source for s in specs])
+    to = np.cumsum([0] + [len(s.target) for s in specs])
+    so = np.cumsum([0] + [len(s.source) for s in specs])
+    T, infos = gcvo.gcvo_register_batch(to_dev(tgt), to, to_dev(src), so, None, gcvo.params_from_spec(specs[0]))
+    for k, s in enumerate(specs):
+        Ts, _ = gcvo.gcvo_register(to_dev(s.target), to_dev(s.source), None, gcvo.params_from_spec(s))
+        assert infos[k]["converged"]
+        assert np.array_equal(T[k], Ts), k
