@@ -104,7 +104,7 @@ struct Plan {
     int *d_active = nullptr;
     char *desc_begin = nullptr;
     size_t desc_bytes = 0;
-    int max_n = 0, max_job_n = 0;
+    int max_n = 0, max_job_n = 0, max_cells = 0;
 };
 
 // Lays out (base == nullptr: sizes) every device array of a batch.
@@ -118,7 +118,7 @@ void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &p
     for (int k = 0; k < np; ++k) {
         if (mode == Mode::Register) {
             nst[k] = stage_schedule(in[k].p, &ells[(size_t)k * kMaxStages]);
-            n_jobs += 2 + nst[k];
+            n_jobs += 3 + nst[k];
         } else if (mode == Mode::Eval) {
             nst[k] = 1;
             ells[(size_t)k * kMaxStages] = in[k].eval_ell;
@@ -127,7 +127,7 @@ void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &p
             nst[k] = 0;
             n_jobs += 1;
         }
-        if (mode != Mode::Shapes) n_tasks += (int)((in[k].n_s + kBlock - 1) / kBlock);
+        if (mode != Mode::Shapes) n_tasks += (int)((in[k].n_s + kPointsPerBlock - 1) / kPointsPerBlock);
     }
     pl.d_pairs = A.take<PairDev>(np);
     pl.desc_begin = reinterpret_cast<char *>(pl.d_pairs);
@@ -179,7 +179,7 @@ void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &p
         if (mode != Mode::Shapes) P.s_sorted = A.take<float>(kSortedRows * (size_t)ns);
         P.st = A.take<State>(1);
         P.iter_pairs = A.take<long long>((size_t)std::max(I.p.max_iters, 1));
-        P.n_blocks = (ns + kBlock - 1) / kBlock;
+        P.n_blocks = (ns + kPointsPerBlock - 1) / kPointsPerBlock;
         P.first_block = task;
         P.partials = A.take<float>((size_t)std::max(P.n_blocks, 1) * kPartialStride * 2);
         auto make_job = [&](int kind, int n, const float *x, int max_cells) {
@@ -194,13 +194,18 @@ void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &p
             J.keys_tmp = A.take<uint32_t>(n);
             J.idx = A.take<uint32_t>(n);
             J.idx_tmp = A.take<uint32_t>(n);
-            J.cell_start = A.take<int>((size_t)max_cells + 1);
+            J.cell_start = max_cells > 0 ? A.take<int>((size_t)max_cells + 1) : nullptr;
+            J.tile_counts = A.take<unsigned>(256 * (size_t)std::max(1, (n + 1023) / 1024));
             J.pair = k;
             J.kind = kind;
             pl.max_job_n = std::max(pl.max_job_n, n);
+            pl.max_cells = std::max(pl.max_cells, max_cells);
             return J;
         };
-        const int knn_cells_t = 4 * nt + 64, knn_cells_s = 4 * ns + 64, stage_cells = 16 * nt + 64;
+        // cell tables: at most 16 cells per point (keys stay below 2^30, the radix sort's 4 passes)
+        const int knn_cells_t = (int)std::min<long long>(16LL * nt + 64, (1 << 30) - 1);
+        const int knn_cells_s = (int)std::min<long long>(16LL * ns + 64, (1 << 30) - 1);
+        const int stage_cells = knn_cells_t;
         if (mode == Mode::Register || mode == Mode::Shapes) {
             SortJob J = make_job(kJobKnnTarget, nt, P.t_orig, knn_cells_t);
             J.want_shapes = 1;
@@ -209,11 +214,18 @@ void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &p
             if (base) pl.jobs[job] = J;
             ++job;
         }
-        if (mode != Mode::Shapes) {
+        if (mode == Mode::Register) {
             SortJob J = make_job(kJobKnnSource, ns, P.s_orig, knn_cells_s);
-            J.want_shapes = (mode == Mode::Register) ? 1 : 0;
+            J.want_shapes = 1;
             J.shape_out = P.s_shape;
             P.job_knn_s = pl.d_jobs + job;
+            if (base) pl.jobs[job] = J;
+            ++job;
+        }
+        if (mode != Mode::Shapes) {
+            SortJob J = make_job(kJobOrderSource, ns, P.s_orig, 0);
+            J.morton = 1;
+            P.job_order_s = pl.d_jobs + job;
             if (base) pl.jobs[job] = J;
             ++job;
             P.job_stage0 = pl.d_jobs + job;
@@ -284,7 +296,8 @@ int upload_and_prepare(Plan &pl, int knn, hipStream_t s) {
                 pl.tasks.size() * sizeof(BlockTask));
     HIP_OK(hipMemcpyAsync(d0, blob.data(), pl.desc_bytes, hipMemcpyHostToDevice, s));
     const int n_jobs = (int)pl.jobs.size();
-    HIP_OK(launch_prepare(pl.d_pairs, (int)pl.pairs.size(), pl.max_n, pl.d_jobs, n_jobs, pl.max_job_n, knn, s));
+    HIP_OK(launch_prepare(pl.d_pairs, (int)pl.pairs.size(), pl.max_n, pl.d_jobs, n_jobs, pl.max_job_n, pl.max_cells,
+                          knn, s));
     return GCVO_OK;
 }
 
@@ -337,22 +350,22 @@ int run_iterations(Plan &pl, int max_iters, int precision, hipStream_t s) {
     const int np = (int)pl.pairs.size();
     int launched = 0, slot = 0, rc = GCVO_OK;
     bool pending[2] = {false, false};
+    if (launch_count_active(pl.d_pairs, np, pl.d_active, s) != hipSuccess) rc = GCVO_ERR_HIP;
     auto enqueue = [&](int c) -> hipError_t {
-        if (!g_prof.on) return launch_iterations(pl.d_pairs, pl.d_tasks, n_tasks, c, precision, s);
+        if (!g_prof.on) return launch_iterations(pl.d_pairs, np, pl.d_tasks, n_tasks, c, precision, pl.d_active, s);
         for (int i = 0; i < c; ++i) {
             hipEvent_t a = prof_event(2 * (size_t)(launched + i)), b = prof_event(2 * (size_t)(launched + i) + 1);
             if (!a || !b) return hipErrorOutOfMemory;
             hipError_t e = hipEventRecord(a, s);
-            if (e == hipSuccess) e = launch_iterations(pl.d_pairs, pl.d_tasks, n_tasks, 1, precision, s);
+            if (e == hipSuccess) e = launch_iterations(pl.d_pairs, np, pl.d_tasks, n_tasks, 1, precision, pl.d_active, s);
             if (e == hipSuccess) e = hipEventRecord(b, s);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
     };
-    while (launched < max_iters) {
+    while (rc == GCVO_OK && launched < max_iters) {
         const int c = std::min(kChunk, max_iters - launched);
         if (enqueue(c) != hipSuccess ||
-            launch_count_active(pl.d_pairs, np, pl.d_active, s) != hipSuccess ||
             hipMemcpyAsync(&flags[slot], pl.d_active, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipEventRecord(ev[slot], s) != hipSuccess) {
             rc = GCVO_ERR_HIP;
@@ -623,7 +636,8 @@ int gcvo_eval_fgh(const float *tgt_xyz, const float *tgt_shape6, long long n_tgt
     build_plan(workspace, Mode::Eval, in, pl);
     int rc = upload_and_prepare(pl, 0, s);
     if (rc) return rc;
-    HIP_OK(launch_iterations(pl.d_pairs, pl.d_tasks, (int)pl.tasks.size(), 1, precision, s));
+    HIP_OK(launch_count_active(pl.d_pairs, 1, pl.d_active, s));
+    HIP_OK(launch_iterations(pl.d_pairs, 1, pl.d_tasks, (int)pl.tasks.size(), 1, precision, pl.d_active, s));
     State st;
     HIP_OK(hipMemcpyAsync(&st, pl.pairs[0].st, sizeof st, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));

@@ -21,12 +21,18 @@ constexpr int kNumSums = 28;          // f, g (6), upper triangle of H_main (21)
 constexpr int kPartialStride = 32;    // floats per block partial: 28 sums + pair count + pad
 constexpr float kCellMargin = 1.001f; // pair-grid cell edge = margin * cutoff (see Grid)
 constexpr int kSortedRows = 12;      // rows of the sorted per-point arrays (see PairDev)
+constexpr int kGroupLanes = 16;      // pair kernel: lanes serving one source point
+constexpr int kGroupsPerWave = 64 / kGroupLanes;
+constexpr int kPointsPerBlock = (kBlock / 64) * kGroupsPerWave;   // source points per pair-kernel block
+constexpr int kMaxRows = 64;         // pair kernel: cell rows listed per batch and point
+constexpr int kReduceSplit = 8;      // blocks per pair of the cross-block reduction
+constexpr float kPairCellFraction = 0.5f;   // pair-grid cell edge as a fraction of the cutoff
 
 // Uniform grid over an axis-aligned box.  Cell of a point p along axis d is
 // clamp(floor((p_d - lo_d) * inv_h), 0, n_d - 1); cells are numbered x-fastest.
-// For the pair grid the edge h is at least 1.001 * cutoff, so two points within
-// the cutoff always fall in cells whose indices differ by at most one per axis
-// even after FP32 rounding of the cell computation.
+// The pair grid's edge is half the cutoff (grown when the box would need more
+// cells than the workspace holds); the pair kernel finds candidates with a ball
+// of radius 1.001 * cutoff, which absorbs FP32 rounding of cell coordinates.
 struct Grid {
     float lo[3];
     float h;
@@ -48,16 +54,18 @@ struct SortJob {
     Grid *grid;               // written by the setup kernel
     uint32_t *keys, *keys_tmp, *idx, *idx_tmp;   // idx: sorted position -> point index
     int *cell_start;
+    unsigned *tile_counts;    // radix sort scratch: [256][ceil(n / 1024)] digit counts, then offsets
     int pair;                 // owning pair
     int kind;                 // kJobKnnTarget, kJobKnnSource or kJobStage + stage
     int want_shapes;          // kNN jobs: 1 = compute shapes into shape_out
-    int pad;
+    int morton;               // 1: key = 30-bit Morton code of the 1024^3 grid cell (no cell table)
     float *shape_out;         // SoA [6][n], original point order
 };
 
-constexpr int kJobKnnTarget = 0;
-constexpr int kJobKnnSource = 1;
-constexpr int kJobStage = 2;
+constexpr int kJobKnnTarget = 0;    // grid for the target's kNN shapes
+constexpr int kJobKnnSource = 1;    // grid for the source's kNN shapes
+constexpr int kJobOrderSource = 2;  // Morton order of the source (pair-kernel point order)
+constexpr int kJobStage = 3;        // kJobStage + s: pair grid of stage s over the target
 
 // Per-pair solver state, FP64, owned by the device for the whole solve.
 struct State {
@@ -68,8 +76,9 @@ struct State {
     long long pairs_last;
     int iter, stage, stage_iter, done, status, converged, damped;
     int stage_iters[kMaxStages];
-    unsigned int counter;  // blocks of the current iteration that finished
-    int pad;
+    double sub[kReduceSplit][32];     // cross-block sums of the current iteration, by reduction block
+    unsigned long long sub_pairs[kReduceSplit];
+    int pad[2];
 };
 
 // Everything one registration problem needs on the device.
@@ -93,18 +102,20 @@ struct PairDev {
     float *t_orig, *s_orig;           // SoA [3][n] original coordinates (kNN grids)
     float *t_rec, *s_rec;             // SoA [3][n] recentred coordinates
     float *t_shape, *s_shape;         // SoA [6][n] shapes, original point order
-    // Sorted SoA arrays [kSortedRows][n]: rows 0-2 recentred xyz (float32),
-    // rows 3-8 shape, rows 9-11 original xyz (read by the FP64 instantiation,
-    // which recentres exactly in FP64).
-    float *s_sorted;                  // source, in its own grid order
+    // Sorted per-point arrays of kSortedRows floats per point: recentred xyz
+    // (float32), the 6 shape entries, original xyz (read by the FP64
+    // instantiation, which recentres exactly in FP64).  The source is stored as
+    // structure of arrays [12][n]; the target as 48-byte records
+    // {x, y, z, s00 | s01, s02, s11, s12 | s22, x0, y0, z0} (three float4).
+    float *s_sorted;                  // source, in Morton order
     float *t_sorted[kMaxStages];      // target, in each stage grid's order
     int *t_cells[kMaxStages];         // cell_start of each stage grid
     Grid *t_grid[kMaxStages];
-    SortJob *job_knn_t, *job_knn_s, *job_stage0;   // job_stage0[s] for s < n_stages
+    SortJob *job_knn_t, *job_knn_s, *job_order_s, *job_stage0;   // job_stage0[s] for s < n_stages
     State *st;
     long long *iter_pairs;            // [max_iters] pairs within the cutoff at each iteration
-    float *partials;                  // [n_blocks][kPartialStride]
-    int n_blocks;                     // 256-point blocks of the source cloud
+    float *partials;                  // [n_blocks][kPartialStride] block sums (pair-term precision)
+    int n_blocks;                     // pair-kernel blocks (kPointsPerBlock source points each)
     int first_block;                  // index of the pair's first BlockTask
     int shapes_given;                 // 1: t_shape / s_shape are caller memory (eval path)
     int eval_only;                    // 1: stop after one evaluation, no step
@@ -144,10 +155,12 @@ __device__ __forceinline__ float wave_max(float v) {
 // copies, cell keys, radix sorts, kNN shapes and the sorted per-stage arrays.
 // knn selects the kNN kernel instantiation (0: no shapes are computed).
 hipError_t launch_prepare(PairDev *pairs_dev, int n_pairs, int max_n, SortJob *jobs_dev, int n_jobs,
-                          int max_job_n, int knn, hipStream_t s);
+                          int max_job_n, int max_cells, int knn, hipStream_t s);
 // Enqueue n_iters Gauss-Newton iterations (each a no-op for pairs already done).
-hipError_t launch_iterations(PairDev *pairs_dev, BlockTask *tasks_dev, int n_tasks, int n_iters,
-                             int precision, hipStream_t s);
+// `active` (device int) must hold the number of pairs not yet done; pairs that
+// finish decrement it.
+hipError_t launch_iterations(PairDev *pairs_dev, int n_pairs, BlockTask *tasks_dev, int n_tasks, int n_iters,
+                             int precision, int *active, hipStream_t s);
 // Count pairs not yet done into *active (device int).
 hipError_t launch_count_active(PairDev *pairs_dev, int n_pairs, int *active, hipStream_t s);
 

@@ -41,46 +41,61 @@ struct Fast<double> {
 };
 
 // ------------------------------------------------------------------ FP64 step
+//
+// All 6x6 algebra below is fully unrolled with compile-time indices so that it
+// stays in registers (one lane per pair runs it).
 
-// Solve A x = b (6x6) by elimination with partial pivoting; false when a pivot
-// is below tiny * max|A|.
-__device__ __noinline__ bool lu_solve6(const double Ain[36], const double b[6], double x[6], double tiny) {
-    double A[6][6], y[6];
-    int perm[6];
+// Solve A x = b (6x6) by Gaussian elimination with partial pivoting (rows of A
+// and b swapped in place); false when a pivot is below tiny * max|A|.
+__device__ __forceinline__ bool solve6(double A[6][6], double b[6], double x[6], double tiny) {
     double amax = 0.0;
-    for (int r = 0; r < 6; ++r) {
-        perm[r] = r;
-        for (int c = 0; c < 6; ++c) {
-            A[r][c] = Ain[r * 6 + c];
-            amax = fmax(amax, fabs(A[r][c]));
-        }
-    }
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) amax = fmax(amax, fabs(A[r][c]));
     if (!(amax > 0.0) || !isfinite(amax)) return false;
+#pragma unroll
     for (int k = 0; k < 6; ++k) {
         int p = k;
-        for (int r = k + 1; r < 6; ++r)
-            if (fabs(A[r][k]) > fabs(A[p][k])) p = r;
-        if (!(fabs(A[p][k]) >= tiny * amax)) return false;
-        if (p != k) {
-            for (int c = 0; c < 6; ++c) {
-                double t = A[k][c]; A[k][c] = A[p][c]; A[p][c] = t;
-            }
-            int t = perm[k]; perm[k] = perm[p]; perm[p] = t;
-        }
+        double best = fabs(A[k][k]);
+#pragma unroll
         for (int r = k + 1; r < 6; ++r) {
-            A[r][k] /= A[k][k];
-            for (int c = k + 1; c < 6; ++c) A[r][c] -= A[r][k] * A[k][c];
+            const double v = fabs(A[r][k]);
+            if (v > best) {
+                best = v;
+                p = r;
+            }
+        }
+        if (!(best >= tiny * amax)) return false;
+#pragma unroll
+        for (int r = k + 1; r < 6; ++r) {
+            if (r == p) {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    const double t = A[k][c];
+                    A[k][c] = A[r][c];
+                    A[r][c] = t;
+                }
+                const double t = b[k];
+                b[k] = b[r];
+                b[r] = t;
+            }
+        }
+        const double inv = 1.0 / A[k][k];
+#pragma unroll
+        for (int r = k + 1; r < 6; ++r) {
+            const double f = A[r][k] * inv;
+#pragma unroll
+            for (int c = k + 1; c < 6; ++c) A[r][c] -= f * A[k][c];
+            b[r] -= f * b[k];
         }
     }
-    for (int r = 0; r < 6; ++r) {   // forward substitution with the unit-lower factor
-        double s = b[perm[r]];
-        for (int c = 0; c < r; ++c) s -= A[r][c] * y[c];
-        y[r] = s;
-    }
+#pragma unroll
     for (int r = 5; r >= 0; --r) {
-        double s = y[r];
-        for (int c = r + 1; c < 6; ++c) s -= A[r][c] * x[c];
-        x[r] = s / A[r][r];
+        double acc = b[r];
+#pragma unroll
+        for (int c = r + 1; c < 6; ++c) acc -= A[r][c] * x[c];
+        x[r] = acc / A[r][r];
     }
     return true;
 }
@@ -89,38 +104,36 @@ __device__ __noinline__ bool lu_solve6(const double Ain[36], const double b[6], 
 // plain H first; if singular or not an ascent direction, H_main shifted by
 // -lambda * ||diag H_main||_2 with lambda = 1e-6 * 10^m, m = 0..6.
 // Returns 0 (plain), m + 1 (damped) or -1 (failed).
-__device__ __noinline__ int damped_step(const double H[36], const double Hm[36], const double g[6], double xi[6]) {
+__device__ __forceinline__ int damped_step(const double H[6][6], const double Hm[6][6], const double g[6],
+                                           double xi[6]) {
     bool zero = true;
-    double mg[6];
-    for (int a = 0; a < 6; ++a) {
-        mg[a] = -g[a];
-        zero = zero && (g[a] == 0.0);
-    }
+#pragma unroll
+    for (int a = 0; a < 6; ++a) zero = zero && (g[a] == 0.0);
     if (zero) {
+#pragma unroll
         for (int a = 0; a < 6; ++a) xi[a] = 0.0;
         return 0;
     }
-    double x[6];
-    if (lu_solve6(H, mg, x, 1e-12)) {
-        double gx = 0.0;
-        for (int a = 0; a < 6; ++a) gx += g[a] * x[a];
-        if (gx > 0.0) {
-            for (int a = 0; a < 6; ++a) xi[a] = x[a];
-            return 0;
-        }
-    }
     double dn = 0.0;
-    for (int a = 0; a < 6; ++a) dn += Hm[7 * a] * Hm[7 * a];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) dn += Hm[a][a] * Hm[a][a];
     dn = sqrt(dn);
-    double lam = 1e-6;
-    for (int m = 0; m <= 6; ++m, lam *= 10.0) {
-        double Hd[36];
-        for (int e = 0; e < 36; ++e) Hd[e] = Hm[e];
-        for (int a = 0; a < 6; ++a) Hd[7 * a] -= lam * dn;
-        if (lu_solve6(Hd, mg, x, 1e-12)) {
+    for (int m = -1; m <= 6; ++m) {
+        double A[6][6], b[6], x[6];
+        const double shift = (m < 0) ? 0.0 : 1e-6 * exp10((double)m) * dn;
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) A[r][c] = (m < 0) ? H[r][c] : Hm[r][c];
+            A[r][r] -= shift;
+            b[r] = -g[r];
+        }
+        if (solve6(A, b, x, 1e-12)) {
             double gx = 0.0;
+#pragma unroll
             for (int a = 0; a < 6; ++a) gx += g[a] * x[a];
             if (gx > 0.0) {
+#pragma unroll
                 for (int a = 0; a < 6; ++a) xi[a] = x[a];
                 return m + 1;
             }
@@ -131,7 +144,7 @@ __device__ __noinline__ int damped_step(const double H[36], const double Hm[36],
 
 // exp of the twist (w, v): Rodrigues for the rotation, the left Jacobian V for
 // the translation; half-angle form for (1 - cos)/th^2, series for small angles.
-__device__ __noinline__ void twist_exp(const double xi[6], double E[16]) {
+__device__ __forceinline__ void twist_exp(const double xi[6], double E[4][4]) {
     const double wx = xi[0], wy = xi[1], wz = xi[2];
     const double th2 = wx * wx + wy * wy + wz * wz, th = sqrt(th2);
     double a, b, c;
@@ -150,20 +163,20 @@ __device__ __noinline__ void twist_exp(const double xi[6], double E[16]) {
     // W = w^, W^2 = w w^T - th2 I
     const double W[3][3] = {{0.0, -wz, wy}, {wz, 0.0, -wx}, {-wy, wx, 0.0}};
     const double w[3] = {wx, wy, wz};
-    double Rm[3][3], V[3][3];
+    double V[3][3];
+#pragma unroll
     for (int r = 0; r < 3; ++r)
+#pragma unroll
         for (int q = 0; q < 3; ++q) {
             const double W2 = w[r] * w[q] - (r == q ? th2 : 0.0);
             const double I = (r == q) ? 1.0 : 0.0;
-            Rm[r][q] = I + a * W[r][q] + b * W2;
+            E[r][q] = I + a * W[r][q] + b * W2;
             V[r][q] = I + b * W[r][q] + c * W2;
         }
-    for (int r = 0; r < 3; ++r) {
-        for (int q = 0; q < 3; ++q) E[4 * r + q] = Rm[r][q];
-        E[4 * r + 3] = V[r][0] * xi[3] + V[r][1] * xi[4] + V[r][2] * xi[5];
-    }
-    E[12] = E[13] = E[14] = 0.0;
-    E[15] = 1.0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) E[r][3] = V[r][0] * xi[3] + V[r][1] * xi[4] + V[r][2] * xi[5];
+    E[3][0] = E[3][1] = E[3][2] = 0.0;
+    E[3][3] = 1.0;
 }
 
 // ------------------------------------------------------------------ pair kernel
@@ -204,65 +217,84 @@ __device__ __forceinline__ void pair_term(PairSums<Real> &s, unsigned &cnt, Real
 // Upper-triangle index of (r, c), r <= c, in row-major order of a 6x6 matrix.
 __host__ __device__ constexpr int ut(int r, int c) { return r * 6 - (r * (r - 1)) / 2 + (c - r); }
 
-// Single-thread FP64 tail of an iteration: frame change of the summed terms,
-// connection term, damped solve, retraction, stage and stop logic.  Kept out of
-// line so that its registers do not limit the occupancy of the pair loop.
-__device__ __noinline__ void finish_iteration(PairDev &P, State &St, const double *tot,
-                                              unsigned long long tot_pairs, int stage) {
-    // Back to the caller's frame: with A = [[I, 0], [-c^, I]] (the adjoint of the
-    // recentring translation), g = A^T g', H_main = A^T H' A.
-    double gp[6], Hp[36];
-    for (int a = 0; a < 6; ++a) gp[a] = tot[1 + a];
-    for (int r = 0; r < 6; ++r)
-        for (int c = r; c < 6; ++c) Hp[6 * r + c] = Hp[6 * c + r] = tot[7 + ut(r, c)];
-    const double *cc = P.centre;
-    const double Ch[3][3] = {{0.0, -cc[2], cc[1]}, {cc[2], 0.0, -cc[0]}, {-cc[1], cc[0], 0.0}};
-    double A[36];
-    for (int e = 0; e < 36; ++e) A[e] = 0.0;
-    for (int a = 0; a < 6; ++a) A[7 * a] = 1.0;
+// FP64 tail of an iteration (one lane per pair): frame change of the summed
+// terms, connection term, damped solve, retraction, stage and stop logic.
+__device__ __forceinline__ void finish_iteration(PairDev &P, State &St, const double tot[kNumSums],
+                                                 unsigned long long tot_pairs, int stage) {
+    // Back to the caller's frame.  With K = -c^ and A = [[I, 0], [K, I]] (the
+    // adjoint of the recentring translation): g = A^T g', H_main = A^T H' A.
+    // In 3x3 blocks H' = [[P, Q], [Q^T, S]] this is
+    //   [[P + QK + (QK)^T + K^T S K,  Q + (SK)^T], [Q^T + SK,  S]].
+    const double cx = P.centre[0], cy = P.centre[1], cz = P.centre[2];
+    const double K[3][3] = {{0.0, cz, -cy}, {-cz, 0.0, cx}, {cy, -cx, 0.0}};
+    double Pm[3][3], Q[3][3], S[3][3];
+#pragma unroll
     for (int r = 0; r < 3; ++r)
-        for (int c = 0; c < 3; ++c) A[6 * (3 + r) + c] = -Ch[r][c];
-    double g[6], HA[36], Hm[36];
-    for (int a = 0; a < 6; ++a) {
-        double acc = 0.0;
-        for (int b = 0; b < 6; ++b) acc += A[6 * b + a] * gp[b];
-        g[a] = acc;
-    }
-    for (int r = 0; r < 6; ++r)
-        for (int c = 0; c < 6; ++c) {
-            double acc = 0.0;
-            for (int b = 0; b < 6; ++b) acc += Hp[6 * r + b] * A[6 * b + c];
-            HA[6 * r + c] = acc;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            Pm[r][c] = tot[7 + ut(r < c ? r : c, r < c ? c : r)];
+            Q[r][c] = tot[7 + ut(r, 3 + c)];
+            S[r][c] = tot[7 + ut(3 + (r < c ? r : c), 3 + (r < c ? c : r))];
         }
-    for (int r = 0; r < 6; ++r)
-        for (int c = 0; c < 6; ++c) {
-            double acc = 0.0;
-            for (int b = 0; b < 6; ++b) acc += A[6 * b + r] * HA[6 * b + c];
-            Hm[6 * r + c] = acc;
+    double QK[3][3], SK[3][3], KSK[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            QK[r][c] = Q[r][0] * K[0][c] + Q[r][1] * K[1][c] + Q[r][2] * K[2][c];
+            SK[r][c] = S[r][0] * K[0][c] + S[r][1] * K[1][c] + S[r][2] * K[2][c];
         }
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) KSK[r][c] = K[0][r] * SK[0][c] + K[1][r] * SK[1][c] + K[2][r] * SK[2][c];
     const double sig = P.sigma2;
-    const double f = sig * tot[0];
-    for (int a = 0; a < 6; ++a) g[a] *= sig;
-    for (int e = 0; e < 36; ++e) Hm[e] *= sig;
-    // H_GN = H_main + C(g), C(g) = [[-1/2 g_w^, 0], [-g_v^, 0]]
-    double H[36];
-    for (int e = 0; e < 36; ++e) H[e] = Hm[e];
+    double g[6], Hm[6][6];
     {
-        const double gw[3] = {g[0], g[1], g[2]}, gv[3] = {g[3], g[4], g[5]};
-        const double Gw[3][3] = {{0.0, -gw[2], gw[1]}, {gw[2], 0.0, -gw[0]}, {-gw[1], gw[0], 0.0}};
-        const double Gv[3][3] = {{0.0, -gv[2], gv[1]}, {gv[2], 0.0, -gv[0]}, {-gv[1], gv[0], 0.0}};
+        const double gw[3] = {tot[1], tot[2], tot[3]}, gv[3] = {tot[4], tot[5], tot[6]};
+        // g_w = g'_w + K^T g'_v, g_v = g'_v
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            g[r] = sig * (gw[r] + K[0][r] * gv[0] + K[1][r] * gv[1] + K[2][r] * gv[2]);
+            g[3 + r] = sig * gv[r];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            Hm[r][c] = sig * (Pm[r][c] + QK[r][c] + QK[c][r] + KSK[r][c]);
+            Hm[r][3 + c] = sig * (Q[r][c] + SK[c][r]);
+            Hm[3 + r][c] = sig * (Q[c][r] + SK[r][c]);
+            Hm[3 + r][3 + c] = sig * S[r][c];
+        }
+    const double f = sig * tot[0];
+    // H_GN = H_main + C(g), C(g) = [[-1/2 g_w^, 0], [-g_v^, 0]]
+    double H[6][6];
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) H[r][c] = Hm[r][c];
+    {
+        const double Gw[3][3] = {{0.0, -g[2], g[1]}, {g[2], 0.0, -g[0]}, {-g[1], g[0], 0.0}};
+        const double Gv[3][3] = {{0.0, -g[5], g[4]}, {g[5], 0.0, -g[3]}, {-g[4], g[3], 0.0}};
+#pragma unroll
         for (int r = 0; r < 3; ++r)
+#pragma unroll
             for (int c = 0; c < 3; ++c) {
-                H[6 * r + c] -= 0.5 * Gw[r][c];
-                H[6 * (3 + r) + c] -= Gv[r][c];
+                H[r][c] -= 0.5 * Gw[r][c];
+                H[3 + r][c] -= Gv[r][c];
             }
     }
     St.f = f;
+#pragma unroll
     for (int a = 0; a < 6; ++a) St.g[a] = g[a];
-    for (int e = 0; e < 36; ++e) St.H[e] = H[e];
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) St.H[6 * r + c] = H[r][c];
     St.pairs_last = (long long)tot_pairs;
     if (P.iter_pairs && St.iter < P.max_iters) P.iter_pairs[St.iter] = (long long)tot_pairs;
-    St.counter = 0;
     if (P.eval_only) {
         St.done = 1;
         return;
@@ -280,16 +312,23 @@ __device__ __noinline__ void finish_iteration(PairDev &P, State &St, const doubl
         return;
     }
     if (dmp > 0) ++St.damped;
-    double E[16], Tn[16];
-    twist_exp(xi, E);
+    double E[4][4], T[4][4];
+#pragma unroll
     for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) T[r][c] = St.T[4 * r + c];
+    twist_exp(xi, E);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
         for (int c = 0; c < 4; ++c) {
             double acc = 0.0;
-            for (int b = 0; b < 4; ++b) acc += St.T[4 * r + b] * E[4 * b + c];
-            Tn[4 * r + c] = acc;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc += T[r][b] * E[b][c];
+            St.T[4 * r + c] = acc;
         }
-    for (int e = 0; e < 16; ++e) St.T[e] = Tn[e];
     double l1 = 0.0;
+#pragma unroll
     for (int a = 0; a < 6; ++a) {
         St.xi[a] = xi[a];
         l1 += fabs(xi[a]);
@@ -311,37 +350,43 @@ __device__ __noinline__ void finish_iteration(PairDev &P, State &St, const doubl
     if (St.iter >= P.max_iters) St.done = 1;
 }
 
+// Lane layout of the pair kernel: a wave serves kGroupsPerWave neighbouring
+// source points (sorted order), kGroupLanes lanes each.  Every point lists the
+// contiguous x-rows of target cells that meet its cutoff ball; its lanes walk
+// that list with stride kGroupLanes through a (row, offset) cursor, so no lane
+// idles at row ends.  The 16 partial sums of a point are combined with xor
+// shuffles.
 template <typename Real>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_iterate(PairDev *pairs, const BlockTask *tasks) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_iterate(PairDev *pairs,
+                                                                                          const BlockTask *tasks) {
     const BlockTask task = tasks[blockIdx.x];
     PairDev &P = pairs[task.pair];
     State &St = *P.st;
     if (St.done) return;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int grp = lane / kGroupLanes, q = lane % kGroupLanes;
     const int stage = St.stage;
     const double ell = P.ell[stage];
     const Grid G = *P.t_grid[stage];
     const int *cells = P.t_cells[stage];
     const int nt = P.n_t, ns = P.n_s;
     constexpr bool kExact = sizeof(Real) == 8;   // FP64: recentre the original coordinates in FP64
-    const float *tx = P.t_sorted[stage], *ty = tx + nt, *tz = ty + nt;
-    const float *t0 = tz + nt, *t1 = t0 + nt, *t2 = t1 + nt, *t3 = t2 + nt, *t4 = t3 + nt, *t5 = t4 + nt;
-    const float *ox = t5 + nt, *oy = ox + nt, *oz = oy + nt;
+    const float4 *trec = reinterpret_cast<const float4 *>(P.t_sorted[stage]);
     const double c0 = P.centre[0], c1 = P.centre[1], c2 = P.centre[2];
 
     // Recentred pose T' = C^{-1} T C: R' = R, t' = R c + t - c.
     double Rd[9], td[3];
     for (int r = 0; r < 3; ++r) {
-        for (int q = 0; q < 3; ++q) Rd[3 * r + q] = St.T[4 * r + q];
+        for (int k = 0; k < 3; ++k) Rd[3 * r + k] = St.T[4 * r + k];
         td[r] = St.T[4 * r + 3] - P.centre[r];
-        for (int q = 0; q < 3; ++q) td[r] += Rd[3 * r + q] * P.centre[q];
+        for (int k = 0; k < 3; ++k) td[r] += Rd[3 * r + k] * P.centre[k];
     }
 
-    PairSums<Real> s = {};
-    unsigned cnt = 0;
-    const int j = task.block * kBlock + tid;
-    Real yx = 0, yy = 0, yz = 0;
-    if (j < ns) {
+    const int j = task.block * kPointsPerBlock + wave * kGroupsPerWave + grp;
+    const bool valid = j < ns;
+    double y0 = 0.0, y1 = 0.0, y2 = 0.0;
+    Real p00 = 0, p01 = 0, p02 = 0, p11 = 0, p12 = 0, p22 = 0;
+    if (valid) {
         const float *src = P.s_sorted;
         double zx, zy, zz;
         if (kExact) {
@@ -354,10 +399,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             zz = (double)src[2 * ns + j] - td[2];
         }
         // y = R^T (z - t)
-        const double y0 = Rd[0] * zx + Rd[3] * zy + Rd[6] * zz;
-        const double y1 = Rd[1] * zx + Rd[4] * zy + Rd[7] * zz;
-        const double y2 = Rd[2] * zx + Rd[5] * zy + Rd[8] * zz;
-        yx = (Real)y0; yy = (Real)y1; yz = (Real)y2;
+        y0 = Rd[0] * zx + Rd[3] * zy + Rd[6] * zz;
+        y1 = Rd[1] * zx + Rd[4] * zy + Rd[7] * zz;
+        y2 = Rd[2] * zx + Rd[5] * zy + Rd[8] * zz;
         // S' = R^T S R
         const double S[3][3] = {{src[3 * ns + j], src[4 * ns + j], src[5 * ns + j]},
                                 {src[4 * ns + j], src[6 * ns + j], src[7 * ns + j]},
@@ -367,129 +411,204 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             for (int b = 0; b < 3; ++b) SR[a][b] = S[a][0] * Rd[b] + S[a][1] * Rd[3 + b] + S[a][2] * Rd[6 + b];
         for (int a = 0; a < 3; ++a)
             for (int b = a; b < 3; ++b) Sp[a][b] = Rd[a] * SR[0][b] + Rd[3 + a] * SR[1][b] + Rd[6 + a] * SR[2][b];
-        const Real p00 = (Real)Sp[0][0], p01 = (Real)Sp[0][1], p02 = (Real)Sp[0][2];
-        const Real p11 = (Real)Sp[1][1], p12 = (Real)Sp[1][2], p22 = (Real)Sp[2][2];
+        p00 = (Real)Sp[0][0]; p01 = (Real)Sp[0][1]; p02 = (Real)Sp[0][2];
+        p11 = (Real)Sp[1][1]; p12 = (Real)Sp[1][2]; p22 = (Real)Sp[2][2];
+    }
+    const Real yx = (Real)y0, yy = (Real)y1, yz = (Real)y2;
+    const double rc = P.cutoff_scale * ell;
+    const Real rc2 = (Real)(rc * rc);
+    const Real kexp = (Real)(-1.4426950408889634 / (ell * ell));   // f = exp2(q * inv_det * kexp)
 
-        const double rc = P.cutoff_scale * ell;
-        const Real rc2 = (Real)(rc * rc);
-        // f = exp(-q / (ell^2 det)) = exp2(q * inv_det * kexp)
-        const Real kexp = (Real)(-1.4426950408889634 / (ell * ell));
-        const float fyx = (float)y0, fyy = (float)y1, fyz = (float)y2;
-        const int cx = (int)floorf((fyx - G.lo[0]) * G.inv_h);
-        const int cy = (int)floorf((fyy - G.lo[1]) * G.inv_h);
-        const int cz = (int)floorf((fyz - G.lo[2]) * G.inv_h);
-        const int x0 = max(cx - 1, 0), x1 = min(cx + 1, G.n[0] - 1);
-        if (x0 <= x1) {
-            for (int dz = -1; dz <= 1; ++dz) {
-                const int zc = cz + dz;
-                if (zc < 0 || zc >= G.n[2]) continue;
-                for (int dy = -1; dy <= 1; ++dy) {
-                    const int yc = cy + dy;
-                    if (yc < 0 || yc >= G.n[1]) continue;
-                    const int row = G.n[0] * (yc + G.n[1] * zc);
-                    const int b = cells[row + x0], e = cells[row + x1 + 1];
-                    for (int i = b; i < e; ++i) {
-                        const Real xx = kExact ? (Real)((double)ox[i] - c0) : (Real)tx[i];
-                        const Real xy = kExact ? (Real)((double)oy[i] - c1) : (Real)ty[i];
-                        const Real xz = kExact ? (Real)((double)oz[i] - c2) : (Real)tz[i];
-                        pair_term<Real>(s, cnt, xx - yx, xy - yy, xz - yz,
-                                        (Real)t0[i] + p00, (Real)t1[i] + p01, (Real)t2[i] + p02,
-                                        (Real)t3[i] + p11, (Real)t4[i] + p12, (Real)t5[i] + p22, rc2, kexp);
+    // Candidate rows of this point: the x-rows of cells (fixed cy, cz) that meet
+    // the ball of radius rcm = 1.001 * cutoff around y, each clipped to the x
+    // extent of the ball's section over that row.  A group's 16 lanes fill the
+    // group's row table, then walk it with stride 16.
+    __shared__ int sh_rs[kBlock / 64][kGroupsPerWave][kMaxRows], sh_rl[kBlock / 64][kGroupsPerWave][kMaxRows];
+    PairSums<Real> s = {};
+    unsigned cnt = 0;
+    {
+        const float rcm = (float)(rc * (double)kCellMargin);
+        const float fy0 = (float)y0, fy1 = (float)y1, fy2 = (float)y2;
+        const float gx = (fy0 - G.lo[0]) * G.inv_h, gy = (fy1 - G.lo[1]) * G.inv_h, gz = (fy2 - G.lo[2]) * G.inv_h;
+        // radius in cell units, padded for the FP32 rounding of cell coordinates
+        const float rh = rcm * G.inv_h + 4e-7f * fmaxf(fabsf(gx), fmaxf(fabsf(gy), fabsf(gz)));
+        const int y_lo = max(0, (int)floorf(gy - rh)), y_hi = min(G.n[1] - 1, (int)floorf(gy + rh));
+        const int z_lo = max(0, (int)floorf(gz - rh)), z_hi = min(G.n[2] - 1, (int)floorf(gz + rh));
+        const int nyr = (valid && y_lo <= y_hi && z_lo <= z_hi) ? y_hi - y_lo + 1 : 0;
+        const int nrows = (nyr > 0) ? nyr * (z_hi - z_lo + 1) : 0;
+        int (*rs_t)[kMaxRows] = sh_rs[wave];
+        int (*rl_t)[kMaxRows] = sh_rl[wave];
+        for (int r0 = 0; r0 < nrows; r0 += kMaxRows) {
+            const int nb = min(kMaxRows, nrows - r0);
+            for (int r = q; r < nb; r += kGroupLanes) {
+                const int cy = y_lo + (r0 + r) % nyr, cz = z_lo + (r0 + r) / nyr;
+                // distance (cell units) from the point to the row's y-z square
+                const float dy = fmaxf(0.0f, fmaxf((float)cy - gy, gy - (float)(cy + 1)));
+                const float dz = fmaxf(0.0f, fmaxf((float)cz - gz, gz - (float)(cz + 1)));
+                const float rem = rh * rh - dy * dy - dz * dz;
+                int b = 0, len = 0;
+                if (rem >= 0.0f) {
+                    const float ext = sqrtf(rem);
+                    const int x_lo = max(0, (int)floorf(gx - ext)), x_hi = min(G.n[0] - 1, (int)floorf(gx + ext));
+                    if (x_lo <= x_hi) {
+                        const int row = G.n[0] * (cy + G.n[1] * cz);
+                        b = cells[row + x_lo];
+                        len = cells[row + x_hi + 1] - b;
                     }
                 }
+                rs_t[grp][r] = b;
+                rl_t[grp][r] = len;
             }
+            __builtin_amdgcn_wave_barrier();
+            int r = 0, o = q, rs = rs_t[grp][0], rl = rl_t[grp][0];
+            while (r < nb && o >= rl) {
+                o -= rl;
+                if (++r < nb) { rs = rs_t[grp][r]; rl = rl_t[grp][r]; }
+            }
+            while (r < nb) {
+                const float4 *rec = trec + 3 * (size_t)(rs + o);
+                const float4 ra = rec[0], rb = rec[1], rcc = rec[2];
+                const Real xx = kExact ? (Real)((double)rcc.y - c0) : (Real)ra.x;
+                const Real xy = kExact ? (Real)((double)rcc.z - c1) : (Real)ra.y;
+                const Real xz = kExact ? (Real)((double)rcc.w - c2) : (Real)ra.z;
+                pair_term<Real>(s, cnt, xx - yx, xy - yy, xz - yz, (Real)ra.w + p00, (Real)rb.x + p01,
+                                (Real)rb.y + p02, (Real)rb.z + p11, (Real)rb.w + p12, (Real)rcc.x + p22, rc2,
+                                kexp);
+                o += kGroupLanes;
+                while (r < nb && o >= rl) {
+                    o -= rl;
+                    if (++r < nb) { rs = rs_t[grp][r]; rl = rl_t[grp][r]; }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
         }
     }
 
-    // Finish the source point: the 28 sums in the recentred frame.
-    Real v[kNumSums];
-    {
-        const Real k2 = (Real)(2.0 / (ell * ell));
+    // Combine the 16 lanes of each point.
+#pragma unroll
+    for (int off = kGroupLanes / 2; off >= 1; off >>= 1) {
+        s.F += __shfl_xor(s.F, off, 64);
+        s.A0 += __shfl_xor(s.A0, off, 64); s.A1 += __shfl_xor(s.A1, off, 64); s.A2 += __shfl_xor(s.A2, off, 64);
+        s.B00 += __shfl_xor(s.B00, off, 64); s.B01 += __shfl_xor(s.B01, off, 64);
+        s.B02 += __shfl_xor(s.B02, off, 64); s.B11 += __shfl_xor(s.B11, off, 64);
+        s.B12 += __shfl_xor(s.B12, off, 64); s.B22 += __shfl_xor(s.B22, off, 64);
+    }
+
+    // Finish the source point (lane 0 of its group): the 28 sums, recentred frame.
+    __shared__ Real sh_pts[kPointsPerBlock][kNumSums];
+    __shared__ unsigned sh_cnt[kBlock / 64];
+    if (q == 0) {
+        Real v[kNumSums];
+        const Real k2 = valid ? (Real)(2.0 / (ell * ell)) : (Real)0;
         const Real a0 = k2 * s.A0, a1 = k2 * s.A1, a2 = k2 * s.A2;
         const Real b00 = k2 * s.B00, b01 = k2 * s.B01, b02 = k2 * s.B02;
         const Real b11 = k2 * s.B11, b12 = k2 * s.B12, b22 = k2 * s.B22;
-        v[0] = s.F;
+        v[0] = valid ? s.F : (Real)0;
         // g_w = -y x a, g_v = -a
         v[1] = -(yy * a2 - yz * a1);
         v[2] = -(yz * a0 - yx * a2);
         v[3] = -(yx * a1 - yy * a0);
         v[4] = -a0; v[5] = -a1; v[6] = -a2;
-        // Y = y^, M = Y B  (B symmetric)
+        // Y = y^, M = Y B; H blocks: top-left Y B Y, top-right -Y B, bottom-right -B
         const Real B[3][3] = {{b00, b01, b02}, {b01, b11, b12}, {b02, b12, b22}};
         const Real Y[3][3] = {{0, -yz, yy}, {yz, 0, -yx}, {-yy, yx, 0}};
         Real M[3][3];
         for (int r = 0; r < 3; ++r)
             for (int c = 0; c < 3; ++c) M[r][c] = Y[r][0] * B[0][c] + Y[r][1] * B[1][c] + Y[r][2] * B[2][c];
-        // top-left Y B Y, top-right -Y B, bottom-right -B
         for (int r = 0; r < 3; ++r)
-            for (int c = r; c < 3; ++c)
-                v[7 + ut(r, c)] = M[r][0] * Y[0][c] + M[r][1] * Y[1][c] + M[r][2] * Y[2][c];
+            for (int c = r; c < 3; ++c) v[7 + ut(r, c)] = M[r][0] * Y[0][c] + M[r][1] * Y[1][c] + M[r][2] * Y[2][c];
         for (int r = 0; r < 3; ++r)
             for (int c = 0; c < 3; ++c) v[7 + ut(r, 3 + c)] = -M[r][c];
         for (int r = 0; r < 3; ++r)
             for (int c = r; c < 3; ++c) v[7 + ut(3 + r, 3 + c)] = -B[r][c];
-    }
-
-    // Block reduction in Real: wave sums, then the 4 waves in fixed order.
-    __shared__ Real sh[4][kNumSums];
-    __shared__ unsigned sh_cnt[4];
-    const int lane = tid & 63, wave = tid >> 6;
+        const int slot = wave * kGroupsPerWave + grp;
 #pragma unroll
-    for (int k = 0; k < kNumSums; ++k) v[k] = wave_sum(v[k]);
+        for (int k = 0; k < kNumSums; ++k) sh_pts[slot][k] = v[k];
+    }
     cnt = wave_sum(cnt);
-    if (lane == 0) {
-#pragma unroll
-        for (int k = 0; k < kNumSums; ++k) sh[wave][k] = v[k];
-        sh_cnt[wave] = cnt;
-    }
+    if (lane == 0) sh_cnt[wave] = cnt;
     __syncthreads();
     Real *part = reinterpret_cast<Real *>(P.partials) + (size_t)task.block * kPartialStride;
-    if (tid < kNumSums) part[tid] = ((sh[0][tid] + sh[1][tid]) + sh[2][tid]) + sh[3][tid];
-    if (tid == kNumSums)
-        *reinterpret_cast<unsigned long long *>(part + kNumSums) =
-            (unsigned long long)sh_cnt[0] + sh_cnt[1] + sh_cnt[2] + sh_cnt[3];
-
-    // Last block of this pair: reduce, step, advance.
-    __shared__ int sh_last;
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) {
-        const unsigned prev = __hip_atomic_fetch_add(&St.counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        sh_last = (prev == (unsigned)(P.n_blocks - 1));
+    if (tid < kNumSums) {
+        Real acc = 0;
+        for (int pnt = 0; pnt < kPointsPerBlock; ++pnt) acc += sh_pts[pnt][tid];
+        part[tid] = acc;
     }
-    __syncthreads();
-    if (!sh_last) return;
-    __threadfence();
+    if (tid == kNumSums) {
+        unsigned long long c = 0;
+        for (int w = 0; w < kBlock / 64; ++w) c += sh_cnt[w];
+        *reinterpret_cast<unsigned long long *>(part + kNumSums) = c;
+    }
 
-    __shared__ double tot[kNumSums];
-    __shared__ unsigned long long tot_pairs;
+}
+
+// Cross-block reduction of one pair's block sums, split over kReduceSplit
+// blocks per pair.  Block s takes the pair-kernel blocks b = s (mod
+// kReduceSplit); in it, thread t adds component t % 32 (the 28 sums and the
+// pair count) over every 32nd of those blocks with a Kahan-compensated sum in
+// the pair-term precision, and the 32 slices are added in FP64 in a fixed
+// order.  The step kernel adds the kReduceSplit results, again in fixed order.
+constexpr int kReduceThreads = 1024;
+constexpr int kSlices = kReduceThreads / 32;
+
+template <typename Real>
+__global__ __launch_bounds__(kReduceThreads) void k_reduce(PairDev *pairs) {
+    PairDev &P = pairs[blockIdx.y];
+    State &St = *P.st;
+    if (St.done) return;
+    const int split = blockIdx.x;
+    const int tid = threadIdx.x, ck = tid & 31, slice = tid >> 5;
     const Real *parts = reinterpret_cast<const Real *>(P.partials);
-    for (int k = wave; k < kNumSums + 1; k += 4) {
-        if (k < kNumSums) {
-            // compensated per-lane sum over the lane's blocks, then an FP64 tree
-            Real sum = 0, comp = 0;
-            for (int b = lane; b < P.n_blocks; b += 64) {
-                const Real x = __builtin_nontemporal_load(parts + (size_t)b * kPartialStride + k) - comp;
-                const Real t = sum + x;
-                comp = (t - sum) - x;
-                sum = t;
-            }
-            double d = (double)sum - (double)comp;
-            d = wave_sum(d);
-            if (lane == 0) tot[k] = d;
-        } else {
-            unsigned long long c = 0;
-            for (int b = lane; b < P.n_blocks; b += 64)
-                c += __builtin_nontemporal_load(
-                    reinterpret_cast<const unsigned long long *>(parts + (size_t)b * kPartialStride + kNumSums));
-            c = wave_sum(c);
-            if (lane == 0) tot_pairs = c;
+    __shared__ double sh[kSlices][33];
+    __shared__ unsigned long long sh_c[kSlices];
+    const int nb = P.n_blocks, step = kSlices * kReduceSplit;
+    if (ck < kNumSums) {
+        Real sm = 0, cp = 0;
+        for (int b = split + kReduceSplit * slice; b < nb; b += step) {
+            const Real y = parts[(size_t)b * kPartialStride + ck] - cp;
+            const Real t = sm + y;
+            cp = (t - sm) - y;
+            sm = t;
         }
+        sh[slice][ck] = (double)sm - (double)cp;
+    } else if (ck == kNumSums) {
+        unsigned long long c = 0;
+        for (int b = split + kReduceSplit * slice; b < nb; b += step)
+            c += *reinterpret_cast<const unsigned long long *>(parts + (size_t)b * kPartialStride + kNumSums);
+        sh_c[slice] = c;
     }
     __syncthreads();
-    if (tid != 0) return;
+    if (tid < kNumSums) {
+        double acc = 0.0;
+        for (int sl = 0; sl < kSlices; ++sl) acc += sh[sl][tid];
+        St.sub[split][tid] = acc;
+    } else if (tid == kNumSums) {
+        unsigned long long c = 0;
+        for (int sl = 0; sl < kSlices; ++sl) c += sh_c[sl];
+        St.sub_pairs[split] = c;
+    }
+}
 
-    finish_iteration(P, St, tot, tot_pairs, stage);
+// The FP64 step of one pair, on one lane (its registers are not shared with
+// any wide kernel).  A pair that finishes decrements the batch's count of
+// active pairs, which the host polls.
+__global__ __launch_bounds__(64) void k_step(PairDev *pairs, int *active) {
+    PairDev &P = pairs[blockIdx.x];
+    State &St = *P.st;
+    if (St.done || threadIdx.x != 0) return;
+    double tot[kNumSums];
+    unsigned long long c = 0;
+#pragma unroll
+    for (int k = 0; k < kNumSums; ++k) {
+        double acc = 0.0;
+#pragma unroll
+        for (int sp = 0; sp < kReduceSplit; ++sp) acc += St.sub[sp][k];
+        tot[k] = acc;
+    }
+#pragma unroll
+    for (int sp = 0; sp < kReduceSplit; ++sp) c += St.sub_pairs[sp];
+    finish_iteration(P, St, tot, c, St.stage);
+    if (St.done) atomicSub(active, 1);
 }
 
 __global__ void k_count_active(const PairDev *pairs, int n_pairs, int *active) {
@@ -502,14 +621,18 @@ __global__ void k_count_active(const PairDev *pairs, int n_pairs, int *active) {
     if (threadIdx.x == 0) *active = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
-hipError_t launch_iterations(PairDev *pairs, BlockTask *tasks, int n_tasks, int n_iters, int precision,
-                             hipStream_t s) {
+hipError_t launch_iterations(PairDev *pairs, int n_pairs, BlockTask *tasks, int n_tasks, int n_iters,
+                             int precision, int *active, hipStream_t s) {
     if (n_tasks <= 0) return hipSuccess;
     for (int it = 0; it < n_iters; ++it) {
-        if (precision == GCVO_PRECISION_FP64)
+        if (precision == GCVO_PRECISION_FP64) {
             hipLaunchKernelGGL(k_iterate<double>, dim3(n_tasks), dim3(kBlock), 0, s, pairs, tasks);
-        else
+            hipLaunchKernelGGL(k_reduce<double>, dim3(kReduceSplit, n_pairs), dim3(kReduceThreads), 0, s, pairs);
+        } else {
             hipLaunchKernelGGL(k_iterate<float>, dim3(n_tasks), dim3(kBlock), 0, s, pairs, tasks);
+            hipLaunchKernelGGL(k_reduce<float>, dim3(kReduceSplit, n_pairs), dim3(kReduceThreads), 0, s, pairs);
+        }
+        hipLaunchKernelGGL(k_step, dim3(n_pairs), dim3(64), 0, s, pairs, active);
     }
     return hipGetLastError();
 }

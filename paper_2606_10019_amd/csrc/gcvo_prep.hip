@@ -3,8 +3,8 @@
 //   k_setup    grids for every binning job, recentring shift, initial state
 //   k_soa      AoS float32 input -> SoA original and recentred copies
 //   k_keys     linear cell key of every point of every job
-//   k_sort     stable LSD radix sort of (key, index), one 1024-thread block per job,
-//              plus the cell_start table
+//   k_sort_*   stable multi-block LSD radix sort of (key, index) for all jobs,
+//   k_cells    the cell_start table of each grid
 //   k_knn      n nearest neighbours (FP64 distances, ties to the smaller index),
 //              covariance about the point, cyclic Jacobi, eigenvalue floor
 //              (eq. (covariance), Remark 1)
@@ -130,8 +130,9 @@ __device__ void make_grid(Grid &G, const float lo[3], const float hi[3], double 
     G.key_bits = bits_for(G.ncells > 1 ? G.ncells - 1 : 1);
 }
 
-// Cell edge for a kNN grid: about one point per cell of the bounding volume
-// (flat extents are widened to 1e-3 of the largest so the volume stays positive).
+// Cell edge for a kNN grid: half the edge that would hold one point per cell of
+// the bounding volume (points lie on surfaces, so most of that volume is empty;
+// flat extents are widened to 1e-3 of the largest so the volume stays positive).
 __device__ double knn_cell(const float lo[3], const float hi[3], int n) {
     double ext[3], emax = 0.0;
     for (int d = 0; d < 3; ++d) {
@@ -141,7 +142,7 @@ __device__ double knn_cell(const float lo[3], const float hi[3], int n) {
     if (!(emax > 0.0)) return 1.0;
     double vol = 1.0;
     for (int d = 0; d < 3; ++d) vol *= fmax(ext[d], 1e-3 * emax);
-    return cbrt(vol / (double)(n > 0 ? n : 1));
+    return 0.5 * cbrt(vol / (double)(n > 0 ? n : 1));
 }
 
 __global__ void k_setup(PairDev *pairs, int n_pairs) {
@@ -153,6 +154,20 @@ __global__ void k_setup(PairDev *pairs, int n_pairs) {
                                P.job_knn_t->max_cells);
     if (P.job_knn_s) make_grid(*P.job_knn_s->grid, P.lo_s, P.hi_s, knn_cell(P.lo_s, P.hi_s, P.n_s),
                                P.job_knn_s->max_cells);
+    if (P.job_order_s) {   // 1024 cells along the longest axis; keys are Morton codes
+        Grid &M = *P.job_order_s->grid;
+        double emax = 0.0;
+        for (int d = 0; d < 3; ++d) emax = fmax(emax, (double)P.hi_s[d] - (double)P.lo_s[d]);
+        const double h = (isfinite(emax) && emax > 0.0) ? emax / 1023.5 : 1.0;
+        for (int d = 0; d < 3; ++d) {
+            M.lo[d] = isfinite(P.lo_s[d]) ? P.lo_s[d] : 0.0f;
+            M.n[d] = 1024;
+        }
+        M.h = (float)h;
+        M.inv_h = (float)(1.0 / h);
+        M.ncells = 0;
+        M.key_bits = 30;
+    }
     // Stage grids over the recentred target.  float(x - c) is monotone in x,
     // so the recentred box is the rounded original box.
     float lo[3], hi[3];
@@ -161,7 +176,7 @@ __global__ void k_setup(PairDev *pairs, int n_pairs) {
         hi[d] = (float)((double)P.hi_t[d] - P.centre[d]);
     }
     for (int s = 0; s < P.n_stages; ++s)
-        make_grid(*P.t_grid[s], lo, hi, (double)kCellMargin * P.cutoff_scale * P.ell[s],
+        make_grid(*P.t_grid[s], lo, hi, (double)kPairCellFraction * P.cutoff_scale * P.ell[s],
                   P.job_stage0[s].max_cells);
     State &S = *P.st;
     for (int a = 0; a < 16; ++a) S.T[a] = P.T_init[a];
@@ -172,7 +187,6 @@ __global__ void k_setup(PairDev *pairs, int n_pairs) {
     S.pairs_last = 0;
     S.iter = S.stage = S.stage_iter = S.converged = S.damped = 0;
     for (int s = 0; s < kMaxStages; ++s) S.stage_iters[s] = 0;
-    S.counter = 0;
     S.status = P.nonfinite ? GCVO_ERR_INVALID : GCVO_OK;
     S.done = P.nonfinite ? 1 : 0;
 }
@@ -211,113 +225,146 @@ __global__ __launch_bounds__(kBlock) void k_keys(SortJob *jobs) {
     int cx = cell_coord(J.x[i], G.lo[0], G.inv_h, G.n[0]);
     int cy = cell_coord(J.y[i], G.lo[1], G.inv_h, G.n[1]);
     int cz = cell_coord(J.z[i], G.lo[2], G.inv_h, G.n[2]);
-    J.keys[i] = (uint32_t)(cx + G.n[0] * (cy + G.n[1] * cz));
+    if (J.morton) {
+        uint32_t key = 0;
+        for (int b = 9; b >= 0; --b)
+            key = (key << 3) | ((((uint32_t)cz >> b) & 1u) << 2) | ((((uint32_t)cy >> b) & 1u) << 1) |
+                  (((uint32_t)cx >> b) & 1u);
+        J.keys[i] = key;
+    } else {
+        J.keys[i] = (uint32_t)(cx + G.n[0] * (cy + G.n[1] * cz));
+    }
     J.idx[i] = (uint32_t)i;
 }
 
-// ------------------------------------------------------------------ k_sort
+// ------------------------------------------------------------------ radix sort
 //
-// Stable LSD radix sort with 8-bit digits, one block per job.  Each pass:
-// digit histogram in LDS, exclusive scan, then the input is streamed in
-// 1024-element tiles in order; inside a tile an element's rank among equal
-// digits comes from ballots within its wave (9 ballots match the 8 digit bits
-// plus a valid bit) and a per-digit prefix over the 16 waves.  Ranks therefore
-// follow input order, so the sort is stable and deterministic.
+// Stable LSD radix sort of (key, index) with 8-bit digits, all jobs at once.
+// Each pass is three launches over tiles of kSortTile elements:
+//   k_sort_up    per-tile digit histograms,
+//   k_sort_scan  per job: exclusive offsets in digit-major, tile-minor order,
+//   k_sort_down  per tile: stable scatter.  A tile is taken in 4 rounds of 256
+//                elements in input order; an element's rank among equal digits
+//                comes from 9 ballots inside its wave plus per-digit prefixes
+//                over the earlier waves and rounds, so ranks follow input order.
+// Jobs whose keys need fewer passes run the extra passes as stable no-ops.
 
-__global__ __launch_bounds__(kSortThreads) void k_sort(SortJob *jobs) {
-    const SortJob J = jobs[blockIdx.x];
-    const int n = J.n;
-    const int ncells = J.grid->ncells;
-    const int passes = (J.grid->key_bits + 7) / 8;
-    __shared__ unsigned s_hist[256];
-    __shared__ unsigned s_base[256];
-    __shared__ unsigned s_tot[256];
-    __shared__ unsigned s_wcnt[16][256];
+constexpr int kSortTile = 1024;
+
+__global__ __launch_bounds__(256) void k_sort_up(SortJob *jobs, int shift, int pass) {
+    const SortJob &J = jobs[blockIdx.y];
+    const int ntile = (J.n + kSortTile - 1) / kSortTile;
+    const int tile = blockIdx.x;
+    if (tile >= ntile) return;
+    const uint32_t *kin = (pass & 1) ? J.keys_tmp : J.keys;
+    __shared__ unsigned hist[256];
+    hist[threadIdx.x] = 0;
+    __syncthreads();
+    const int base = tile * kSortTile;
+    for (int e = threadIdx.x; e < kSortTile; e += 256) {
+        const int i = base + e;
+        if (i < J.n) atomicAdd(&hist[(kin[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    J.tile_counts[(size_t)threadIdx.x * ntile + tile] = hist[threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void k_sort_scan(SortJob *jobs) {
+    const SortJob &J = jobs[blockIdx.x];
+    const int ntile = (J.n + kSortTile - 1) / kSortTile;
+    const int d = threadIdx.x, lane = d & 63, wave = d >> 6;
+    unsigned *row = J.tile_counts + (size_t)d * ntile;
+    unsigned run = 0;
+    for (int t = 0; t < ntile; ++t) {   // exclusive prefix over tiles for digit d
+        const unsigned v = row[t];
+        row[t] = run;
+        run += v;
+    }
+    // exclusive scan of the 256 digit totals
+    unsigned inc = run;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const unsigned o = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += o;
+    }
+    __shared__ unsigned wsum[4];
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    unsigned before = 0;
+    for (int w = 0; w < wave; ++w) before += wsum[w];
+    const unsigned digit_base = before + inc - run;
+    for (int t = 0; t < ntile; ++t) row[t] += digit_base;
+}
+
+__global__ __launch_bounds__(256) void k_sort_down(SortJob *jobs, int shift, int pass) {
+    const SortJob &J = jobs[blockIdx.y];
+    const int ntile = (J.n + kSortTile - 1) / kSortTile;
+    const int tile = blockIdx.x;
+    if (tile >= ntile) return;
+    const uint32_t *kin = (pass & 1) ? J.keys_tmp : J.keys;
+    const uint32_t *iin = (pass & 1) ? J.idx_tmp : J.idx;
+    uint32_t *kout = (pass & 1) ? J.keys : J.keys_tmp;
+    uint32_t *iout = (pass & 1) ? J.idx : J.idx_tmp;
+    __shared__ unsigned base_d[256];    // next free slot of each digit for this tile
+    __shared__ unsigned wcnt[4][256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-
-    uint32_t *kin = J.keys, *iin = J.idx, *kout = J.keys_tmp, *iout = J.idx_tmp;
-    for (int pass = 0; pass < passes; ++pass) {
-        const int shift = 8 * pass;
-        if (tid < 256) s_hist[tid] = 0;
-        for (int c = tid; c < 16 * 256; c += kSortThreads) (&s_wcnt[0][0])[c] = 0;
-        __syncthreads();
-        for (int i = tid; i < n; i += kSortThreads) atomicAdd(&s_hist[(kin[i] >> shift) & 255u], 1u);
-        __syncthreads();
-        if (wave == 0) {
-            unsigned v0 = s_hist[4 * lane], v1 = s_hist[4 * lane + 1], v2 = s_hist[4 * lane + 2],
-                     v3 = s_hist[4 * lane + 3];
-            unsigned loc = v0 + v1 + v2 + v3, inc = loc;
+    base_d[tid] = J.tile_counts[(size_t)tid * ntile + tile];
+    for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+    for (int round = 0; round < kSortTile / 256; ++round) {
+        const int i = tile * kSortTile + round * 256 + tid;
+        const bool valid = i < J.n;
+        const uint32_t key = valid ? kin[i] : 0u;
+        const uint32_t id = valid ? iin[i] : 0u;
+        const unsigned d = valid ? ((key >> shift) & 255u) : 256u;
+        unsigned long long same = ~0ull;
 #pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                unsigned o = __shfl_up(inc, off, 64);
-                if (lane >= off) inc += o;
-            }
-            unsigned ex = inc - loc;
-            s_base[4 * lane] = ex;
-            s_base[4 * lane + 1] = ex + v0;
-            s_base[4 * lane + 2] = ex + v0 + v1;
-            s_base[4 * lane + 3] = ex + v0 + v1 + v2;
+        for (int b = 0; b < 9; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const unsigned long long bb = __ballot(bit);
+            same &= bit ? bb : ~bb;
         }
+        const unsigned rank = (unsigned)__popcll(same & below);
+        if (valid && rank == 0) wcnt[wave][d] = (unsigned)__popcll(same);
         __syncthreads();
-        for (int start = 0; start < n; start += kSortThreads) {
-            const int i = start + tid;
-            const bool valid = i < n;
-            const uint32_t key = valid ? kin[i] : 0u;
-            const uint32_t id = valid ? iin[i] : 0u;
-            const unsigned d = valid ? ((key >> shift) & 255u) : 256u;
-            unsigned long long same = ~0ull;
-#pragma unroll
-            for (int b = 0; b < 9; ++b) {
-                const bool bit = (d >> b) & 1u;
-                const unsigned long long bb = __ballot(bit);
-                same &= bit ? bb : ~bb;
-            }
-            const unsigned rank = (unsigned)__popcll(same & below);
-            if (valid && rank == 0) s_wcnt[wave][d] = (unsigned)__popcll(same);
-            __syncthreads();
-            if (tid < 256) {
-                unsigned run = 0;
-                for (int w = 0; w < 16; ++w) {
-                    unsigned v = s_wcnt[w][tid];
-                    s_wcnt[w][tid] = run;
-                    run += v;
-                }
-                s_tot[tid] = run;
+        {   // per digit: prefix over the 4 waves
+            unsigned run = 0;
+            for (int w = 0; w < 4; ++w) {
+                const unsigned v = wcnt[w][tid];
+                wcnt[w][tid] = run;
+                run += v;
             }
             __syncthreads();
             if (valid) {
-                const unsigned pos = s_base[d] + s_wcnt[wave][d] + rank;
-                kout[pos] = key;
-                iout[pos] = id;
+                const unsigned posn = base_d[d] + wcnt[wave][d] + rank;
+                kout[posn] = key;
+                iout[posn] = id;
             }
             __syncthreads();
-            if (tid < 256) {
-                s_base[tid] += s_tot[tid];
-                for (int w = 0; w < 16; ++w) s_wcnt[w][tid] = 0;
-            }
+            base_d[tid] += run;
+            for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
             __syncthreads();
         }
-        uint32_t *t = kin; kin = kout; kout = t;
-        t = iin; iin = iout; iout = t;
-        __syncthreads();
     }
-    if (passes & 1) {   // result sits in the tmp buffers: move it home
-        for (int i = tid; i < n; i += kSortThreads) {
-            J.keys[i] = kin[i];
-            J.idx[i] = iin[i];
-        }
-        __syncthreads();
-    }
+}
+
+// cell_start[c] = first sorted position whose key is >= c (binary search over
+// the sorted keys, one thread per cell), so cell_start[ncells] = n.
+__global__ __launch_bounds__(kBlock) void k_cells(SortJob *jobs) {
+    const SortJob &J = jobs[blockIdx.y];
+    if (J.morton || !J.cell_start) return;
+    const int n = J.n, ncells = J.grid->ncells;
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c > ncells) return;
     const uint32_t *K = J.keys;
-    int *cs = J.cell_start;
-    for (int i = tid; i < n; i += kSortThreads) {
-        const int k = (int)K[i];
-        const int from = (i == 0) ? 0 : (int)K[i - 1] + 1;
-        for (int c = from; c <= k; ++c) cs[c] = i;
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((int)K[mid] < c) lo = mid + 1;
+        else hi = mid;
     }
-    const int tail = (n == 0) ? 0 : (int)K[n - 1] + 1;
-    for (int c = tail + tid; c <= ncells; c += kSortThreads) cs[c] = n;
+    J.cell_start[c] = lo;
 }
 
 // ------------------------------------------------------------------ k_knn
@@ -359,103 +406,157 @@ __device__ void jacobi_cyclic(double a[3][3], double v[3][3]) {
     }
 }
 
+// kNN with kGroupLanes lanes per point: the group lists the x-rows of grid
+// cells meeting a ball of radius r around the point, every lane keeps the K
+// best candidates it sees within r (FP64 squared distances, ties to the smaller
+// index), and the 16 lists are merged by K rounds of a group minimum.  If fewer
+// than K points lie within r, r doubles and the point is scanned again; the
+// K-th merged distance never exceeds r, so no closer point was skipped.
 template <int K>
 __global__ __launch_bounds__(kBlock) void k_knn(SortJob *jobs, const PairDev *pairs) {
     const SortJob &J = jobs[blockIdx.y];
     if (!J.want_shapes || pairs[J.pair].nonfinite) return;
-    const int pos = blockIdx.x * kBlock + threadIdx.x;
     const int n = J.n;
-    if (pos >= n) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int grp = lane / kGroupLanes, q = lane % kGroupLanes;
+    const int pos = (blockIdx.x * (kBlock / 64) + wave) * kGroupsPerWave + grp;
+    if ((blockIdx.x * (kBlock / 64) + wave) * kGroupsPerWave >= n) return;   // whole wave idle
+    const bool valid = pos < n;
     const double rho = pairs[J.pair].rho;
     const Grid G = *J.grid;
-    const uint32_t p = J.idx[pos];
+    const uint32_t p = valid ? J.idx[pos] : 0u;
     const float fx = J.x[p], fy = J.y[p], fz = J.z[p];
     const double px = fx, py = fy, pz = fz;
-    const int cx = cell_coord(fx, G.lo[0], G.inv_h, G.n[0]);
-    const int cy = cell_coord(fy, G.lo[1], G.inv_h, G.n[1]);
-    const int cz = cell_coord(fz, G.lo[2], G.inv_h, G.n[2]);
-    double bd[K];
-    uint32_t bq[K];
-#pragma unroll
-    for (int m = 0; m < K; ++m) {
-        bd[m] = DBL_MAX;
-        bq[m] = 0xffffffffu;
-    }
+    const float gx = (fx - G.lo[0]) * G.inv_h, gy = (fy - G.lo[1]) * G.inv_h, gz = (fz - G.lo[2]) * G.inv_h;
     const int *cs = J.cell_start;
     const uint32_t *idx = J.idx;
-    auto visit_range = [&](int b, int e) {
-        for (int s = b; s < e; ++s) {
-            const uint32_t q = idx[s];
-            // Exact differences of float32 values in FP64, products and sums in
-            // written order without contraction, so the ranking is reproducible.
-            const double dx = (double)J.x[q] - px, dy = (double)J.y[q] - py, dz = (double)J.z[q] - pz;
-            const double d = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-            if (!nb_less(d, q, bd[K - 1], bq[K - 1])) continue;
-            bool placed = false;
-#pragma unroll
-            for (int m = K - 1; m > 0; --m) {
-                if (!placed) {
-                    if (nb_less(d, q, bd[m - 1], bq[m - 1])) {
-                        bd[m] = bd[m - 1];
-                        bq[m] = bq[m - 1];
-                    } else {
-                        bd[m] = d;
-                        bq[m] = q;
-                        placed = true;
-                    }
-                }
-            }
-            if (!placed) {
-                bd[0] = d;
-                bq[0] = q;
-            }
-        }
-    };
-    // Shells of cells at Chebyshev distance R around p's cell, clamped to the
-    // grid.  After shell R every unvisited point lies at least R cells beyond
-    // p's cell along some axis.  Points still short of K close neighbours after
-    // kMaxShell shells are finished by a scan of the whole cloud.
-    constexpr int kMaxShell = 24;
-    const int cover = max(max(max(cx, G.n[0] - 1 - cx), max(cy, G.n[1] - 1 - cy)), max(cz, G.n[2] - 1 - cz));
-    bool settled = false;
-    for (int R = 0; R <= kMaxShell; ++R) {
-        const int z0 = max(-R, -cz), z1 = min(R, G.n[2] - 1 - cz);
-        const int y0 = max(-R, -cy), y1 = min(R, G.n[1] - 1 - cy);
-        for (int dz = z0; dz <= z1; ++dz) {
-            const int z = cz + dz;
-            for (int dy = y0; dy <= y1; ++dy) {
-                const int y = cy + dy;
-                const int row = G.n[0] * (y + G.n[1] * z);
-                if (dz == -R || dz == R || dy == -R || dy == R) {
-                    const int x0 = max(cx - R, 0), x1 = min(cx + R, G.n[0] - 1);
-                    visit_range(cs[row + x0], cs[row + x1 + 1]);
-                } else {
-                    if (cx - R >= 0) visit_range(cs[row + cx - R], cs[row + cx - R + 1]);
-                    if (R > 0 && cx + R < G.n[0]) visit_range(cs[row + cx + R], cs[row + cx + R + 1]);
-                }
-            }
-        }
-        const double reach = (double)R * (double)G.h * (1.0 - 1e-4);
-        if ((bq[K - 1] != 0xffffffffu && bd[K - 1] < reach * reach) || R >= cover) {
-            settled = true;
-            break;
-        }
-    }
-    if (!settled) {
+    __shared__ int sh_rs[kBlock / 64][kGroupsPerWave][kMaxRows], sh_rl[kBlock / 64][kGroupsPerWave][kMaxRows];
+    int (*rs_t)[kMaxRows] = sh_rs[wave];
+    int (*rl_t)[kMaxRows] = sh_rl[wave];
+
+    double md[K];    // merged K nearest (identical on the group's lanes)
+    uint32_t mq[K];
+    bool done = !valid;
+    double rad = 1.5 * (double)G.h;
+    for (int attempt = 0; attempt < 40; ++attempt) {
+        double bd[K];
+        uint32_t bq[K];
 #pragma unroll
         for (int m = 0; m < K; ++m) {
             bd[m] = DBL_MAX;
             bq[m] = 0xffffffffu;
         }
-        visit_range(0, n);   // sorted positions 0..n-1 cover every point once
+        if (!done) {
+            const double r2 = rad * rad;
+            const float rh = (float)(rad * (double)kCellMargin) * G.inv_h +
+                             4e-7f * fmaxf(fabsf(gx), fmaxf(fabsf(gy), fabsf(gz)));
+            const int y_lo = max(0, (int)floorf(gy - rh)), y_hi = min(G.n[1] - 1, (int)floorf(gy + rh));
+            const int z_lo = max(0, (int)floorf(gz - rh)), z_hi = min(G.n[2] - 1, (int)floorf(gz + rh));
+            const int nyr = (y_lo <= y_hi && z_lo <= z_hi) ? y_hi - y_lo + 1 : 0;
+            const int nrows = (nyr > 0) ? nyr * (z_hi - z_lo + 1) : 0;
+            for (int r0 = 0; r0 < nrows; r0 += kMaxRows) {
+                const int nb = min(kMaxRows, nrows - r0);
+                for (int r = q; r < nb; r += kGroupLanes) {
+                    const int cy = y_lo + (r0 + r) % nyr, cz = z_lo + (r0 + r) / nyr;
+                    const float dy = fmaxf(0.0f, fmaxf((float)cy - gy, gy - (float)(cy + 1)));
+                    const float dz = fmaxf(0.0f, fmaxf((float)cz - gz, gz - (float)(cz + 1)));
+                    const float rem = rh * rh - dy * dy - dz * dz;
+                    int b = 0, len = 0;
+                    if (rem >= 0.0f) {
+                        const float ext = sqrtf(rem);
+                        const int x_lo = max(0, (int)floorf(gx - ext)), x_hi = min(G.n[0] - 1, (int)floorf(gx + ext));
+                        if (x_lo <= x_hi) {
+                            const int row = G.n[0] * (cy + G.n[1] * cz);
+                            b = cs[row + x_lo];
+                            len = cs[row + x_hi + 1] - b;
+                        }
+                    }
+                    rs_t[grp][r] = b;
+                    rl_t[grp][r] = len;
+                }
+                __builtin_amdgcn_wave_barrier();
+                int r = 0, o = q, rs = rs_t[grp][0], rl = rl_t[grp][0];
+                while (r < nb && o >= rl) {
+                    o -= rl;
+                    if (++r < nb) { rs = rs_t[grp][r]; rl = rl_t[grp][r]; }
+                }
+                while (r < nb) {
+                    const uint32_t c = idx[rs + o];
+                    // Exact differences of float32 values in FP64, products and sums
+                    // in written order without contraction: reproducible ranking.
+                    const double dx = (double)J.x[c] - px, dyy = (double)J.y[c] - py, dzz = (double)J.z[c] - pz;
+                    const double d = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dyy, dyy)), __dmul_rn(dzz, dzz));
+                    if (d <= r2 && nb_less(d, c, bd[K - 1], bq[K - 1])) {
+                        bool placed = false;
+#pragma unroll
+                        for (int m = K - 1; m > 0; --m) {
+                            if (!placed) {
+                                if (nb_less(d, c, bd[m - 1], bq[m - 1])) {
+                                    bd[m] = bd[m - 1];
+                                    bq[m] = bq[m - 1];
+                                } else {
+                                    bd[m] = d;
+                                    bq[m] = c;
+                                    placed = true;
+                                }
+                            }
+                        }
+                        if (!placed) {
+                            bd[0] = d;
+                            bq[0] = c;
+                        }
+                    }
+                    o += kGroupLanes;
+                    while (r < nb && o >= rl) {
+                        o -= rl;
+                        if (++r < nb) { rs = rs_t[grp][r]; rl = rl_t[grp][r]; }
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        // Merge: K rounds of a lexicographic group minimum over the lists' heads.
+#pragma unroll
+        for (int m = 0; m < K; ++m) {
+            double d = bd[0];
+            uint32_t c = bq[0];
+#pragma unroll
+            for (int off = kGroupLanes / 2; off >= 1; off >>= 1) {
+                const double od = __shfl_xor(d, off, 64);
+                const uint32_t oc = __shfl_xor(c, off, 64);
+                if (nb_less(od, oc, d, c)) {
+                    d = od;
+                    c = oc;
+                }
+            }
+            if (!done) {
+                md[m] = d;
+                mq[m] = c;
+            }
+            if (bq[0] == c && bd[0] == d) {   // this lane supplied the minimum: pop it
+#pragma unroll
+                for (int k = 0; k < K - 1; ++k) {
+                    bd[k] = bd[k + 1];
+                    bq[k] = bq[k + 1];
+                }
+                bd[K - 1] = DBL_MAX;
+                bq[K - 1] = 0xffffffffu;
+            }
+        }
+        if (!done) {
+            if (mq[K - 1] != 0xffffffffu) done = true;   // K points within rad: the K nearest
+            else rad *= 2.0;
+        }
+        if (__all(done)) break;
     }
-    // Covariance about p (eq. (covariance)), FP64.
+    if (!valid || q != 0 || !done) return;
+
+    // Covariance about p (eq. (covariance)), FP64, by the group's first lane.
     double a[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
 #pragma unroll
     for (int m = 0; m < K; ++m) {
-        const uint32_t q = bq[m];
-        if (q >= (uint32_t)n) continue;   // unfilled slot (cannot happen for n >= K)
-        const double d0 = (double)J.x[q] - px, d1 = (double)J.y[q] - py, d2 = (double)J.z[q] - pz;
+        const uint32_t c = mq[m];
+        const double d0 = (double)J.x[c] - px, d1 = (double)J.y[c] - py, d2 = (double)J.z[c] - pz;
         a[0][0] += d0 * d0; a[0][1] += d0 * d1; a[0][2] += d0 * d2;
         a[1][1] += d1 * d1; a[1][2] += d1 * d2; a[2][2] += d2 * d2;
     }
@@ -493,23 +594,31 @@ __global__ __launch_bounds__(kBlock) void k_knn(SortJob *jobs, const PairDev *pa
 
 __global__ __launch_bounds__(kBlock) void k_gather(SortJob *jobs, const PairDev *pairs) {
     const SortJob &J = jobs[blockIdx.y];
-    if (J.kind == kJobKnnTarget) return;
+    if (J.kind == kJobKnnTarget || J.kind == kJobKnnSource) return;
     const int pos = blockIdx.x * kBlock + threadIdx.x;
     if (pos >= J.n) return;
     const PairDev &P = pairs[J.pair];
     const uint32_t p = J.idx[pos];
-    const bool src = J.kind == kJobKnnSource;
+    const bool src = J.kind == kJobOrderSource;
     const int n = J.n;
     const float *rec = src ? P.s_rec : P.t_rec;
     const float *org = src ? P.s_orig : P.t_orig;
     const float *shp = src ? P.s_shape : P.t_shape;
-    float *out = src ? P.s_sorted : P.t_sorted[J.kind - kJobStage];
+    if (src) {   // source: structure of arrays, read once per point and iteration
+        float *out = P.s_sorted;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) out[(size_t)d * n + pos] = rec[(size_t)d * n + p];
+        for (int d = 0; d < 3; ++d) out[(size_t)d * n + pos] = rec[(size_t)d * n + p];
 #pragma unroll
-    for (int e = 0; e < 6; ++e) out[(size_t)(3 + e) * n + pos] = shp[(size_t)e * n + p];
+        for (int e = 0; e < 6; ++e) out[(size_t)(3 + e) * n + pos] = shp[(size_t)e * n + p];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) out[(size_t)(9 + d) * n + pos] = org[(size_t)d * n + p];
+        for (int d = 0; d < 3; ++d) out[(size_t)(9 + d) * n + pos] = org[(size_t)d * n + p];
+    } else {     // target: 48-byte records, three float4 loads per candidate
+        float4 *out = reinterpret_cast<float4 *>(P.t_sorted[J.kind - kJobStage]) + 3 * (size_t)pos;
+        out[0] = make_float4(rec[p], rec[(size_t)n + p], rec[2 * (size_t)n + p], shp[p]);
+        out[1] = make_float4(shp[(size_t)n + p], shp[2 * (size_t)n + p], shp[3 * (size_t)n + p],
+                             shp[4 * (size_t)n + p]);
+        out[2] = make_float4(shp[5 * (size_t)n + p], org[p], org[(size_t)n + p], org[2 * (size_t)n + p]);
+    }
 }
 
 // ------------------------------------------------------------------ launcher
@@ -520,7 +629,7 @@ static void launch_knn(dim3 grid, SortJob *jobs, const PairDev *pairs, hipStream
 }
 
 hipError_t launch_prepare(PairDev *pairs, int n_pairs, int max_n, SortJob *jobs, int n_jobs, int max_job_n,
-                          int knn, hipStream_t s) {
+                          int max_cells, int knn, hipStream_t s) {
     hipLaunchKernelGGL(k_stats, dim3(2 * n_pairs), dim3(1024), 0, s, pairs);
     hipLaunchKernelGGL(k_setup, dim3((n_pairs + 63) / 64), dim3(64), 0, s, pairs, n_pairs);
     const int bx = (max_n + kBlock - 1) / kBlock;
@@ -528,9 +637,17 @@ hipError_t launch_prepare(PairDev *pairs, int n_pairs, int max_n, SortJob *jobs,
     const int jx = (max_job_n + kBlock - 1) / kBlock;
     if (n_jobs > 0 && jx > 0) {
         hipLaunchKernelGGL(k_keys, dim3(jx, n_jobs), dim3(kBlock), 0, s, jobs);
-        hipLaunchKernelGGL(k_sort, dim3(n_jobs), dim3(kSortThreads), 0, s, jobs);
+        // Every job's keys fit in 30 bits: 4 passes (a job with fewer key bits
+        // sorts stably on zero digits in its last passes).
+        const int tiles = (max_job_n + kSortTile - 1) / kSortTile;
+        for (int pass = 0; pass < 4; ++pass) {
+            hipLaunchKernelGGL(k_sort_up, dim3(tiles, n_jobs), dim3(256), 0, s, jobs, 8 * pass, pass);
+            hipLaunchKernelGGL(k_sort_scan, dim3(n_jobs), dim3(256), 0, s, jobs);
+            hipLaunchKernelGGL(k_sort_down, dim3(tiles, n_jobs), dim3(256), 0, s, jobs, 8 * pass, pass);
+        }
+        hipLaunchKernelGGL(k_cells, dim3((max_cells + kBlock) / kBlock, n_jobs), dim3(kBlock), 0, s, jobs);
         if (knn > 0) {
-            dim3 g(jx, n_jobs);
+            dim3 g((max_job_n + kPointsPerBlock - 1) / kPointsPerBlock, n_jobs);
             switch (knn) {
                 case 2: launch_knn<2>(g, jobs, pairs, s); break;
                 case 3: launch_knn<3>(g, jobs, pairs, s); break;
