@@ -105,6 +105,29 @@ def main():
     print(f"[bench] timed {args.steps} registrations in {elapsed:.3f} s; {passed} within the gate; "
           f"max err {max(e[0] for e in errs):.2e} deg {max(e[1] for e in errs):.2e} m", file=sys.stderr, flush=True)
 
+    # Batched leg: the same pairs registered together by one gcvo_register_batch
+    # call (kernels shared by all pairs, per-pair state on the device).
+    tgt_cat = torch.cat([c[0] for c in clouds]).contiguous()
+    src_cat = torch.cat([c[1] for c in clouds]).contiguous()
+    to = np.cumsum([0] + [len(s.target) for s in specs])
+    so = np.cumsum([0] + [len(s.source) for s in specs])
+    bneed = gcvo.gcvo_batch_workspace_size(to, so, params)
+    bws = gcvo.workspace(bneed, dev)
+    gcvo.gcvo_register_batch(tgt_cat, to, src_cat, so, None, params, ws=bws)
+    torch.cuda.synchronize()
+    b_calls = max(1, args.steps // N_INSTANCES)
+    tb = time.perf_counter()
+    b_out = [gcvo.gcvo_register_batch(tgt_cat, to, src_cat, so, None, params, ws=bws) for _ in range(b_calls)]
+    torch.cuda.synchronize()
+    b_elapsed = time.perf_counter() - tb
+    b_pass = sum(1 for T, infos in b_out for i in range(N_INSTANCES)
+                 if infos[i]["converged"] and rot_err_deg(T[i], refs[i]) <= 1e-3 and trans_err_m(T[i], refs[i]) <= 1e-5)
+    batch = {"pairs_per_call": N_INSTANCES, "calls": b_calls, "registrations_per_s": b_pass / b_elapsed,
+             "registrations_in_gate": b_pass, "registrations_total": b_calls * N_INSTANCES,
+             "ms_per_call": 1e3 * b_elapsed / b_calls}
+    print(f"[bench] batched: {b_calls} calls x {N_INSTANCES} pairs in {b_elapsed:.3f} s, {b_pass} within the gate",
+          file=sys.stderr, flush=True)
+
     # Roofline pass: the same steps with every pair-kernel launch bracketed by events.
     gcvo.gcvo_profile_reset()
     gcvo.gcvo_profile_enable(True)
@@ -152,7 +175,8 @@ def main():
                    "instances": N_INSTANCES, "registrations_total": args.steps,
                    "registrations_in_gate": passed, "mean_iterations": float(np.mean(iters)),
                    "kernel_pairs_per_s": pairs_per_s,
-                   "pct_fp32_valu_peak": 100.0 * achieved / FP32_VALU_PEAK_TFLOPS},
+                   "pct_fp32_valu_peak": 100.0 * achieved / FP32_VALU_PEAK_TFLOPS,
+                   "batched": batch},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": None,
                      "kernel": "k_iterate<float>", "avg_launch_us": avg_launch_us,

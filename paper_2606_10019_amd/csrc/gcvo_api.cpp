@@ -202,11 +202,11 @@ void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &p
             pl.max_cells = std::max(pl.max_cells, max_cells);
             return J;
         };
-        // cell tables: at most 16 cells per point for kNN grids and 64 for pair
-        // grids (keys stay below 2^30, the radix sort's 4 passes)
+        // cell tables: at most 16 cells per point (keys stay below 2^30, the radix
+        // sort's 4 passes)
         const int knn_cells_t = (int)std::min<long long>(16LL * nt + 64, (1 << 30) - 1);
         const int knn_cells_s = (int)std::min<long long>(16LL * ns + 64, (1 << 30) - 1);
-        const int stage_cells = (int)std::min<long long>(64LL * nt + 64, (1 << 30) - 1);
+        const int stage_cells = knn_cells_t;
         if (mode == Mode::Register || mode == Mode::Shapes) {
             SortJob J = make_job(kJobKnnTarget, nt, P.t_orig, knn_cells_t);
             J.want_shapes = 1;

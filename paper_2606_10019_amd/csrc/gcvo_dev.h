@@ -26,12 +26,12 @@ constexpr int kGroupsPerWave = 64 / kGroupLanes;
 constexpr int kPointsPerBlock = (kBlock / 64) * kGroupsPerWave;   // source points per pair-kernel block
 constexpr int kMaxRows = 64;         // pair kernel: cell rows listed per batch and point
 constexpr int kReduceSplit = 8;      // blocks per pair of the cross-block reduction
-constexpr float kPairCellFraction = 0.25f;  // pair-grid cell edge as a fraction of the cutoff
+constexpr float kPairCellFraction = 0.5f;   // pair-grid cell edge as a fraction of the cutoff
 
 // Uniform grid over an axis-aligned box.  Cell of a point p along axis d is
 // clamp(floor((p_d - lo_d) * inv_h), 0, n_d - 1); cells are numbered x-fastest.
-// The pair grid's edge is a quarter of the cutoff (grown when the box would need
-// more cells than the workspace holds); the pair kernel finds candidates with a ball
+// The pair grid's edge is half the cutoff (grown when the box would need more
+// cells than the workspace holds); the pair kernel finds candidates with a ball
 // of radius 1.001 * cutoff, which absorbs FP32 rounding of cell coordinates.
 struct Grid {
     float lo[3];
