@@ -37,12 +37,82 @@ FP32_VALU_PEAK_TFLOPS = 157.3
 N_INSTANCES = 4
 
 
+def precision_leg(gcvo, synth, golden, dev, rot_err_deg, trans_err_m, reps=2):
+    """RGB-D pair registered with FP32 pair terms and with the all-FP64 kernels;
+    time per registration and pose error of each against the oracle."""
+    import torch
+    s = synth.make_config3(0)
+    g = golden[s.name]
+    assert g["digest"] == s.digest(), f"input drift for {s.name}"
+    Tref = np.array(g["T_ref"]).reshape(4, 4)
+    tgt, src = torch.from_numpy(s.target).to(dev), torch.from_numpy(s.source).to(dev)
+    Tp = np.array(g["T_prod"]).reshape(4, 4)
+    out = {"workload": f"rgbd_room_640x480_{len(s.target)}pts_anneal0.2to0.025",
+           "oracle_production_tol": {"rot_err_deg": rot_err_deg(Tp, Tref), "trans_err_m": trans_err_m(Tp, Tref)}}
+    for name, prec in (("fp32", gcvo.GCVO_PRECISION_FP32), ("fp64", gcvo.GCVO_PRECISION_FP64)):
+        p = gcvo.params_from_spec(s, precision=prec)
+        need = gcvo.gcvo_workspace_size(len(s.target), len(s.source), p)
+        ws = gcvo.workspace(need, dev)
+        gcvo.gcvo_register(tgt, src, None, p, ws=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            T, info = gcvo.gcvo_register(tgt, src, None, p, ws=ws)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out[name] = {"ms_per_registration": 1e3 * dt, "iters": info["iters"], "converged": bool(info["converged"]),
+                     "rot_err_deg": rot_err_deg(T, Tref), "trans_err_m": trans_err_m(T, Tref)}
+        print(f"[bench] precision {name}: {1e3 * dt:.2f} ms, {info['iters']} iters, err "
+              f"{out[name]['rot_err_deg']:.2e} deg {out[name]['trans_err_m']:.2e} m", file=sys.stderr, flush=True)
+    return out
+
+
+def objects_leg(gcvo, synth, golden, dev, rot_err_deg, trans_err_m, n_pairs=256):
+    """The 256 object pairs (1k-50k points each) registered by one batch call;
+    pairs of the oracle-checked sample are gated, the rest reported as converged."""
+    import torch
+    t0 = time.perf_counter()
+    specs = [synth.make_config4(i) for i in range(n_pairs)]
+    print(f"[bench] objects: generated {n_pairs} pairs ({sum(len(s.source) for s in specs)} source points) in "
+          f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    tgt = torch.from_numpy(np.concatenate([s.target for s in specs])).to(dev)
+    src = torch.from_numpy(np.concatenate([s.source for s in specs])).to(dev)
+    to = np.cumsum([0] + [len(s.target) for s in specs])
+    so = np.cumsum([0] + [len(s.source) for s in specs])
+    params = [gcvo.params_from_spec(s) for s in specs]
+    ws = gcvo.workspace(gcvo.gcvo_batch_workspace_size(to, so, params), dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    T, infos = gcvo.gcvo_register_batch(tgt, to, src, so, None, params, ws=ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    converged = sum(1 for i in infos if i["converged"])
+    sample, in_gate = 0, 0
+    for k, s in enumerate(specs):
+        g = golden.get(s.name)
+        if g is None or not (g["prod_converged"] and g["ref_converged"]):
+            continue
+        sample += 1
+        Tref = np.array(g["T_ref"]).reshape(4, 4)
+        if infos[k]["converged"] and rot_err_deg(T[k], Tref) <= 1e-3 and trans_err_m(T[k], Tref) <= 1e-5:
+            in_gate += 1
+    out = {"pairs": n_pairs, "seconds_per_batch": dt, "converged": converged,
+           "registrations_per_s_converged": converged / dt, "oracle_sample": sample, "oracle_sample_in_gate": in_gate,
+           "mean_iterations": float(np.mean([i["iters"] for i in infos]))}
+    print(f"[bench] objects: {dt:.2f} s for {n_pairs} pairs, {converged} converged, oracle sample "
+          f"{in_gate}/{sample} in gate", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision", action="store_true", help="skip the RGB-D FP32/FP64 precision leg")
+    ap.add_argument("--objects", action="store_true",
+                    help="add the 256 object-pair batch leg (one gcvo_register_batch call)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -107,26 +177,30 @@ def main():
 
     # Batched leg: the same pairs registered together by one gcvo_register_batch
     # call (kernels shared by all pairs, per-pair state on the device).
-    tgt_cat = torch.cat([c[0] for c in clouds]).contiguous()
-    src_cat = torch.cat([c[1] for c in clouds]).contiguous()
-    to = np.cumsum([0] + [len(s.target) for s in specs])
-    so = np.cumsum([0] + [len(s.source) for s in specs])
-    bneed = gcvo.gcvo_batch_workspace_size(to, so, params)
-    bws = gcvo.workspace(bneed, dev)
-    gcvo.gcvo_register_batch(tgt_cat, to, src_cat, so, None, params, ws=bws)
-    torch.cuda.synchronize()
-    b_calls = max(1, args.steps // N_INSTANCES)
-    tb = time.perf_counter()
-    b_out = [gcvo.gcvo_register_batch(tgt_cat, to, src_cat, so, None, params, ws=bws) for _ in range(b_calls)]
-    torch.cuda.synchronize()
-    b_elapsed = time.perf_counter() - tb
-    b_pass = sum(1 for T, infos in b_out for i in range(N_INSTANCES)
-                 if infos[i]["converged"] and rot_err_deg(T[i], refs[i]) <= 1e-3 and trans_err_m(T[i], refs[i]) <= 1e-5)
-    batch = {"pairs_per_call": N_INSTANCES, "calls": b_calls, "registrations_per_s": b_pass / b_elapsed,
-             "registrations_in_gate": b_pass, "registrations_total": b_calls * N_INSTANCES,
-             "ms_per_call": 1e3 * b_elapsed / b_calls}
-    print(f"[bench] batched: {b_calls} calls x {N_INSTANCES} pairs in {b_elapsed:.3f} s, {b_pass} within the gate",
-          file=sys.stderr, flush=True)
+    batch = None
+    if not args.no_batched:
+        tgt_cat = torch.cat([c[0] for c in clouds]).contiguous()
+        src_cat = torch.cat([c[1] for c in clouds]).contiguous()
+        to = np.cumsum([0] + [len(s.target) for s in specs])
+        so = np.cumsum([0] + [len(s.source) for s in specs])
+        bws = gcvo.workspace(gcvo.gcvo_batch_workspace_size(to, so, params), dev)
+        gcvo.gcvo_register_batch(tgt_cat, to, src_cat, so, None, params, ws=bws)
+        torch.cuda.synchronize()
+        b_calls = max(1, args.steps // N_INSTANCES)
+        tb = time.perf_counter()
+        b_out = [gcvo.gcvo_register_batch(tgt_cat, to, src_cat, so, None, params, ws=bws) for _ in range(b_calls)]
+        torch.cuda.synchronize()
+        b_elapsed = time.perf_counter() - tb
+        b_pass = sum(1 for T, infos in b_out for i in range(N_INSTANCES) if infos[i]["converged"]
+                     and rot_err_deg(T[i], refs[i]) <= 1e-3 and trans_err_m(T[i], refs[i]) <= 1e-5)
+        batch = {"pairs_per_call": N_INSTANCES, "calls": b_calls, "registrations_per_s": b_pass / b_elapsed,
+                 "registrations_in_gate": b_pass, "registrations_total": b_calls * N_INSTANCES,
+                 "ms_per_call": 1e3 * b_elapsed / b_calls}
+        print(f"[bench] batched: {b_calls} calls x {N_INSTANCES} pairs in {b_elapsed:.3f} s, {b_pass} within the "
+              "gate", file=sys.stderr, flush=True)
+
+    precision = None if args.no_precision else precision_leg(gcvo, synth, golden, dev, rot_err_deg, trans_err_m)
+    objects = objects_leg(gcvo, synth, golden, dev, rot_err_deg, trans_err_m) if args.objects else None
 
     # Roofline pass: the same steps with every pair-kernel launch bracketed by events.
     gcvo.gcvo_profile_reset()
@@ -176,7 +250,7 @@ def main():
                    "registrations_in_gate": passed, "mean_iterations": float(np.mean(iters)),
                    "kernel_pairs_per_s": pairs_per_s,
                    "pct_fp32_valu_peak": 100.0 * achieved / FP32_VALU_PEAK_TFLOPS,
-                   "batched": batch},
+                   "batched": batch, "precision": precision, "objects": objects},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": None,
                      "kernel": "k_iterate<float>", "avg_launch_us": avg_launch_us,

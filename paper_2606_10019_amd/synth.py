@@ -286,8 +286,288 @@ def make_config2(instance: int = 0, voxel: float = 0.3, forward_m: float = 1.0,
                     extra=dict(voxel=voxel))
 
 
-CONFIGS = {1: make_config1, 2: make_config2}
+# --------------------------------------------------------------------------
+# Configuration 3: 640x480 pinhole depth camera in a 6 x 5 x 3 m room with
+# boxes and spheres, depth noise 0.0015 z^2, voxel size bisected to ~20k points.
+# --------------------------------------------------------------------------
+
+@dataclass
+class RoomScene:
+    box_lo: np.ndarray
+    box_hi: np.ndarray
+    sph_c: np.ndarray
+    sph_r: np.ndarray
+
+
+def make_room_scene(rng: np.random.Generator, keep_clear: np.ndarray, n_boxes: int = 20,
+                    n_spheres: int = 20) -> RoomScene:
+    """Boxes (sides U[0.2, 1] m) rest on the floor, spheres (r U[0.1, 0.5] m)
+    float at random heights; objects within 0.5 m of a camera are redrawn."""
+    lo, hi = [], []
+    while len(lo) < n_boxes:
+        side = rng.uniform(0.2, 1.0, size=3)
+        c = rng.uniform([0.0, 0.0], [6.0, 5.0])
+        blo = np.array([c[0] - side[0] / 2, c[1] - side[1] / 2, 0.0])
+        bhi = np.array([c[0] + side[0] / 2, c[1] + side[1] / 2, side[2]])
+        d = np.maximum(0.0, np.maximum(blo[None] - keep_clear, keep_clear - bhi[None]))
+        if np.min(np.linalg.norm(d, axis=1)) < 0.5:
+            continue
+        lo.append(blo)
+        hi.append(bhi)
+    cc, rr = [], []
+    while len(cc) < n_spheres:
+        r = rng.uniform(0.1, 0.5)
+        c = rng.uniform([r, r, r], [6.0 - r, 5.0 - r, 3.0 - r])
+        if np.min(np.linalg.norm(keep_clear - c[None], axis=1)) - r < 0.5:
+            continue
+        cc.append(c)
+        rr.append(r)
+    return RoomScene(np.array(lo), np.array(hi), np.array(cc), np.array(rr))
+
+
+def _slab_hits(lo, hi, origin, dirs, inv):
+    t0 = (lo[None] - origin[None]) * inv
+    t1 = (hi[None] - origin[None]) * inv
+    tn = np.max(np.minimum(t0, t1), axis=1)
+    tf = np.min(np.maximum(t0, t1), axis=1)
+    return tn, tf
+
+
+def room_depth_rays(scene: RoomScene, origin: np.ndarray, dirs: np.ndarray) -> np.ndarray:
+    """Distance along unit rays from a camera inside the room to the first surface."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        inv = np.where(np.abs(dirs) > 1e-15, 1.0 / np.where(np.abs(dirs) > 1e-15, dirs, 1.0), 1e30)
+    # room interior: exit distance through the walls, floor and ceiling
+    _, best = _slab_hits(np.zeros(3), np.array([6.0, 5.0, 3.0]), origin, dirs, inv)
+    for lo, hi in zip(scene.box_lo, scene.box_hi):
+        tn, tf = _slab_hits(lo, hi, origin, dirs, inv)
+        hit = (tf >= tn) & (tn > 0)
+        best = np.where(hit & (tn < best), tn, best)
+    for c, r in zip(scene.sph_c, scene.sph_r):
+        oc = origin - c
+        b = dirs @ oc
+        disc = b * b - (oc @ oc - r * r)
+        ok = disc >= 0
+        t = -b - np.sqrt(np.where(ok, disc, 0.0))
+        hit = ok & (t > 0)
+        best = np.where(hit & (t < best), t, best)
+    return best
+
+
+def depth_view(scene: RoomScene, cam_pose: np.ndarray, rng: np.random.Generator, width: int = 640,
+               height: int = 480, f: float = 525.0, noise_k: float = 0.0015) -> np.ndarray:
+    """Back-projected depth image in the camera frame (x right, y down, z forward)."""
+    u, v = np.meshgrid(np.arange(width, dtype=np.float64), np.arange(height, dtype=np.float64))
+    cx, cy = (width - 1) / 2.0, (height - 1) / 2.0
+    d_c = np.stack([(u - cx) / f, (v - cy) / f, np.ones_like(u)], -1).reshape(-1, 3)
+    norm = np.linalg.norm(d_c, axis=1)
+    d_w = (d_c / norm[:, None]) @ cam_pose[:3, :3].T
+    t = room_depth_rays(scene, cam_pose[:3, 3], d_w)
+    z = t / norm                                   # depth along the optical axis
+    z = z + rng.normal(0.0, 1.0, size=z.shape) * noise_k * z * z
+    keep = np.isfinite(z) & (z > 0.1)
+    return d_c[keep] * z[keep, None]
+
+
+def voxel_to_count(P: np.ndarray, target: int, lo: float = 0.002, hi: float = 0.5) -> float:
+    """Voxel size (bisection) whose centroid downsampling leaves about `target` points."""
+    for _ in range(30):
+        mid = np.sqrt(lo * hi)
+        if len(voxel_centroids(P, mid)) > target:
+            lo = mid
+        else:
+            hi = mid
+    return np.sqrt(lo * hi)
+
+
+def make_config3(instance: int = 0, target_points: int = 20000, trans_m: float = 0.05,
+                 angle_deg: float = 3.0) -> PairSpec:
+    """RGB-D pair: X = view 1, Z = view 2 after motion M (camera frame); T = M^{-1}."""
+    rng = rng_for(3, instance)
+    R_wc = np.array([[0.0, 0.0, 1.0], [-1.0, 0.0, 0.0], [0.0, -1.0, 0.0]])   # camera z -> world +x
+    C1 = rigid(R_wc, [1.0, 2.5, 1.5])
+    M = rigid(rotation_about(random_unit(rng), np.deg2rad(angle_deg)), trans_m * random_unit(rng))
+    C2 = C1 @ M
+    scene = make_room_scene(rng, np.array([C1[:3, 3], C2[:3, 3]]))
+    P1 = depth_view(scene, C1, rng)
+    P2 = depth_view(scene, C2, rng)
+    vox = voxel_to_count(P1, target_points)
+    x = voxel_centroids(P1, vox)
+    z = voxel_centroids(P2, vox)
+    return PairSpec(name=f"c3_rgbd_{instance}", target=np.ascontiguousarray(x, np.float32),
+                    source=np.ascontiguousarray(z, np.float32), G=M, length_scale=0.2,
+                    length_scale_min=0.025, anneal_factor=0.5, eig_ratio_min=0.01, max_iters=150,
+                    max_iters_per_stage=40, extra=dict(voxel=vox))
+
+
+
+
+# --------------------------------------------------------------------------
+# Configuration 4: object-scale pairs (unions of 1-4 primitives), uneven sizes.
+# --------------------------------------------------------------------------
+
+PRIMITIVES = ("box", "cylinder", "torus", "ellipsoid")
+
+
+def _uniform_rotation(rng: np.random.Generator) -> np.ndarray:
+    q = rng.normal(size=4)
+    return Rotation.from_quat(q / np.linalg.norm(q)).as_matrix()
+
+
+def _primitive_area(kind: str, dims: np.ndarray) -> float:
+    if kind == "box":
+        a, b, c = dims
+        return 2.0 * (a * b + b * c + a * c)
+    if kind == "cylinder":
+        r, h = dims[:2]
+        return 2.0 * np.pi * r * (r + h)
+    if kind == "torus":
+        R, r = dims[:2]
+        return 4.0 * np.pi ** 2 * R * r
+    a, b, c = dims                                          # ellipsoid: Monte-Carlo area
+    n = np.random.default_rng(0).normal(size=(20000, 3))
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    g = np.sqrt((b * c * n[:, 0]) ** 2 + (a * c * n[:, 1]) ** 2 + (a * b * n[:, 2]) ** 2)
+    return 4.0 * np.pi * float(np.mean(g))
+
+
+def _sample_primitive(rng: np.random.Generator, kind: str, dims: np.ndarray, n: int) -> np.ndarray:
+    """n area-uniform points on the closed surface of a primitive in its own frame."""
+    if n == 0:
+        return np.zeros((0, 3))
+    if kind == "box":
+        ext = dims
+        face_area = np.array([ext[1] * ext[2], ext[0] * ext[2], ext[0] * ext[1]])
+        face = rng.choice(6, size=n, p=np.repeat(face_area, 2) / (2.0 * face_area.sum()))
+        P = (rng.uniform(size=(n, 3)) - 0.5) * ext
+        ax = face // 2
+        P[np.arange(n), ax] = np.where(face % 2 == 1, 0.5, -0.5) * ext[ax]
+        return P
+    if kind == "cylinder":
+        r, h = dims[:2]
+        side = rng.uniform(size=n) < h / (h + r)                 # lateral 2 pi r h vs caps 2 pi r^2
+        th = rng.uniform(0.0, 2.0 * np.pi, size=n)
+        rad = np.where(side, r, r * np.sqrt(rng.uniform(size=n)))
+        zc = np.where(rng.uniform(size=n) < 0.5, -h / 2, h / 2)
+        z = np.where(side, rng.uniform(-h / 2, h / 2, size=n), zc)
+        return np.stack([rad * np.cos(th), rad * np.sin(th), z], 1)
+    if kind == "torus":
+        R, r = dims[:2]
+        out = []
+        while sum(len(o) for o in out) < n:
+            m = 2 * n
+            phi = rng.uniform(0.0, 2.0 * np.pi, size=m)
+            keep = rng.uniform(size=m) * (R + r) <= R + r * np.cos(phi)
+            th = rng.uniform(0.0, 2.0 * np.pi, size=m)
+            w = R + r * np.cos(phi)
+            out.append(np.stack([w * np.cos(th), w * np.sin(th), r * np.sin(phi)], 1)[keep])
+        return np.concatenate(out)[:n]
+    a, b, c = dims
+    gmax = max(b * c, a * c, a * b)
+    out = []
+    while sum(len(o) for o in out) < n:
+        m = 2 * n
+        u = rng.normal(size=(m, 3))
+        u /= np.linalg.norm(u, axis=1, keepdims=True)
+        g = np.sqrt((b * c * u[:, 0]) ** 2 + (a * c * u[:, 1]) ** 2 + (a * b * u[:, 2]) ** 2)
+        keep = rng.uniform(size=m) * gmax <= g
+        out.append((u * np.array([a, b, c]))[keep])
+    return np.concatenate(out)[:n]
+
+
+@dataclass
+class ObjectScene:
+    kinds: list
+    dims: list
+    poses: list
+    areas: np.ndarray
+
+
+def make_object_scene(rng: np.random.Generator) -> ObjectScene:
+    """1-4 primitives, characteristic size s ~ U[0.2, 1] m, uniformly random
+    orientation, centre uniform in the unit cube."""
+    k = int(rng.integers(1, 5))
+    kinds, dims, poses = [], [], []
+    for _ in range(k):
+        kind = PRIMITIVES[int(rng.integers(0, 4))]
+        s = rng.uniform(0.2, 1.0)
+        if kind == "box":
+            d = s * rng.uniform(0.3, 1.0, size=3)
+        elif kind == "cylinder":
+            d = np.array([s * rng.uniform(0.15, 0.5), s * rng.uniform(0.5, 1.0), 0.0])
+        elif kind == "torus":
+            R = s * rng.uniform(0.3, 0.5)
+            d = np.array([R, R * rng.uniform(0.2, 0.5), 0.0])
+        else:
+            d = 0.5 * s * rng.uniform(0.3, 1.0, size=3)
+        kinds.append(kind)
+        dims.append(d)
+        poses.append(rigid(_uniform_rotation(rng), rng.uniform(0.0, 1.0, size=3)))
+    areas = np.array([_primitive_area(kd, d) for kd, d in zip(kinds, dims)])
+    return ObjectScene(kinds, dims, poses, areas)
+
+
+def sample_object_cloud(scene: ObjectScene, rng: np.random.Generator, n: int, noise: float,
+                        outlier_frac: float) -> np.ndarray:
+    """n points: area-weighted surface samples of the union with iid Gaussian
+    noise, of which a fraction is replaced by uniform outliers in the cloud's
+    bounding box; rows in random order."""
+    n_out = int(round(outlier_frac * n))
+    counts = rng.multinomial(n - n_out, scene.areas / scene.areas.sum())
+    parts = [transform_points(T, _sample_primitive(rng, kd, d, int(c)))
+             for kd, d, T, c in zip(scene.kinds, scene.dims, scene.poses, counts)]
+    P = np.concatenate(parts) + rng.normal(0.0, noise, size=(n - n_out, 3))
+    lo, hi = P.min(0), P.max(0)
+    P = np.concatenate([P, rng.uniform(lo, hi, size=(n_out, 3))])
+    return P[rng.permutation(n)]
+
+
+def median_nn_spacing(P: np.ndarray) -> float:
+    from scipy.spatial import cKDTree
+    d, _ = cKDTree(P).query(P, k=2)
+    return float(np.median(d[:, 1]))
+
+
+def make_config4(instance: int = 0, n: int | None = None, n_lo: int = 1000, n_hi: int = 50000,
+                 noise: float = 0.005, outlier_frac: float = 0.1, max_angle_deg: float = 30.0,
+                 max_trans_m: float = 0.2) -> PairSpec:
+    """Object pair `instance` of the batch: independent source/target samples of
+    one random union of primitives, N ~ U{n_lo..n_hi} (same N for both clouds);
+    target x = G p with G a rotation of U[0, 30] deg about a uniform axis through
+    the unit cube's centre followed by a translation of U[0, 0.2] m."""
+    rng = rng_for(4, instance)
+    scene = make_object_scene(rng)
+    N = int(rng.integers(n_lo, n_hi + 1))
+    N = N if n is None else int(n)
+    angle = np.deg2rad(rng.uniform(0.0, max_angle_deg))
+    Rg = rotation_about(random_unit(rng), angle)
+    tg = rng.uniform(0.0, max_trans_m) * random_unit(rng)
+    c0 = np.full(3, 0.5)
+    G = rigid(Rg, c0 - Rg @ c0 + tg)
+    z = sample_object_cloud(scene, rng, N, noise, outlier_frac)
+    x = transform_points(G, sample_object_cloud(scene, rng, N, noise, outlier_frac))
+    x32 = np.ascontiguousarray(x, np.float32)
+    ell_min = max(0.01, 2.0 * median_nn_spacing(x32.astype(np.float64)))
+    return PairSpec(name=f"c4_objects_{instance}" + ("" if n is None else f"_n{N}"), target=x32,
+                    source=np.ascontiguousarray(z, np.float32), G=G, length_scale=0.2,
+                    length_scale_min=min(0.2, ell_min), anneal_factor=0.5, eig_ratio_min=0.01,
+                    max_iters=200, max_iters_per_stage=40,
+                    extra=dict(kinds=list(scene.kinds), angle_deg=float(np.rad2deg(angle))))
+
+
+def config4_sizes(n_pairs: int = 256, n_lo: int = 1000, n_hi: int = 50000) -> list:
+    """Point counts of the first n_pairs object pairs without building clouds
+    (replays each pair's scene draws, then its size draw)."""
+    out = []
+    for i in range(n_pairs):
+        rng = rng_for(4, i)
+        make_object_scene(rng)
+        out.append(int(rng.integers(n_lo, n_hi + 1)))
+    return out
 
 
 def make_pair(config: int, instance: int = 0) -> PairSpec:
     return CONFIGS[config](instance)
+
+
+CONFIGS = {1: make_config1, 2: make_config2, 3: make_config3, 4: make_config4}

@@ -25,7 +25,11 @@ from oracle import oracle as O  # noqa: E402
 from paper_2606_10019_amd import synth  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_poses.json")
-INSTANCES = {1: range(8), 2: range(4)}
+# Object pairs: the oracle-checked sample of the 256-pair batch is every pair
+# whose natural size is at most 4000 points.
+C4_SAMPLE_MAX_N = 4000
+INSTANCES = {1: range(8), 2: range(4), 3: range(2),
+             4: [i for i, n in enumerate(synth.config4_sizes()) if n <= C4_SAMPLE_MAX_N]}
 
 
 def rot_err_deg(Ta, Tb):
