@@ -286,6 +286,32 @@ def make_config2(instance: int = 0, voxel: float = 0.3, forward_m: float = 1.0,
                     extra=dict(voxel=voxel))
 
 
+C5_EVAL_OFFSET = 500_000
+
+
+def make_config5(instance: int = 0, split: str = "train", max_trans_m: float = 3.0,
+                 max_yaw_deg: float = 15.0, voxel: float = 0.3, sensor_height: float = 1.8) -> PairSpec:
+    """LiDAR pair with a large ego motion (warm-start workload): the config-2
+    scene and scanner, scan 2 after a yaw of U[-15, 15] deg and a planar
+    translation of U[0, 3] m in a uniform direction.  Training and evaluation
+    instances draw from disjoint seeds.  Expected T = M^{-1}."""
+    rng = rng_for(5, instance + (C5_EVAL_OFFSET if split == "eval" else 0))
+    S1 = rigid(np.eye(3), [0.0, 0.0, sensor_height])
+    yaw = np.deg2rad(rng.uniform(-max_yaw_deg, max_yaw_deg))
+    phi = rng.uniform(0.0, 2.0 * np.pi)
+    d = rng.uniform(0.0, max_trans_m)
+    M = rigid(rotation_about(np.array([0.0, 0.0, 1.0]), yaw), [d * np.cos(phi), d * np.sin(phi), 0.0])
+    S2 = S1 @ M
+    scene = make_lidar_scene(rng, np.array([S1[:2, 3], S2[:2, 3]]))
+    x = voxel_centroids(lidar_scan(scene, S1, rng), voxel)
+    z = voxel_centroids(lidar_scan(scene, S2, rng), voxel)
+    return PairSpec(name=f"c5_{split}_{instance}", target=np.ascontiguousarray(x, np.float32),
+                    source=np.ascontiguousarray(z, np.float32), G=M,
+                    length_scale=1.0, length_scale_min=0.1, anneal_factor=0.5,
+                    eig_ratio_min=0.1, max_iters=200, max_iters_per_stage=60,
+                    extra=dict(voxel=voxel, yaw_deg=float(np.rad2deg(yaw)), trans_m=float(d)))
+
+
 # --------------------------------------------------------------------------
 # Configuration 3: 640x480 pinhole depth camera in a 6 x 5 x 3 m room with
 # boxes and spheres, depth noise 0.0015 z^2, voxel size bisected to ~20k points.
@@ -570,4 +596,4 @@ def make_pair(config: int, instance: int = 0) -> PairSpec:
     return CONFIGS[config](instance)
 
 
-CONFIGS = {1: make_config1, 2: make_config2, 3: make_config3, 4: make_config4}
+CONFIGS = {1: make_config1, 2: make_config2, 3: make_config3, 4: make_config4, 5: make_config5}
