@@ -8,8 +8,8 @@ The paper has no learned component (it warm-starts only from a constant
 velocity model and names learning as future work, Sec. Conclusion); this
 network is the project's own addition, and this module is its definition:
 
-  per cloud, for each of its P input points p (already gathered, the source
-  moved by its per-pair motion, everything divided by the input scale):
+  per cloud, for each of its P input points p (already gathered, moved by the
+  cloud's per-pair motion if it has one, divided by the input scale):
       h1 = relu(W1 p + b1)            3 -> 64
       h2 = relu(W2 h1 + b2)           64 -> 128
       g  = max over the P points of h2, per channel
@@ -65,19 +65,21 @@ def cloud_feature(P: np.ndarray, p: dict):
     return g, arg, pre1, h1, pre2
 
 
-def gather_inputs(src_clouds, tgt_clouds, src_idx, tgt_idx, src_motion, input_scale):
-    """Input points of each pair: the chosen rows of each cloud; the source rows
-    moved by the pair's 3x4 motion [R | t] (p -> R p + t); all divided by the
-    input scale."""
+def gather_inputs(src_clouds, tgt_clouds, src_idx, tgt_idx, src_motion, input_scale, tgt_motion=None):
+    """Input points of each pair: the chosen rows of each cloud, moved by the
+    pair's 3x4 motion [R | t] for that cloud (p -> R p + t) when one is given,
+    then divided by the input scale."""
+    def pick(cloud, idx, motion):
+        P = np.asarray(cloud, np.float64)[np.asarray(idx)]
+        if motion is not None:
+            M = np.asarray(motion, np.float64).reshape(3, 4)
+            P = P @ M[:, :3].T + M[:, 3]
+        return P / input_scale
+
     S, T = [], []
     for b in range(len(src_clouds)):
-        zs = np.asarray(src_clouds[b], np.float64)[np.asarray(src_idx[b])]
-        if src_motion is not None:
-            M = np.asarray(src_motion[b], np.float64).reshape(3, 4)
-            zs = zs @ M[:, :3].T + M[:, 3]
-        xs = np.asarray(tgt_clouds[b], np.float64)[np.asarray(tgt_idx[b])]
-        S.append(zs / input_scale)
-        T.append(xs / input_scale)
+        S.append(pick(src_clouds[b], src_idx[b], None if src_motion is None else src_motion[b]))
+        T.append(pick(tgt_clouds[b], tgt_idx[b], None if tgt_motion is None else tgt_motion[b]))
     return S, T
 
 

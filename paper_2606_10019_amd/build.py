@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libgcvo.so")
-SOURCES = ["gcvo_prep.hip", "gcvo_iter.hip", "gcvo_api.cpp"]
+SOURCES = ["gcvo_prep.hip", "gcvo_iter.hip", "gcvo_api.cpp", "gcvo_mlp.hip"]
 ARCH = "gfx950"
 
 HIP_FLAGS = [

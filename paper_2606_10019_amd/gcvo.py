@@ -35,7 +35,13 @@ GCVO_MAX_STAGES = 16
 EXPORTED = ["gcvo_default_params", "gcvo_workspace_size", "gcvo_register", "gcvo_batch_workspace_size",
             "gcvo_register_batch", "gcvo_eval_workspace_size", "gcvo_eval_fgh", "gcvo_shapes_workspace_size",
             "gcvo_point_shapes", "gcvo_strerror", "gcvo_abi_version", "gcvo_profile_enable",
-            "gcvo_profile_reset", "gcvo_profile_read"]
+            "gcvo_profile_reset", "gcvo_profile_read",
+            "gcvo_mlp_param_count", "gcvo_mlp_workspace_size", "gcvo_mlp_forward", "gcvo_mlp_loss_grad",
+            "gcvo_mlp_adam"]
+
+GCVO_MLP_N_PARAMS = 42246
+GCVO_MLP_ROT_SCALE = 0.3
+GCVO_MLP_TRANS_SCALE = 3.0
 
 
 class gcvo_params(ctypes.Structure):
@@ -56,6 +62,17 @@ class gcvo_info(ctypes.Structure):
         return dict(status=self.status, converged=bool(self.converged), iters=self.iters, stages=self.stages,
                     pairs_last=self.pairs_last, f=self.f, g=list(self.g), xi_l1=self.xi_l1,
                     stage_iters=list(self.stage_iters)[:max(self.stages, 0)])
+
+
+class gcvo_mlp_batch(ctypes.Structure):
+    _fields_ = [("n_pairs", ctypes.c_int), ("n_points", ctypes.c_int),
+                ("tgt_xyz", ctypes.c_void_p), ("n_tgt_rows", ctypes.c_longlong),
+                ("tgt_start", ctypes.c_void_p), ("tgt_count", ctypes.c_void_p),
+                ("src_xyz", ctypes.c_void_p), ("n_src_rows", ctypes.c_longlong),
+                ("src_start", ctypes.c_void_p), ("src_count", ctypes.c_void_p),
+                ("tgt_idx", ctypes.c_void_p), ("src_idx", ctypes.c_void_p),
+                ("tgt_motion", ctypes.c_void_p), ("src_motion", ctypes.c_void_p),
+                ("input_scale", ctypes.c_float)]
 
 
 class GcvoError(RuntimeError):
@@ -105,6 +122,15 @@ def load_library() -> ctypes.CDLL:
     L.gcvo_profile_reset.restype = None
     L.gcvo_profile_read.argtypes = [_P, _P, _P, _P]
     L.gcvo_profile_read.restype = None
+    L.gcvo_mlp_param_count.argtypes = []
+    L.gcvo_mlp_param_count.restype = ctypes.c_longlong
+    L.gcvo_mlp_workspace_size.argtypes = [ctypes.c_int, ctypes.c_int]
+    L.gcvo_mlp_workspace_size.restype = ctypes.c_size_t
+    bp = ctypes.POINTER(gcvo_mlp_batch)
+    L.gcvo_mlp_forward.argtypes = [bp, _P, _P, _P, _P, ctypes.c_size_t, _P]
+    L.gcvo_mlp_loss_grad.argtypes = [bp, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
+    L.gcvo_mlp_adam.argtypes = [_P, _P, _P, _P, _P, ctypes.c_longlong, ctypes.c_int, ctypes.c_float,
+                                ctypes.c_float, ctypes.c_float, ctypes.c_float, _P]
     _lib = L
     return L
 
@@ -324,3 +350,98 @@ def gcvo_profile_read() -> dict:
     load_library().gcvo_profile_read(ctypes.byref(ms), ctypes.byref(launches), ctypes.byref(pairs),
                                      ctypes.byref(points))
     return dict(pair_kernel_ms=ms.value, launches=launches.value, pairs=pairs.value, source_points=points.value)
+
+
+# ------------------------------------------------------------ warm-start network
+
+class MlpBatch:
+    """Inputs of one network call: two device clouds with the host row ranges
+    (start, count) of every sample's target and source, device int32 row
+    indices [B, P] within those ranges, optional device float32 target and
+    source motions [B, 12], and the input scale in metres.  Holds references to every array it
+    points at."""
+
+    def __init__(self, targets, tgt_start, tgt_count, sources, src_start, src_count, tgt_idx, src_idx,
+                 tgt_motion=None, src_motion=None, input_scale: float = 20.0):
+        torch = _torch()
+        self.targets = _cloud(targets, "targets")
+        self.sources = _cloud(sources, "sources")
+        self.ranges = [np.ascontiguousarray(a, dtype=np.int64) for a in (tgt_start, tgt_count, src_start, src_count)]
+        B = len(self.ranges[0])
+        if any(len(r) != B for r in self.ranges):
+            raise TypeError("row ranges must all have one entry per sample")
+        for name, t in (("tgt_idx", tgt_idx), ("src_idx", src_idx)):
+            if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.int32 or t.dim() != 2 \
+                    or t.shape[0] != B:
+                raise TypeError(f"{name} must be an int32 CUDA tensor [{B}, P]")
+        self.tgt_idx = tgt_idx.contiguous()
+        self.src_idx = src_idx.contiguous()
+        if self.tgt_idx.shape != self.src_idx.shape:
+            raise TypeError("tgt_idx and src_idx must have the same shape")
+        self.motions = []
+        for name, m in (("tgt_motion", tgt_motion), ("src_motion", src_motion)):
+            if m is not None and (not m.is_cuda or m.dtype != torch.float32 or tuple(m.shape) != (B, 12)):
+                raise TypeError(f"{name} must be a float32 CUDA tensor [{B}, 12]")
+            self.motions.append(m.contiguous() if m is not None else None)
+        r = self.ranges
+        self.c = gcvo_mlp_batch(B, int(self.tgt_idx.shape[1]), self.targets.data_ptr(), self.targets.shape[0],
+                                r[0].ctypes.data, r[1].ctypes.data, self.sources.data_ptr(), self.sources.shape[0],
+                                r[2].ctypes.data, r[3].ctypes.data, self.tgt_idx.data_ptr(), self.src_idx.data_ptr(),
+                                *[m.data_ptr() if m is not None else None for m in self.motions],
+                                float(input_scale))
+
+    @property
+    def n_pairs(self) -> int:
+        return self.c.n_pairs
+
+
+def gcvo_mlp_workspace_size(n_pairs: int, n_points: int) -> int:
+    return int(load_library().gcvo_mlp_workspace_size(int(n_pairs), int(n_points)))
+
+
+def gcvo_mlp_forward(batch: MlpBatch, w_bf16, poses: bool = False, ws=None, stream=None):
+    """Network outputs (float32 CUDA [B, 6]) and, with poses=True, the predicted
+    poses exp(xi^) as a float64 numpy [B, 4, 4] array."""
+    torch = _torch()
+    L = load_library()
+    B, P = batch.c.n_pairs, batch.c.n_points
+    out = torch.empty((B, 6), dtype=torch.float32, device=batch.targets.device)
+    holder, wptr, wbytes = ws if ws is not None else workspace(max(gcvo_mlp_workspace_size(B, P), 256),
+                                                              batch.targets.device)
+    T = np.zeros((B, 4, 4)) if poses else None
+    st = L.gcvo_mlp_forward(ctypes.byref(batch.c), _ptr(w_bf16), _ptr(out),
+                            T.ctypes.data_as(_P) if T is not None else None, ctypes.c_void_p(wptr), wbytes,
+                            _stream_handle(stream))
+    del holder
+    if st != GCVO_OK:
+        raise GcvoError(st, "gcvo_mlp_forward")
+    return (out, T) if poses else out
+
+
+def gcvo_mlp_loss_grad(batch: MlpBatch, w_bf16, y6, grad=None, loss=None, out6=None, ws=None, stream=None):
+    """Loss (float32 CUDA [1]) and gradient (float32 CUDA [n_params])."""
+    torch = _torch()
+    L = load_library()
+    dev = batch.targets.device
+    B, P = batch.c.n_pairs, batch.c.n_points
+    if not y6.is_cuda or y6.dtype != torch.float32 or tuple(y6.shape) != (B, 6):
+        raise TypeError(f"y6 must be a float32 CUDA tensor [{B}, 6]")
+    y6 = y6.contiguous()
+    grad = grad if grad is not None else torch.empty(GCVO_MLP_N_PARAMS, dtype=torch.float32, device=dev)
+    loss = loss if loss is not None else torch.empty(1, dtype=torch.float32, device=dev)
+    holder, wptr, wbytes = ws if ws is not None else workspace(max(gcvo_mlp_workspace_size(B, P), 256), dev)
+    st = L.gcvo_mlp_loss_grad(ctypes.byref(batch.c), _ptr(w_bf16), _ptr(y6), _ptr(out6), _ptr(loss), _ptr(grad),
+                              ctypes.c_void_p(wptr), wbytes, _stream_handle(stream))
+    del holder
+    if st != GCVO_OK:
+        raise GcvoError(st, "gcvo_mlp_loss_grad")
+    return loss, grad
+
+
+def gcvo_mlp_adam(w, w_bf16, m, v, grad, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+                  eps: float = 1e-8, stream=None) -> None:
+    L = load_library()
+    st = L.gcvo_mlp_adam(_ptr(w), _ptr(w_bf16), _ptr(m), _ptr(v), _ptr(grad), int(w.numel()), int(step),
+                         float(lr), float(beta1), float(beta2), float(eps), _stream_handle(stream))
+    if st != GCVO_OK:
+        raise GcvoError(st, "gcvo_mlp_adam")

@@ -12,7 +12,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    src = open(os.path.join(ROOT, "include", "gcvo.h")).read()
+    inc = os.path.join(ROOT, "include")
+    src = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc)) if f.endswith(".h"))
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(gcvo_[a-z_0-9]+)\s*\(", src)))
 
@@ -88,3 +89,14 @@ def test_register_rejects_bad_arguments_without_gpu_work():
                          ctypes.byref(info), None, 0, None)
     assert st == gcvo.GCVO_ERR_TOO_FEW_POINTS
     assert all(v == 0.0 for v in T)   # pose output untouched
+
+
+def test_mlp_sizes():
+    L = gcvo.load_library()
+    assert L.gcvo_mlp_param_count() == gcvo.GCVO_MLP_N_PARAMS == 42246
+    assert ctypes.sizeof(gcvo.gcvo_mlp_batch) == 4 + 4 + 8 * 4 + 8 * 4 + 8 * 4 + 8
+    a = gcvo.gcvo_mlp_workspace_size(16, 1024)
+    assert 0 < a < gcvo.gcvo_mlp_workspace_size(128, 1024)
+    assert gcvo.gcvo_mlp_workspace_size(0, 1024) == 0
+    assert gcvo.gcvo_mlp_workspace_size(4, 0) == 0
+    assert gcvo.gcvo_mlp_workspace_size(4, 1 << 20) == 0
