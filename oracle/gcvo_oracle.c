@@ -19,7 +19,9 @@
  *   - the exact frozen-covariance derivative of the gradient (the first, second
  *     and fourth terms of eq. (direction_derivative_gradf)) for derivative tests
  *     and for the exact-Hessian (Newton) variant;
- *   - the update T <- T exp(xi^) of eq. (gn_update) and Algorithm 1's loop.
+ *   - the update T <- T exp(xi^) of eq. (gn_update) and Algorithm 1's loop;
+ *   - the first-order method: the quartic line-search polynomial along the
+ *     gradient (App. "Line search", coefficients re-derived) and its step.
  *
  * Readings of points the paper leaves open (length scale, eigenvalue floor,
  * cutoff, damping, annealing schedule) are the ones stated in the project's
@@ -435,6 +437,187 @@ void orc_se3_exp(const double xi[6], double T[16]) {
 }
 
 /*
+ * Line-search polynomial of the first-order method (Sec. "A first-order
+ * method", App. "Line search"), re-derived because the printed coefficients
+ * are partly garbled (reading): along T(t) = T exp(t xi^) with the covariances
+ * frozen at T,
+ *   y_j(t) = exp(-t xi^) y_j = y - t e1 + t^2/2 e2 - t^3/6 e3 + t^4/24 e4 + O(t^5),
+ *   e1 = w x y_j + v,  e_{k+1} = w x e_k,
+ * so with P = Sigma_ij^{-1} and r = x_i - y_j the exponent of k_ij is
+ *   -1/2 r^T P r + beta t + gamma t^2 + delta t^3 + eps t^4 + O(t^5),
+ *   beta  = -e1.P r
+ *   gamma = -1/2 e1.P e1 + 1/2 e2.P r
+ *   delta =  1/2 e1.P e2 - 1/6 e3.P r
+ *   eps   = -1/8 e2.P e2 - 1/6 e1.P e3 + 1/24 e4.P r
+ * and exp() of that series is 1 + g1 t + g2 t^2 + g3 t^3 + g4 t^4 with the
+ * paper's combination g1 = beta, g2 = gamma + beta^2/2, g3 = delta + beta gamma
+ * + beta^3/6, g4 = eps + beta delta + beta^2 gamma/2 + gamma^2/2 + beta^4/24.
+ * c[0] = sum f_ij, c[k] = sum f_ij g^k_ij (k = 1..4): G(t) ~ sum_k c[k] t^k.
+ * Same pair set and loop order as orc_eval.
+ */
+int orc_line_coeffs(const double *X, const double *SX, long nx, const double *Z, const double *SZ, long nz,
+                    const double T[16], double ell, double cutoff, double sigma2, const double xi[6],
+                    double c_out[5], long long *npairs_out) {
+    if (!X || !SX || !Z || !SZ || !T || !xi || !c_out || nx < 0 || nz < 0 || !(ell > 0.0))
+        return ORC_ERR_INVALID;
+    double *slot = (double *)calloc((size_t)(nz > 0 ? nz : 1) * 5, sizeof(double));
+    long long *pcount = (long long *)calloc((size_t)(nz > 0 ? nz : 1), sizeof(long long));
+    if (!slot || !pcount) { free(slot); free(pcount); return ORC_ERR_INVALID; }
+    double R[9], t[3], Rt[9];
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) R[r * 3 + c] = T[r * 4 + c];
+        t[r] = T[r * 4 + 3];
+    }
+    transpose(R, Rt, 3, 3);
+    const double half_l2 = 0.5 * ell * ell;
+    const double rc2 = (cutoff > 0.0) ? cutoff * cutoff : INFINITY;
+    double W[9];
+    hat3(xi, W);
+
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long j = 0; j < nz; ++j) {
+        double *acc = slot + (size_t)j * 5;
+        double zt[3] = {Z[3 * j] - t[0], Z[3 * j + 1] - t[1], Z[3 * j + 2] - t[2]};
+        double y[3];
+        matmul(Rt, zt, y, 3, 3, 1);
+        double Sj[9], tmp[9], SjR[9];
+        shape6_to_mat(SZ + 6 * j, Sj);
+        matmul(Rt, Sj, tmp, 3, 3, 3);
+        matmul(tmp, R, SjR, 3, 3, 3);
+        double e[5][3];                        /* e[1..4] */
+        matmul(W, y, e[1], 3, 3, 1);
+        for (int a = 0; a < 3; ++a) e[1][a] += xi[3 + a];
+        for (int k = 2; k <= 4; ++k) matmul(W, e[k - 1], e[k], 3, 3, 1);
+        for (long i = 0; i < nx; ++i) {
+            double r3[3] = {X[3 * i] - y[0], X[3 * i + 1] - y[1], X[3 * i + 2] - y[2]};
+            double d2 = r3[0] * r3[0] + r3[1] * r3[1] + r3[2] * r3[2];
+            if (!(d2 <= rc2)) continue;
+            double Si[9], Sig[9], P[9];
+            shape6_to_mat(SX + 6 * i, Si);
+            for (int a = 0; a < 9; ++a) Sig[a] = half_l2 * (Si[a] + SjR[a]);
+            if (!inv3(Sig, P)) continue;
+            double Pr[3], Pe1[3], Pe2[3];
+            matmul(P, r3, Pr, 3, 3, 1);
+            matmul(P, e[1], Pe1, 3, 3, 1);
+            matmul(P, e[2], Pe2, 3, 3, 1);
+            double quad = r3[0] * Pr[0] + r3[1] * Pr[1] + r3[2] * Pr[2];
+            double fij = sigma2 * exp(-0.5 * quad);
+            double e1Pr = 0, e2Pr = 0, e3Pr = 0, e4Pr = 0, e1Pe1 = 0, e2Pe2 = 0, e1Pe2 = 0, e3Pe1 = 0;
+            for (int a = 0; a < 3; ++a) {
+                e1Pr += e[1][a] * Pr[a];
+                e2Pr += e[2][a] * Pr[a];
+                e3Pr += e[3][a] * Pr[a];
+                e4Pr += e[4][a] * Pr[a];
+                e1Pe1 += e[1][a] * Pe1[a];
+                e2Pe2 += e[2][a] * Pe2[a];
+                e1Pe2 += e[1][a] * Pe2[a];
+                e3Pe1 += e[3][a] * Pe1[a];
+            }
+            double beta = -e1Pr;
+            double gamma = -0.5 * e1Pe1 + 0.5 * e2Pr;
+            double delta = 0.5 * e1Pe2 - e3Pr / 6.0;
+            double eps = -0.125 * e2Pe2 - e3Pe1 / 6.0 + e4Pr / 24.0;
+            double g1 = beta;
+            double g2 = gamma + 0.5 * beta * beta;
+            double g3 = delta + beta * gamma + beta * beta * beta / 6.0;
+            double g4 = eps + beta * delta + 0.5 * beta * beta * gamma + 0.5 * gamma * gamma +
+                        beta * beta * beta * beta / 24.0;
+            acc[0] += fij;
+            acc[1] += fij * g1;
+            acc[2] += fij * g2;
+            acc[3] += fij * g3;
+            acc[4] += fij * g4;
+            pcount[j] += 1;
+        }
+    }
+    double c[5] = {0};
+    long long np = 0;
+    for (long j = 0; j < nz; ++j) {
+        for (int k = 0; k < 5; ++k) c[k] += slot[(size_t)j * 5 + k];
+        np += pcount[j];
+    }
+    free(slot);
+    free(pcount);
+    memcpy(c_out, c, sizeof c);
+    if (npairs_out) *npairs_out = np;
+    return ORC_OK;
+}
+
+static double dpoly(const double c[5], double t) {
+    return c[1] + t * (2.0 * c[2] + t * (3.0 * c[3] + t * 4.0 * c[4]));
+}
+
+/* Bisection of G' on [lo, hi] with G'(lo) > 0 >= G'(hi). */
+static double bisect_root(const double c[5], double lo, double hi) {
+    for (int it = 0; it < 400 && hi - lo > 1e-17 * hi; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (dpoly(c, mid) > 0.0) lo = mid;
+        else hi = mid;
+    }
+    return hi;
+}
+
+/*
+ * Step size of eq. (linesearch): the smallest positive real root t* of
+ * G'(t) = c1 + 2 c2 t + 3 c3 t^2 + 4 c4 t^3 and mu = max(mu0, t*).  The
+ * critical points of G' (roots of G'', closed form) split t > 0 into intervals
+ * where G' is monotone; the first interval whose right end has G' <= 0 holds
+ * t*, found by bisection.  Reading where the quartic's derivative has no
+ * positive root (a positive quartic term far outside the expansion's range,
+ * common once the iterate is near a maximum): the paper falls back to a fixed
+ * minimum step mu0, whose size depends on the objective's units; here the
+ * fallback is the maximiser of the quadratic part, -c1 / (2 c2), when c2 < 0,
+ * and mu0 only when even that does not exist.  Returns 1 (quartic root),
+ * 2 (quadratic step) or 0 (mu0).
+ */
+int orc_first_order_step(const double c[5], double mu0, double *mu) {
+    *mu = mu0;
+    if (!(c[1] > 0.0)) return 0;
+    const double tq = (c[2] < 0.0) ? c[1] / (-2.0 * c[2]) : 0.0;
+    double cp[2];
+    int ncp = 0;
+    /* G'' = 2 c2 + 6 c3 t + 12 c4 t^2 */
+    if (c[4] != 0.0) {
+        double a = 12.0 * c[4], b = 6.0 * c[3], cc = 2.0 * c[2];
+        double disc = b * b - 4.0 * a * cc;
+        if (disc >= 0.0) {
+            double sq = sqrt(disc);
+            double r1 = (-b - sq) / (2.0 * a), r2 = (-b + sq) / (2.0 * a);
+            if (r1 > r2) { double tt = r1; r1 = r2; r2 = tt; }
+            if (r1 > 0.0) cp[ncp++] = r1;
+            if (r2 > 0.0 && r2 != r1) cp[ncp++] = r2;
+        }
+    } else if (c[3] != 0.0) {
+        double r = -2.0 * c[2] / (6.0 * c[3]);
+        if (r > 0.0) cp[ncp++] = r;
+    }
+    double lo = 0.0;
+    for (int k = 0; k < ncp; ++k) {
+        if (dpoly(c, cp[k]) <= 0.0) {
+            double t = bisect_root(c, lo, cp[k]);
+            *mu = t > mu0 ? t : mu0;
+            return 1;
+        }
+        lo = cp[k];
+    }
+    /* last interval (lo, inf): a root exists only if G' tends to -inf */
+    double lead = (c[4] != 0.0) ? c[4] : (c[3] != 0.0) ? c[3] : c[2];
+    double hi = (lo > 0.0) ? 2.0 * lo : 1e-30;
+    if (lead < 0.0)
+        for (int it = 0; it < 4000 && dpoly(c, hi) > 0.0; ++it) hi *= 2.0;
+    if (!(lead < 0.0) || dpoly(c, hi) > 0.0) {
+        if (tq > 0.0) {
+            *mu = tq > mu0 ? tq : mu0;
+            return 2;
+        }
+        return 0;
+    }
+    double t = bisect_root(c, lo, hi);
+    *mu = t > mu0 ? t : mu0;
+    return 1;
+}
+
+/*
  * Step of eq. (gn_update): xi = -H^{-1} g with H = Hmain + C(g) (or, for the
  * exact-Hessian variant, H = T1 + T2 + Hmain + C(g), passed in as H).
  * Reading of the damping the paper leaves open:
@@ -507,8 +690,10 @@ static int pose_is_rigid(const double T[16]) {
 }
 
 /*
- * Algorithm 1 with the Gauss-Newton update (or the exact frozen-covariance
- * Hessian when newton != 0), from T_init, with the length-scale annealing the
+ * Algorithm 1 with the Gauss-Newton update (solver 0), the exact
+ * frozen-covariance Hessian (solver 1, the exact-Hessian variant) or the
+ * first-order ascent with the quartic line search and minimum step min_step
+ * (solver 2), from T_init, with the length-scale annealing the
  * paper sketches for Sigma (reading):
  *   stage s uses ell_s; ell_0 = ell, ell_{s+1} = max(alpha * ell_s, ell_min);
  *   a non-final stage ends when ||xi||_1 < stage_tol or after
@@ -519,18 +704,21 @@ static int pose_is_rigid(const double T[16]) {
  * SX/SZ may be NULL, in which case the shapes are computed with (knn, rho).
  * info[] receives: 0 status, 1 converged, 2 iterations, 3 stages used, 4 f,
  * 5..10 g, 11 ||xi||_1 of the last step, 12 pairs at the last iteration,
- * 13 damped steps, 14..29 iterations per stage (up to 16 stages).
+ * 13 damped steps (first-order: steps not taken at a quartic root), 14..29
+ * iterations per stage (up to 16 stages).
  * On error T_out is left untouched.
  */
 int orc_register(const double *X, const double *SXin, long nx, const double *Z, const double *SZin,
                  long nz, const double T_init[16], double ell, double ell_min, double alpha,
                  double cutoff_scale, int knn, double rho, double sigma2, int max_iters,
-                 int max_iters_per_stage, double tol, double stage_tol, int newton,
+                 int max_iters_per_stage, double tol, double stage_tol, int solver, double min_step,
                  double T_out[16], double info[32]) {
+    const int newton = (solver == 1), first_order = (solver == 2);
     for (int a = 0; a < 32; ++a) info[a] = 0.0;
     if (!X || !Z || !T_init || !T_out || nx < 0 || nz < 0 || !(ell > 0.0) || !(ell_min > 0.0) ||
         ell_min > ell || !(alpha > 0.0) || alpha > 1.0 || !(cutoff_scale > 0.0) || max_iters < 1 ||
-        max_iters_per_stage < 1 || !(tol > 0.0) || !pose_is_rigid(T_init)) {
+        max_iters_per_stage < 1 || !(tol > 0.0) || !pose_is_rigid(T_init) || solver < 0 || solver > 2 ||
+        (first_order && !(min_step > 0.0))) {
         info[0] = ORC_ERR_INVALID;
         return ORC_ERR_INVALID;
     }
@@ -563,13 +751,22 @@ int orc_register(const double *X, const double *SXin, long nx, const double *Z, 
                       newton ? T1 : NULL, newton ? T2 : NULL, &np);
         if (st != ORC_OK) break;
         if (np == 0) { st = ORC_ERR_NO_PAIRS; break; }
-        orc_connection(g, C);
-        for (int a = 0; a < 36; ++a) H[a] = Hm[a] + C[a] + (newton ? T1[a] + T2[a] : 0.0);
         double xi[6];
-        int dmp = 0;
-        st = orc_solve_step(H, Hm, g, xi, &dmp);
-        if (st != ORC_OK) break;
-        if (dmp) ++damped_steps;
+        if (first_order) {
+            /* gradient ascent along g with the line-search step (eq. (fo_update)) */
+            double cl[5], mu;
+            st = orc_line_coeffs(X, sx, nx, Z, sz, nz, T, cur_ell, cutoff_scale * cur_ell, sigma2, g, cl, NULL);
+            if (st != ORC_OK) break;
+            if (orc_first_order_step(cl, min_step, &mu) != 1) ++damped_steps;
+            for (int a = 0; a < 6; ++a) xi[a] = mu * g[a];
+        } else {
+            orc_connection(g, C);
+            for (int a = 0; a < 36; ++a) H[a] = Hm[a] + C[a] + (newton ? T1[a] + T2[a] : 0.0);
+            int dmp = 0;
+            st = orc_solve_step(H, Hm, g, xi, &dmp);
+            if (st != ORC_OK) break;
+            if (dmp) ++damped_steps;
+        }
         double E[16], Tn[16];
         orc_se3_exp(xi, E);
         matmul(T, E, Tn, 4, 4, 4);

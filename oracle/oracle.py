@@ -60,7 +60,10 @@ def lib() -> ctypes.CDLL:
                                    ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                    ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                    ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
-                                   _dp, _dp]
+                                   ctypes.c_double, _dp, _dp]
+        L.orc_line_coeffs.argtypes = [_dp, _dp, ctypes.c_long, _dp, _dp, ctypes.c_long, _dp, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, _dp, _dp, _llp]
+        L.orc_first_order_step.argtypes = [_dp, ctypes.c_double, _dp]
         L.orc_num_threads.argtypes = []
         _lib = L
     return _lib
@@ -136,6 +139,29 @@ def evaluate(X, SX, Z, SZ, T, ell: float, cutoff: float | None, sigma2: float = 
     return Eval(f.value, g, H, T1, T2, npairs.value)
 
 
+def line_coeffs(X, SX, Z, SZ, T, xi, ell: float, cutoff: float | None, sigma2: float = 1.0):
+    """(c[0..4], npairs): G(t) = f(T exp(t xi^)) ~ sum_k c[k] t^k with the
+    covariances frozen at T."""
+    X, SX, Z, SZ, T, xi = _d(X), _d(SX), _d(Z), _d(SZ), _d(T), _d(xi)
+    c = np.zeros(5)
+    npairs = ctypes.c_longlong()
+    st = lib().orc_line_coeffs(_p(X), _p(SX), len(X), _p(Z), _p(SZ), len(Z), _p(T), float(ell),
+                               float(cutoff) if cutoff is not None else -1.0, float(sigma2), _p(xi), _p(c),
+                               ctypes.byref(npairs))
+    if st:
+        raise OracleError(st, "orc_line_coeffs")
+    return c, npairs.value
+
+
+def first_order_step(c, min_step: float):
+    """(mu, kind): kind 1 = smallest positive root of G' (mu = max(min_step,
+    root)), 2 = quadratic-model step, 0 = min_step."""
+    c = _d(c)
+    mu = ctypes.c_double()
+    kind = lib().orc_first_order_step(_p(c), float(min_step), ctypes.byref(mu))
+    return mu.value, int(kind)
+
+
 def connection(g) -> np.ndarray:
     g = _d(g)
     C = np.zeros((6, 6))
@@ -178,7 +204,10 @@ def register(X, Z, T_init=None, *, SX=None, SZ=None, length_scale: float, length
              anneal_factor: float = 0.5, cutoff_scale: float = 3.0, knn: int = 10,
              eig_ratio_min: float = 0.01, sigma2: float = 1.0, max_iters: int = 30,
              max_iters_per_stage: int = 30, tol: float = 1e-6, stage_tol: float = 1e-4,
-             newton: bool = False) -> RegResult:
+             newton: bool = False, solver: int | None = None, min_step: float = 1e-10) -> RegResult:
+    """solver: 0 Gauss-Newton, 1 exact frozen-covariance Hessian (newton=True),
+    2 first-order ascent with the quartic line search."""
+    solver = (1 if newton else 0) if solver is None else int(solver)
     X, Z = _d(X), _d(Z)
     T0 = np.eye(4) if T_init is None else _d(T_init)
     lmin = length_scale if length_scale_min is None else length_scale_min
@@ -189,7 +218,7 @@ def register(X, Z, T_init=None, *, SX=None, SZ=None, length_scale: float, length
     st = lib().orc_register(_p(X), _p(SXp), len(X), _p(Z), _p(SZp), len(Z), _p(T0),
                             float(length_scale), float(lmin), float(anneal_factor), float(cutoff_scale),
                             int(knn), float(eig_ratio_min), float(sigma2), int(max_iters),
-                            int(max_iters_per_stage), float(tol), float(stage_tol), int(bool(newton)),
+                            int(max_iters_per_stage), float(tol), float(stage_tol), solver, float(min_step),
                             _p(Tout), _p(info))
     if st:
         raise OracleError(st, "orc_register")

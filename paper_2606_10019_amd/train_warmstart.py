@@ -59,7 +59,7 @@ def label(specs, chunk: int = 64):
     return np.array(Ts), np.array(conv)
 
 
-def evaluate(net, specs, refs, log, refine_length_scale: float = 0.5):
+def evaluate(net, specs, refs, log, refine_length_scale=None):
     """Plain from identity vs warm-started, both batched, judged against refs
     (plain solver from the true motion) at 1e-3 deg / 1e-5 m."""
     import torch
@@ -128,8 +128,7 @@ def main():
     t_train = time.time() - t0
     log(f"trained {args.steps} steps x {args.batch} in {t_train:.1f} s")
     ev_keep = [k for k in range(len(eval_specs)) if rconv[k]]
-    results = [evaluate(net, [eval_specs[k] for k in ev_keep], refs[ev_keep], log, ell)
-               for ell in (1.0, 0.5, 0.25)]
+    results = [evaluate(net, [eval_specs[k] for k in ev_keep], refs[ev_keep], log, ell) for ell in (None, 0.5)]
     meta = dict(pairs=int(len(keep)), steps=args.steps, batch=args.batch, lr=args.lr, lr_final=args.lr_final,
                 seed=args.seed, crop_m=warmstart.CROP_M,
                 samples=args.steps * args.batch, input_scale=warmstart.INPUT_SCALE, n_points=warmstart.N_POINTS,

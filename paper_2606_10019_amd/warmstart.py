@@ -19,11 +19,14 @@ The network sees a 1024-point subsample of the points within CROP_M metres
 (horizontally) of each sensor.
 
 Warm-started registration: the network predicts T0 from those subsamples,
-plain G-CVO refines from T0 with the annealing schedule starting at
-``refine_length_scale``, and the result is kept unless its final objective is
-below the objective at T = I for the same final length scale (one extra
-evaluation); then the plain solver from identity is run and its result
-returned.
+plain G-CVO refines from T0 with the pair's annealing schedule (optionally
+starting at a smaller length scale), and the result is kept unless the refine
+did not converge or its objective is below the objective at T = I, both
+evaluated at the schedule's first length scale (two evaluations); then the
+plain solver from identity is run and its result returned.  The comparison is
+made at the first length scale because at the final one the objective of two
+scans from a spinning sensor peaks at T = I, where the scan rings coincide,
+whatever the true motion.
 """
 from __future__ import annotations
 
@@ -248,33 +251,42 @@ def predict(net: Network, ps: PairSet, seed: int = 0) -> np.ndarray:
     return T
 
 
-def register_warm(net: Network, ps: PairSet, params, refine_length_scale: float = 0.5, seed: int = 0):
+def _params_copy(p, **kw):
+    q = gcvo.gcvo_params()
+    for name, _ in gcvo.gcvo_params._fields_:
+        setattr(q, name, getattr(p, name))
+    for k, v in kw.items():
+        setattr(q, k, v)
+    return q
+
+
+def objective_at(ps: PairSet, poses, params, length_scales):
+    """f at the given poses (None = identity) with each pair's length scale:
+    one iteration of the solver, whose reported f is the objective at its
+    starting pose."""
+    ep = [_params_copy(p, length_scale=ell, length_scale_min=ell, max_iters=1, max_iters_per_stage=1)
+          for p, ell in zip(params, length_scales)]
+    _, infos = gcvo.gcvo_register_batch(ps.targets, ps.tgt_off, ps.sources, ps.src_off, poses, ep)
+    return np.array([i["f"] for i in infos])
+
+
+def register_warm(net: Network, ps: PairSet, params, refine_length_scale: float | None = None, seed: int = 0):
     """Warm-started batch registration with the objective fallback.  params:
-    one gcvo_params per pair (the plain schedule).  Returns (T [B,4,4], infos,
-    record) where record says which pairs fell back."""
+    one gcvo_params per pair (the plain schedule); refine_length_scale, when
+    given, starts the refine's schedule there instead.  Returns (T [B,4,4],
+    infos, record) where record holds the predictions, which pairs fell back,
+    and the two objectives compared."""
     T0 = predict(net, ps, seed)
-    rp = []
-    for p in params:
-        q = gcvo.gcvo_params()
-        for name, _ in gcvo.gcvo_params._fields_:
-            setattr(q, name, getattr(p, name))
-        q.length_scale = max(min(refine_length_scale, p.length_scale), p.length_scale_min)
-        rp.append(q)
+    rp = [p if refine_length_scale is None else
+          _params_copy(p, length_scale=max(min(refine_length_scale, p.length_scale), p.length_scale_min))
+          for p in params]
     T, infos = gcvo.gcvo_register_batch(ps.targets, ps.tgt_off, ps.sources, ps.src_off, T0, rp)
-    # f at T = I with the final length scale: one evaluation (max_iters = 1).
-    ep = []
-    for p in params:
-        q = gcvo.gcvo_params()
-        for name, _ in gcvo.gcvo_params._fields_:
-            setattr(q, name, getattr(p, name))
-        q.length_scale = q.length_scale_min = p.length_scale_min
-        q.max_iters = q.max_iters_per_stage = 1
-        ep.append(q)
-    _, e_infos = gcvo.gcvo_register_batch(ps.targets, ps.tgt_off, ps.sources, ps.src_off, None, ep)
-    fall = [k for k in range(ps.n) if not infos[k]["converged"] or infos[k]["f"] < e_infos[k]["f"]]
-    if fall:
-        for k in fall:
-            tg = ps.targets[ps.tgt_off[k]:ps.tgt_off[k + 1]]
-            sr = ps.sources[ps.src_off[k]:ps.src_off[k + 1]]
-            T[k], infos[k] = gcvo.gcvo_register(tg, sr, None, params[k])
-    return T, infos, dict(T0=T0, fallback=fall, f_identity=[e["f"] for e in e_infos])
+    ell0 = [p.length_scale for p in params]
+    f_ref = objective_at(ps, T, params, ell0)
+    f_id = objective_at(ps, None, params, ell0)
+    fall = [k for k in range(ps.n) if not infos[k]["converged"] or f_ref[k] < f_id[k]]
+    for k in fall:
+        tg = ps.targets[ps.tgt_off[k]:ps.tgt_off[k + 1]]
+        sr = ps.sources[ps.src_off[k]:ps.src_off[k + 1]]
+        T[k], infos[k] = gcvo.gcvo_register(tg, sr, None, params[k])
+    return T, infos, dict(T0=T0, fallback=fall, f_refined=f_ref.tolist(), f_identity=f_id.tolist())
