@@ -79,6 +79,26 @@ extern "C" {
 #define GCVO_PRECISION_FP32 0 /* pair terms in FP32, FP32 per-block sums, compensated cross-block sums, FP64 solve */
 #define GCVO_PRECISION_FP64 1 /* the same kernels instantiated in FP64 throughout                                  */
 
+/* Solvers (Sec. "A first-order method", Sec. "A second-order method", the
+ * exact-Hessian ablation).  All three stop on ||xi||_1 and anneal alike.
+ *   GN           Gauss-Newton: H = H_main + C(g) (eq. (hessian_gn), eq. (connection_se3)).
+ *   NEWTON       exact frozen-covariance Hessian: H = H_main + T1 + T2 + C(g),
+ *                T1 = sum f (J^T u)(J^T u)^T (product rule on f_ij), T2 =
+ *                -sum f [u^ J; 0] (derivative of J_j), u = Sigma^{-1} r
+ *                (eq. (direction_derivative_gradf) with Sigma frozen).  The
+ *                damped fallback uses H_main as for GN.
+ *   FIRST_ORDER  T <- T exp(mu g^) (eq. (fo_update)) with mu from the quartic
+ *                expansion of f along g (eq. (linesearch), App. "Line search";
+ *                coefficients re-derived by expanding the kernel exponent along
+ *                exp(-t xi^) y, the printed ones being partly garbled): the
+ *                smallest positive root of the expansion's derivative; where it
+ *                has none, the maximiser of its quadratic part when that
+ *                exists; mu is never below min_step.  Each iteration is a
+ *                gradient pass and a line-search pass over the pairs. */
+#define GCVO_SOLVER_GN 0
+#define GCVO_SOLVER_NEWTON 1
+#define GCVO_SOLVER_FIRST_ORDER 2
+
 #define GCVO_MAX_KNN 16
 #define GCVO_MAX_STAGES 16
 #define GCVO_MAX_POINTS (1LL << 26) /* per cloud */
@@ -96,12 +116,14 @@ typedef struct gcvo_params {
     double tol;               /* final-stage stop: ||xi||_1 < tol (> 0; 1e-6)                            */
     double stage_tol;         /* non-final stage stop: ||xi||_1 < stage_tol (> 0; 1e-4)                  */
     int precision;            /* GCVO_PRECISION_FP32 (default) or GCVO_PRECISION_FP64                    */
+    int solver;               /* GCVO_SOLVER_GN (default), GCVO_SOLVER_NEWTON or GCVO_SOLVER_FIRST_ORDER */
+    double min_step;          /* first-order solver: smallest step mu (> 0; 1e-10)                      */
 } gcvo_params;
 
 typedef struct gcvo_info {
     int status;              /* mirrors the return value                                    */
     int converged;           /* 1 when the final stage reached ||xi||_1 < tol               */
-    int iters;               /* Gauss-Newton iterations performed                           */
+    int iters;               /* solver iterations performed                                 */
     int stages;              /* length-scale stages entered                                 */
     long long pairs_last;    /* pairs within the cutoff at the last iteration               */
     double f;                /* objective at the last evaluated pose                        */
@@ -111,7 +133,7 @@ typedef struct gcvo_info {
 } gcvo_info;
 
 /* Fills p with the defaults named above (ell = 0.3 fixed, cutoff 3, knn 10,
- * rho 0.01, sigma2 1, 30 iterations, tol 1e-6, stage_tol 1e-4, FP32). */
+ * rho 0.01, sigma2 1, 30 iterations, tol 1e-6, stage_tol 1e-4, FP32, Gauss-Newton). */
 void gcvo_default_params(gcvo_params *p);
 
 /* Bytes of device workspace gcvo_register needs for clouds of these sizes and
@@ -141,7 +163,7 @@ size_t gcvo_batch_workspace_size(int n_pairs, const long long *tgt_off, const lo
  * src_xyz[src_off[k] .. src_off[k+1]) (device float32 [*][3]); the offsets are
  * HOST int64 arrays of n_pairs + 1 entries.  T_init: host [n_pairs][16] or NULL
  * (identity).  p: host array of n_pairs parameter sets, or one set shared by all
- * pairs when shared_params != 0; all pairs must use the same knn and precision.
+ * pairs when shared_params != 0; all pairs must use the same knn, precision and solver.
  * T_out: host [n_pairs][16]; info: host [n_pairs] or NULL.  A pair that fails (for example with no pairs in reach)
  * reports its own status in info[k].status and keeps T_out[k] = T_init[k]; the
  * call returns the first failing pair's code only for argument errors, HIP

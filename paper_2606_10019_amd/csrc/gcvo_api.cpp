@@ -59,6 +59,9 @@ bool params_ok(const gcvo_params *p) {
     if (!(p->eig_ratio_min > 0.0 && p->eig_ratio_min <= 1.0)) return false;
     if (p->max_iters < 1 || p->max_iters_per_stage < 1) return false;
     if (p->precision != GCVO_PRECISION_FP32 && p->precision != GCVO_PRECISION_FP64) return false;
+    if (p->solver != GCVO_SOLVER_GN && p->solver != GCVO_SOLVER_NEWTON && p->solver != GCVO_SOLVER_FIRST_ORDER)
+        return false;
+    if (p->solver == GCVO_SOLVER_FIRST_ORDER && !pos(p->min_step)) return false;
     double e[kMaxStages];
     return stage_schedule(*p, e) > 0;
 }
@@ -162,6 +165,8 @@ void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &p
         P.stage_tol = I.p.stage_tol;
         P.max_iters = I.p.max_iters;
         P.max_per_stage = I.p.max_iters_per_stage;
+        P.solver = (mode == Mode::Eval) ? GCVO_SOLVER_GN : I.p.solver;
+        P.min_step = I.p.min_step;
         std::memcpy(P.T_init, I.T0, sizeof P.T_init);
         P.t_orig = A.take<float>(3 * (size_t)nt);
         P.s_orig = A.take<float>(3 * (size_t)ns);
@@ -305,7 +310,8 @@ int upload_and_prepare(Plan &pl, int knn, hipStream_t s) {
 // After a profiled run: launches in which some pair iterated are the first
 // max_k(iterations of pair k) ones; their event-bracketed durations and the
 // pairs logged by the device are added to the counters.
-int profile_collect(Plan &pl, int launched, hipStream_t s) {
+int profile_collect(Plan &pl, int launched, int solver, hipStream_t s) {
+    const int passes = passes_per_iteration(solver);
     const int np = (int)pl.pairs.size();
     int active = 0;
     long long pairs = 0, points = 0;
@@ -323,7 +329,9 @@ int profile_collect(Plan &pl, int launched, hipStream_t s) {
             points += (long long)it * pl.pairs[k].n_s;
         }
     }
-    active = std::min(active, launched);
+    active = std::min(active, launched) * passes;
+    pairs *= passes;
+    points *= passes;
     double ms = 0.0;
     for (int i = 0; i < active; ++i) {
         float e = 0.0f;
@@ -338,7 +346,7 @@ int profile_collect(Plan &pl, int launched, hipStream_t s) {
     return GCVO_OK;
 }
 
-int run_iterations(Plan &pl, int max_iters, int precision, hipStream_t s) {
+int run_iterations(Plan &pl, int max_iters, int precision, int solver, hipStream_t s) {
     int *flags = pinned_flags();
     if (!flags) return GCVO_ERR_HIP;
     hipEvent_t ev[2];
@@ -353,16 +361,13 @@ int run_iterations(Plan &pl, int max_iters, int precision, hipStream_t s) {
     bool pending[2] = {false, false};
     if (launch_count_active(pl.d_pairs, np, pl.d_active, s) != hipSuccess) rc = GCVO_ERR_HIP;
     auto enqueue = [&](int c) -> hipError_t {
-        if (!g_prof.on) return launch_iterations(pl.d_pairs, np, pl.d_tasks, n_tasks, c, precision, pl.d_active, s);
-        for (int i = 0; i < c; ++i) {
-            hipEvent_t a = prof_event(2 * (size_t)(launched + i)), b = prof_event(2 * (size_t)(launched + i) + 1);
-            if (!a || !b) return hipErrorOutOfMemory;
-            hipError_t e = hipEventRecord(a, s);
-            if (e == hipSuccess) e = launch_iterations(pl.d_pairs, np, pl.d_tasks, n_tasks, 1, precision, pl.d_active, s);
-            if (e == hipSuccess) e = hipEventRecord(b, s);
-            if (e != hipSuccess) return e;
-        }
-        return hipSuccess;
+        if (!g_prof.on)
+            return launch_iterations(pl.d_pairs, np, pl.d_tasks, n_tasks, c, precision, solver, pl.d_active, s);
+        const int per = 2 * passes_per_iteration(solver);
+        std::vector<hipEvent_t> ev((size_t)per * c);
+        for (size_t i = 0; i < ev.size(); ++i)
+            if (!(ev[i] = prof_event((size_t)per * launched + i))) return hipErrorOutOfMemory;
+        return launch_iterations(pl.d_pairs, np, pl.d_tasks, n_tasks, c, precision, solver, pl.d_active, s, ev.data());
     };
     while (rc == GCVO_OK && launched < max_iters) {
         const int c = std::min(kChunk, max_iters - launched);
@@ -388,7 +393,7 @@ int run_iterations(Plan &pl, int max_iters, int precision, hipStream_t s) {
     if (hipStreamSynchronize(s) != hipSuccess) rc = GCVO_ERR_HIP;
     hipEventDestroy(ev[0]);
     hipEventDestroy(ev[1]);
-    if (rc == GCVO_OK && g_prof.on) rc = profile_collect(pl, launched, s);
+    if (rc == GCVO_OK && g_prof.on) rc = profile_collect(pl, launched, solver, s);
     return rc;
 }
 
@@ -411,7 +416,7 @@ bool ws_ok(void *ws, size_t ws_bytes, size_t need) {
 }
 
 int register_many(Mode mode, std::vector<PairInput> &in, double *T_out, gcvo_info *info, void *ws,
-                  size_t ws_bytes, hipStream_t s, int shared_knn, int precision, int max_iters) {
+                  size_t ws_bytes, hipStream_t s, int shared_knn, int precision, int solver, int max_iters) {
     Plan sizing;
     build_plan(nullptr, mode, in, sizing);
     if (!ws_ok(ws, ws_bytes, sizing.bytes)) return GCVO_ERR_WORKSPACE;
@@ -419,7 +424,7 @@ int register_many(Mode mode, std::vector<PairInput> &in, double *T_out, gcvo_inf
     build_plan(ws, mode, in, pl);
     int rc = upload_and_prepare(pl, shared_knn, s);
     if (rc) return rc;
-    rc = run_iterations(pl, max_iters, precision, s);
+    rc = run_iterations(pl, max_iters, precision, solver, s);
     if (rc) return rc;
     const int np = (int)in.size();
     std::vector<State> st(np);
@@ -455,9 +460,11 @@ void gcvo_default_params(gcvo_params *p) {
     p->tol = 1e-6;
     p->stage_tol = 1e-4;
     p->precision = GCVO_PRECISION_FP32;
+    p->solver = GCVO_SOLVER_GN;
+    p->min_step = 1e-10;
 }
 
-int gcvo_abi_version(void) { return 100; }
+int gcvo_abi_version(void) { return 101; }
 
 void gcvo_profile_enable(int on) { g_prof.on = on != 0; }
 
@@ -515,7 +522,7 @@ int gcvo_register(const float *tgt_xyz, long long n_tgt, const float *src_xyz, l
     std::memcpy(in[0].T0, T_init ? T_init : kIdentity, sizeof in[0].T0);
     double T[16];
     int rc = register_many(Mode::Register, in, T, info, workspace, workspace_bytes, (hipStream_t)stream, p->knn,
-                           p->precision, p->max_iters);
+                           p->precision, p->solver, p->max_iters);
     if (rc == GCVO_ERR_HIP || rc == GCVO_ERR_WORKSPACE) return fail(rc);   // info not filled by the run
     if (rc != GCVO_OK) return rc;                                           // info holds the run's summary
     std::memcpy(T_out, T, sizeof T);
@@ -544,10 +551,10 @@ int gcvo_register_batch(int n_pairs, const float *tgt_xyz, const long long *tgt_
                         double *T_out, gcvo_info *info, void *workspace, size_t workspace_bytes, void *stream) {
     if (n_pairs < 1 || !tgt_xyz || !tgt_off || !src_xyz || !src_off || !p || !T_out) return GCVO_ERR_INVALID;
     std::vector<PairInput> in(n_pairs);
-    int knn = p[0].knn, prec = p[0].precision, max_it = 0;
+    int knn = p[0].knn, prec = p[0].precision, solver = p[0].solver, max_it = 0;
     for (int k = 0; k < n_pairs; ++k) {
         const gcvo_params &pk = shared_params ? p[0] : p[k];
-        if (!params_ok(&pk) || pk.knn != knn || pk.precision != prec) return GCVO_ERR_INVALID;
+        if (!params_ok(&pk) || pk.knn != knn || pk.precision != prec || pk.solver != solver) return GCVO_ERR_INVALID;
         const long long nt = tgt_off[k + 1] - tgt_off[k], ns = src_off[k + 1] - src_off[k];
         if (nt < 0 || ns < 0 || tgt_off[k] < 0 || src_off[k] < 0) return GCVO_ERR_INVALID;
         if (nt > GCVO_MAX_POINTS || ns > GCVO_MAX_POINTS) return GCVO_ERR_CAPACITY;
@@ -577,7 +584,7 @@ int gcvo_register_batch(int n_pairs, const float *tgt_xyz, const long long *tgt_
     std::vector<gcvo_info> inf(run.size());
     for (size_t r = 0; r < run.size(); ++r) std::memcpy(&T[16 * r], run[r].T0, 16 * sizeof(double));
     int rc = register_many(Mode::Register, run, T.data(), inf.data(), workspace, workspace_bytes,
-                           (hipStream_t)stream, knn, prec, max_it);
+                           (hipStream_t)stream, knn, prec, solver, max_it);
     if (rc == GCVO_ERR_HIP || rc == GCVO_ERR_WORKSPACE) return rc;
     for (size_t r = 0; r < run.size(); ++r) {
         const int k = keep[r];
@@ -638,7 +645,8 @@ int gcvo_eval_fgh(const float *tgt_xyz, const float *tgt_shape6, long long n_tgt
     int rc = upload_and_prepare(pl, 0, s);
     if (rc) return rc;
     HIP_OK(launch_count_active(pl.d_pairs, 1, pl.d_active, s));
-    HIP_OK(launch_iterations(pl.d_pairs, 1, pl.d_tasks, (int)pl.tasks.size(), 1, precision, pl.d_active, s));
+    HIP_OK(launch_iterations(pl.d_pairs, 1, pl.d_tasks, (int)pl.tasks.size(), 1, precision, GCVO_SOLVER_GN,
+                             pl.d_active, s));
     State st;
     HIP_OK(hipMemcpyAsync(&st, pl.pairs[0].st, sizeof st, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));

@@ -2,8 +2,9 @@
 //
 // Work is described by small POD descriptors that live in device memory inside
 // the caller's workspace: one PairDev per registration problem, one SortJob per
-// (cloud, uniform grid) binning, one BlockTask per 256-point block of the
-// per-iteration pair kernel.  A single registration is a batch of one.
+// (cloud, uniform grid) binning, one BlockTask per block of kPointsPerBlock
+// source points of the per-iteration pair kernel.  A single registration is a
+// batch of one.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,7 +19,10 @@ constexpr int kSortThreads = 1024;    // threads of the one-block-per-job radix 
 constexpr int kMaxStages = GCVO_MAX_STAGES;
 constexpr int kMaxKnn = GCVO_MAX_KNN;
 constexpr int kNumSums = 28;          // f, g (6), upper triangle of H_main (21)
-constexpr int kPartialStride = 32;    // floats per block partial: 28 sums + pair count + pad
+constexpr int kSumsExact = 58;        // + upper triangle of T1 (21) + sum_j y_j a_j^T (9)
+constexpr int kSumsLine = 5;          // line-search polynomial coefficients c0..c4
+constexpr int kMaxSums = 64;          // room per reduction slot
+constexpr int kPartialStride = 64;    // elements per block partial: sums + pair count + pad
 constexpr float kCellMargin = 1.001f; // pair-grid cell edge = margin * cutoff (see Grid)
 constexpr int kSortedRows = 12;      // rows of the sorted per-point arrays (see PairDev)
 constexpr int kGroupLanes = 16;      // pair kernel: lanes serving one source point
@@ -76,9 +80,12 @@ struct State {
     long long pairs_last;
     int iter, stage, stage_iter, done, status, converged, damped;
     int stage_iters[kMaxStages];
-    double sub[kReduceSplit][32];     // cross-block sums of the current iteration, by reduction block
+    int phase;                        // first-order solver: 0 = gradient pass next, 1 = line pass next
+    int pad0;
+    double dir[6];                    // first-order solver: unit ascent direction (caller frame)
+    double gnorm;                     // its gradient's norm
+    double sub[kReduceSplit][kMaxSums];   // cross-block sums of the current pass, by reduction block
     unsigned long long sub_pairs[kReduceSplit];
-    int pad[2];
 };
 
 // Everything one registration problem needs on the device.
@@ -92,6 +99,8 @@ struct PairDev {
     int knn;
     double rho, cutoff_scale, sigma2, tol, stage_tol;
     int max_iters, max_per_stage;
+    int solver;                       // GCVO_SOLVER_*
+    double min_step;                  // first-order solver: smallest step mu
     double T_init[16];                // caller frame
     // derived on device
     double centre[3];                 // target centroid, subtracted before the FP32 cast
@@ -114,7 +123,7 @@ struct PairDev {
     SortJob *job_knn_t, *job_knn_s, *job_order_s, *job_stage0;   // job_stage0[s] for s < n_stages
     State *st;
     long long *iter_pairs;            // [max_iters] pairs within the cutoff at each iteration
-    float *partials;                  // [n_blocks][kPartialStride] block sums (pair-term precision)
+    void *partials;                   // [n_blocks][kPartialStride] block sums (pair-term precision)
     int n_blocks;                     // pair-kernel blocks (kPointsPerBlock source points each)
     int first_block;                  // index of the pair's first BlockTask
     int shapes_given;                 // 1: t_shape / s_shape are caller memory (eval path)
@@ -156,11 +165,16 @@ __device__ __forceinline__ float wave_max(float v) {
 // knn selects the kNN kernel instantiation (0: no shapes are computed).
 hipError_t launch_prepare(PairDev *pairs_dev, int n_pairs, int max_n, SortJob *jobs_dev, int n_jobs,
                           int max_job_n, int max_cells, int knn, hipStream_t s);
-// Enqueue n_iters Gauss-Newton iterations (each a no-op for pairs already done).
-// `active` (device int) must hold the number of pairs not yet done; pairs that
-// finish decrement it.
+// Enqueue n_iters solver iterations (each a no-op for pairs already done) of
+// the given solver (GCVO_SOLVER_*; all pairs of a batch share it).  `active`
+// (device int) must hold the number of pairs not yet done; pairs that finish
+// decrement it.
+// With `events` non-null, every pair-kernel launch is bracketed by two of them
+// (2 * passes_per_iteration(solver) * n_iters events, recorded in order).
 hipError_t launch_iterations(PairDev *pairs_dev, int n_pairs, BlockTask *tasks_dev, int n_tasks, int n_iters,
-                             int precision, int *active, hipStream_t s);
+                             int precision, int solver, int *active, hipStream_t s, hipEvent_t *events = nullptr);
+// Pair-kernel passes per solver iteration (2 for the first-order solver).
+int passes_per_iteration(int solver);
 // Count pairs not yet done into *active (device int).
 hipError_t launch_count_active(PairDev *pairs_dev, int n_pairs, int *active, hipStream_t s);
 

@@ -1,11 +1,13 @@
-// One Gauss-Newton iteration of Algorithm 1 as a single kernel launch.
+// Solver iterations of Algorithm 1: the pair kernel, the cross-block reduction
+// and the FP64 step, for the three solvers.
 //
-// Every block owns 256 source points of one pair (sorted by their own grid, so
-// a block's points are spatially close).  Per point j:
+// Pair kernel (k_iterate).  A block serves kPointsPerBlock source points of one
+// pair (Morton order, so a block's points are close), kGroupLanes lanes per
+// point.  Per point j:
 //   y_j = R'^T (z_j - t'),  S'_j = R'^T S_j R'         (Alg. 1 transform; Remark 4)
-// where T' = C^{-1} T C is the current pose in the frame recentred on the target
-// centroid c.  The point scans the 3 x 3 x 3 neighbouring cells of the stage's
-// target grid (9 contiguous x-rows), and for every target within the cutoff
+// where T' is the current pose in the frame recentred on the target centroid.
+// The point lists the x-rows of target cells that meet its cutoff ball, and
+// for every target within the cutoff
 //   S  = S_i + S'_j              (pair covariance = ell^2/2 * S, eq. (covariance))
 //   C  = adj(S), det = det(S)    (so Sigma^{-1} = (2/ell^2) C / det)
 //   q  = r^T C r,  f = exp(-q / (ell^2 det))              (eq. (kernel), sigma2 later)
@@ -15,12 +17,24 @@
 //   a = (2/ell^2) A, Bm = (2/ell^2) B
 //   g_v -= a, g_w -= y x a                                     (Lemma 1)
 //   H_main -= J^T Bm J = [[y^ Bm y^, -y^ Bm], [Bm y^, -Bm]]    (eq. (hessian_gn))
-// The 28 sums are reduced per wave and per block in the pair-term precision
-// (FP32 in the default path) and written as one block partial.  The last block
-// of the pair to finish sums the partials with compensated per-lane sums and an
-// FP64 tree, maps them back to the caller's frame, adds the connection term
-// (eq. (connection_se3)), solves the damped 6x6 system in FP64, retracts
-// T <- T exp(xi^) (eq. (gn_update)) and advances the stage/stop logic.
+// Pass modes:
+//   kModeGN     the 28 sums above (Gauss-Newton, and the gradient pass of the
+//               first-order solver);
+//   kModeExact  also Q = sum_i f u u^T (u = Sigma^{-1} r) per point, giving the
+//               product-rule term T1 = J^T Q J, and sum_j y_j a_j^T, giving the
+//               derivative-of-J term T2 (eq. (direction_derivative_gradf)):
+//               the exact frozen-covariance Hessian of the exact-Hessian solver;
+//   kModeLine   the quartic line-search coefficients along a unit direction
+//               (first-order solver, App. "Line search", re-derived).
+// Sums are reduced per point (xor shuffles) and per block in the pair-term
+// precision and written as one block partial.
+//
+// Reduction (k_reduce): kReduceSplit blocks per pair sum the block partials
+// with compensated per-lane sums and FP64 slices.  Step (k_step): one lane per
+// pair adds the splits in FP64, maps the sums back to the caller's frame, adds
+// the connection term (eq. (connection_se3)), solves in FP64 (damped Gauss-Newton
+// or Newton system, or the line-search root), retracts T <- T exp(xi^)
+// (eq. (gn_update)) and advances the stage/stop logic.
 #include <math.h>
 
 #include "gcvo_dev.h"
@@ -181,15 +195,30 @@ __device__ __forceinline__ void twist_exp(const double xi[6], double E[4][4]) {
 
 // ------------------------------------------------------------------ pair kernel
 
-template <typename Real>
-struct PairSums {
-    Real F, A0, A1, A2, B00, B01, B02, B11, B12, B22;
+constexpr int kModeGN = 0, kModeExact = 1, kModeLine = 2;
+
+template <int Mode>
+struct ModeInfo {
+    static constexpr int sums = Mode == kModeGN ? kNumSums : Mode == kModeExact ? kSumsExact : kSumsLine;
 };
 
 template <typename Real>
+struct PairSums {
+    Real F, A0, A1, A2, B00, B01, B02, B11, B12, B22;   // Gauss-Newton terms
+    Real Q00, Q01, Q02, Q11, Q12, Q22;                  // exact mode: sum (f/det^2) u' u'^T
+    Real L1, L2, L3, L4;                                // line mode: sum f g^k
+};
+
+// Per-point direction data of the line mode: e1 = w x y + v, e_{k+1} = w x e_k.
+template <typename Real>
+struct LineDir {
+    Real e[4][3];
+};
+
+template <typename Real, int Mode>
 __device__ __forceinline__ void pair_term(PairSums<Real> &s, unsigned &cnt, Real rx, Real ry, Real rz,
                                           Real s00, Real s01, Real s02, Real s11, Real s12, Real s22,
-                                          Real rc2, Real kexp) {
+                                          Real rc2, Real kexp, Real k2, const LineDir<Real> &ld) {
     const Real d2 = rx * rx + ry * ry + rz * rz;
     if (d2 <= rc2) {
         const Real c00 = s11 * s22 - s12 * s12;
@@ -205,11 +234,47 @@ __device__ __forceinline__ void pair_term(PairSums<Real> &s, unsigned &cnt, Real
         const Real uz = c02 * rx + c12 * ry + c22 * rz;
         const Real q = rx * ux + ry * uy + rz * uz;
         const Real f = Fast<Real>::exp2(q * (inv * kexp));
-        const Real w = f * inv;
         s.F += f;
-        s.A0 += w * ux; s.A1 += w * uy; s.A2 += w * uz;
-        s.B00 += w * c00; s.B01 += w * c01; s.B02 += w * c02;
-        s.B11 += w * c11; s.B12 += w * c12; s.B22 += w * c22;
+        if constexpr (Mode == kModeLine) {
+            // P = Sigma^{-1} = sc * C
+            const Real sc = k2 * inv;
+            const Real pr0 = sc * ux, pr1 = sc * uy, pr2 = sc * uz;
+            const Real *e1 = ld.e[0], *e2 = ld.e[1], *e3 = ld.e[2], *e4 = ld.e[3];
+            const Real p10 = sc * (c00 * e1[0] + c01 * e1[1] + c02 * e1[2]);
+            const Real p11 = sc * (c01 * e1[0] + c11 * e1[1] + c12 * e1[2]);
+            const Real p12 = sc * (c02 * e1[0] + c12 * e1[1] + c22 * e1[2]);
+            const Real p20 = sc * (c00 * e2[0] + c01 * e2[1] + c02 * e2[2]);
+            const Real p21 = sc * (c01 * e2[0] + c11 * e2[1] + c12 * e2[2]);
+            const Real p22 = sc * (c02 * e2[0] + c12 * e2[1] + c22 * e2[2]);
+            const Real e1Pr = e1[0] * pr0 + e1[1] * pr1 + e1[2] * pr2;
+            const Real e2Pr = e2[0] * pr0 + e2[1] * pr1 + e2[2] * pr2;
+            const Real e3Pr = e3[0] * pr0 + e3[1] * pr1 + e3[2] * pr2;
+            const Real e4Pr = e4[0] * pr0 + e4[1] * pr1 + e4[2] * pr2;
+            const Real e1Pe1 = e1[0] * p10 + e1[1] * p11 + e1[2] * p12;
+            const Real e2Pe2 = e2[0] * p20 + e2[1] * p21 + e2[2] * p22;
+            const Real e1Pe2 = e1[0] * p20 + e1[1] * p21 + e1[2] * p22;
+            const Real e3Pe1 = e3[0] * p10 + e3[1] * p11 + e3[2] * p12;
+            const Real be = -e1Pr;
+            const Real ga = (Real)0.5 * (e2Pr - e1Pe1);
+            const Real de = (Real)0.5 * e1Pe2 - e3Pr * (Real)(1.0 / 6.0);
+            const Real ep = (Real)-0.125 * e2Pe2 - e3Pe1 * (Real)(1.0 / 6.0) + e4Pr * (Real)(1.0 / 24.0);
+            const Real b2 = be * be;
+            s.L1 += f * be;
+            s.L2 += f * (ga + (Real)0.5 * b2);
+            s.L3 += f * (de + be * ga + b2 * be * (Real)(1.0 / 6.0));
+            s.L4 += f * (ep + be * de + (Real)0.5 * b2 * ga + (Real)0.5 * ga * ga + b2 * b2 * (Real)(1.0 / 24.0));
+        } else {
+            const Real w = f * inv;
+            s.A0 += w * ux; s.A1 += w * uy; s.A2 += w * uz;
+            s.B00 += w * c00; s.B01 += w * c01; s.B02 += w * c02;
+            s.B11 += w * c11; s.B12 += w * c12; s.B22 += w * c22;
+            if constexpr (Mode == kModeExact) {
+                const Real wq = w * inv;
+                const Real qx = wq * ux, qy = wq * uy, qz = wq * uz;
+                s.Q00 += qx * ux; s.Q01 += qx * uy; s.Q02 += qx * uz;
+                s.Q11 += qy * uy; s.Q12 += qy * uz; s.Q22 += qz * uz;
+            }
+        }
         ++cnt;
     }
 }
@@ -217,75 +282,61 @@ __device__ __forceinline__ void pair_term(PairSums<Real> &s, unsigned &cnt, Real
 // Upper-triangle index of (r, c), r <= c, in row-major order of a 6x6 matrix.
 __host__ __device__ constexpr int ut(int r, int c) { return r * 6 - (r * (r - 1)) / 2 + (c - r); }
 
-// FP64 tail of an iteration (one lane per pair): frame change of the summed
-// terms, connection term, damped solve, retraction, stage and stop logic.
-__device__ __forceinline__ void finish_iteration(PairDev &P, State &St, const double tot[kNumSums],
-                                                 unsigned long long tot_pairs, int stage) {
-    // Back to the caller's frame.  With K = -c^ and A = [[I, 0], [K, I]] (the
-    // adjoint of the recentring translation): g = A^T g', H_main = A^T H' A.
-    // In 3x3 blocks H' = [[P, Q], [Q^T, S]] this is
-    //   [[P + QK + (QK)^T + K^T S K,  Q + (SK)^T], [Q^T + SK,  S]].
-    const double cx = P.centre[0], cy = P.centre[1], cz = P.centre[2];
-    const double K[3][3] = {{0.0, cz, -cy}, {-cz, 0.0, cx}, {cy, -cx, 0.0}};
+// ------------------------------------------------------------------ FP64 step
+
+// Caller-frame g and a symmetric 6x6 term from recentred-frame sums (f at
+// tot[0], g' at tot[1..6], the symmetric term's upper triangle at tot[off..]).
+// With K = -c^ and A = [[I, 0], [K, I]] (the adjoint of the recentring
+// translation): g = A^T g', X = A^T X' A; in 3x3 blocks X' = [[P, Q], [Q^T, S]]
+//   X = [[P + QK + (QK)^T + K^T S K,  Q + (SK)^T], [Q^T + SK,  S]].
+__device__ __forceinline__ void frame_sym(const double c[3], const double *upper, double sig, double X[6][6]) {
+    const double K[3][3] = {{0.0, c[2], -c[1]}, {-c[2], 0.0, c[0]}, {c[1], -c[0], 0.0}};
     double Pm[3][3], Q[3][3], S[3][3];
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            Pm[r][c] = tot[7 + ut(r < c ? r : c, r < c ? c : r)];
-            Q[r][c] = tot[7 + ut(r, 3 + c)];
-            S[r][c] = tot[7 + ut(3 + (r < c ? r : c), 3 + (r < c ? c : r))];
+        for (int q = 0; q < 3; ++q) {
+            Pm[r][q] = upper[ut(r < q ? r : q, r < q ? q : r)];
+            Q[r][q] = upper[ut(r, 3 + q)];
+            S[r][q] = upper[ut(3 + (r < q ? r : q), 3 + (r < q ? q : r))];
         }
     double QK[3][3], SK[3][3], KSK[3][3];
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            QK[r][c] = Q[r][0] * K[0][c] + Q[r][1] * K[1][c] + Q[r][2] * K[2][c];
-            SK[r][c] = S[r][0] * K[0][c] + S[r][1] * K[1][c] + S[r][2] * K[2][c];
+        for (int q = 0; q < 3; ++q) {
+            QK[r][q] = Q[r][0] * K[0][q] + Q[r][1] * K[1][q] + Q[r][2] * K[2][q];
+            SK[r][q] = S[r][0] * K[0][q] + S[r][1] * K[1][q] + S[r][2] * K[2][q];
         }
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) KSK[r][c] = K[0][r] * SK[0][c] + K[1][r] * SK[1][c] + K[2][r] * SK[2][c];
-    const double sig = P.sigma2;
-    double g[6], Hm[6][6];
-    {
-        const double gw[3] = {tot[1], tot[2], tot[3]}, gv[3] = {tot[4], tot[5], tot[6]};
-        // g_w = g'_w + K^T g'_v, g_v = g'_v
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            g[r] = sig * (gw[r] + K[0][r] * gv[0] + K[1][r] * gv[1] + K[2][r] * gv[2]);
-            g[3 + r] = sig * gv[r];
-        }
-    }
+        for (int q = 0; q < 3; ++q) KSK[r][q] = K[0][r] * SK[0][q] + K[1][r] * SK[1][q] + K[2][r] * SK[2][q];
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            Hm[r][c] = sig * (Pm[r][c] + QK[r][c] + QK[c][r] + KSK[r][c]);
-            Hm[r][3 + c] = sig * (Q[r][c] + SK[c][r]);
-            Hm[3 + r][c] = sig * (Q[c][r] + SK[r][c]);
-            Hm[3 + r][3 + c] = sig * S[r][c];
+        for (int q = 0; q < 3; ++q) {
+            X[r][q] = sig * (Pm[r][q] + QK[r][q] + QK[q][r] + KSK[r][q]);
+            X[r][3 + q] = sig * (Q[r][q] + SK[q][r]);
+            X[3 + r][q] = sig * (Q[q][r] + SK[r][q]);
+            X[3 + r][3 + q] = sig * S[r][q];
         }
-    const double f = sig * tot[0];
-    // H_GN = H_main + C(g), C(g) = [[-1/2 g_w^, 0], [-g_v^, 0]]
-    double H[6][6];
+}
+
+__device__ __forceinline__ void frame_grad(const double c[3], const double *tot, double sig, double g[6]) {
+    const double K[3][3] = {{0.0, c[2], -c[1]}, {-c[2], 0.0, c[0]}, {c[1], -c[0], 0.0}};
+    const double gw[3] = {tot[1], tot[2], tot[3]}, gv[3] = {tot[4], tot[5], tot[6]};
+    // g_w = g'_w + K^T g'_v, g_v = g'_v
 #pragma unroll
-    for (int r = 0; r < 6; ++r)
-#pragma unroll
-        for (int c = 0; c < 6; ++c) H[r][c] = Hm[r][c];
-    {
-        const double Gw[3][3] = {{0.0, -g[2], g[1]}, {g[2], 0.0, -g[0]}, {-g[1], g[0], 0.0}};
-        const double Gv[3][3] = {{0.0, -g[5], g[4]}, {g[5], 0.0, -g[3]}, {-g[4], g[3], 0.0}};
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                H[r][c] -= 0.5 * Gw[r][c];
-                H[3 + r][c] -= Gv[r][c];
-            }
+    for (int r = 0; r < 3; ++r) {
+        g[r] = sig * (gw[r] + K[0][r] * gv[0] + K[1][r] * gv[1] + K[2][r] * gv[2]);
+        g[3 + r] = sig * gv[r];
     }
+}
+
+// Record the evaluation (f, g, H) of the current pass.
+__device__ __forceinline__ void record_eval(PairDev &P, State &St, double f, const double g[6], const double H[6][6],
+                                            unsigned long long tot_pairs) {
     St.f = f;
 #pragma unroll
     for (int a = 0; a < 6; ++a) St.g[a] = g[a];
@@ -295,23 +346,10 @@ __device__ __forceinline__ void finish_iteration(PairDev &P, State &St, const do
         for (int c = 0; c < 6; ++c) St.H[6 * r + c] = H[r][c];
     St.pairs_last = (long long)tot_pairs;
     if (P.iter_pairs && St.iter < P.max_iters) P.iter_pairs[St.iter] = (long long)tot_pairs;
-    if (P.eval_only) {
-        St.done = 1;
-        return;
-    }
-    if (tot_pairs == 0) {
-        St.status = GCVO_ERR_NO_PAIRS;
-        St.done = 1;
-        return;
-    }
-    double xi[6];
-    const int dmp = damped_step(H, Hm, g, xi);
-    if (dmp < 0) {
-        St.status = GCVO_ERR_SINGULAR;
-        St.done = 1;
-        return;
-    }
-    if (dmp > 0) ++St.damped;
+}
+
+// T <- T exp(xi^), then the stage and stop logic.
+__device__ __forceinline__ void apply_step(PairDev &P, State &St, const double xi[6], int stage) {
     double E[4][4], T[4][4];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -350,6 +388,200 @@ __device__ __forceinline__ void finish_iteration(PairDev &P, State &St, const do
     if (St.iter >= P.max_iters) St.done = 1;
 }
 
+// Gauss-Newton (or Newton) iteration tail.  tot: the pass's sums.  With
+// exact != 0, tot also holds T1 (upper triangle at kNumSums) and
+// M = sum_j y_j a_j^T (row-major at kNumSums + 21), and the system matrix is
+// H_main + T1 + T2 + C(g) with T2' = [[M - tr(M) I, (g'_v)^], [0, 0]], which
+// maps to the caller's frame as [[P2 + Q2 K, Q2], [0, 0]].  The damped
+// fallback always uses H_main.
+__device__ __forceinline__ void finish_iteration(PairDev &P, State &St, const double *tot,
+                                                 unsigned long long tot_pairs, int stage, bool exact) {
+    const double sig = P.sigma2;
+    double g[6], Hm[6][6], H[6][6];
+    frame_grad(P.centre, tot, sig, g);
+    frame_sym(P.centre, tot + 7, sig, Hm);
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) H[r][c] = Hm[r][c];
+    if (exact) {
+        double T1[6][6];
+        frame_sym(P.centre, tot + kNumSums, sig, T1);
+        const double *M = tot + kNumSums + 21;
+        const double tr = M[0] + M[4] + M[8];
+        const double c0 = P.centre[0], c1 = P.centre[1], c2 = P.centre[2];
+        const double K[3][3] = {{0.0, c2, -c1}, {-c2, 0.0, c0}, {c1, -c0, 0.0}};
+        const double Q2[3][3] = {{0.0, -g[5], g[4]}, {g[5], 0.0, -g[3]}, {-g[4], g[3], 0.0}};   // (g_v)^
+        double P2[3][3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                P2[r][c] = sig * (M[3 * r + c] - (r == c ? tr : 0.0)) + Q2[r][0] * K[0][c] + Q2[r][1] * K[1][c] +
+                           Q2[r][2] * K[2][c];
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) H[r][c] += T1[r][c];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                H[r][c] += P2[r][c];
+                H[r][3 + c] += Q2[r][c];
+            }
+    }
+    // + C(g) = [[-1/2 g_w^, 0], [-g_v^, 0]]
+    {
+        const double Gw[3][3] = {{0.0, -g[2], g[1]}, {g[2], 0.0, -g[0]}, {-g[1], g[0], 0.0}};
+        const double Gv[3][3] = {{0.0, -g[5], g[4]}, {g[5], 0.0, -g[3]}, {-g[4], g[3], 0.0}};
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                H[r][c] -= 0.5 * Gw[r][c];
+                H[3 + r][c] -= Gv[r][c];
+            }
+    }
+    record_eval(P, St, sig * tot[0], g, H, tot_pairs);
+    if (P.eval_only) {
+        St.done = 1;
+        return;
+    }
+    if (tot_pairs == 0) {
+        St.status = GCVO_ERR_NO_PAIRS;
+        St.done = 1;
+        return;
+    }
+    double xi[6];
+    const int dmp = damped_step(H, Hm, g, xi);
+    if (dmp < 0) {
+        St.status = GCVO_ERR_SINGULAR;
+        St.done = 1;
+        return;
+    }
+    if (dmp > 0) ++St.damped;
+    apply_step(P, St, xi, stage);
+}
+
+// First-order solver, gradient pass done: store the unit ascent direction and
+// hand over to the line pass (a zero gradient is a zero step).
+__device__ __forceinline__ void finish_direction(PairDev &P, State &St, const double *tot,
+                                                 unsigned long long tot_pairs, int stage) {
+    const double sig = P.sigma2;
+    double g[6], Hm[6][6];
+    frame_grad(P.centre, tot, sig, g);
+    frame_sym(P.centre, tot + 7, sig, Hm);
+    record_eval(P, St, sig * tot[0], g, Hm, tot_pairs);
+    if (tot_pairs == 0) {
+        St.status = GCVO_ERR_NO_PAIRS;
+        St.done = 1;
+        return;
+    }
+    double n2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) n2 += g[a] * g[a];
+    const double gn = sqrt(n2);
+    if (!(gn > 0.0) || !isfinite(gn)) {
+        const double zero[6] = {0, 0, 0, 0, 0, 0};
+        apply_step(P, St, zero, stage);
+        return;
+    }
+#pragma unroll
+    for (int a = 0; a < 6; ++a) St.dir[a] = g[a] / gn;
+    St.gnorm = gn;
+    St.phase = 1;
+}
+
+// G'(s) = c1 + 2 c2 s + 3 c3 s^2 + 4 c4 s^3.
+__device__ __forceinline__ double dG(const double c[5], double s) {
+    return c[1] + s * (2.0 * c[2] + s * (3.0 * c[3] + s * (4.0 * c[4])));
+}
+
+// Root of G' in [a, b] with G'(a) > 0 >= G'(b): Newton steps kept inside the
+// shrinking bracket, bisection when a step leaves it.
+__device__ __forceinline__ double bracketed_root(const double c[5], double a, double b) {
+    double x = 0.5 * (a + b);
+    for (int it = 0; it < 200; ++it) {
+        const double v = dG(c, x);
+        if (v > 0.0) a = x;
+        else b = x;
+        if (!(b - a > 1e-16 * b)) break;
+        const double d = 2.0 * c[2] + x * (6.0 * c[3] + x * 12.0 * c[4]);
+        double xn = (d != 0.0) ? x - v / d : 0.5 * (a + b);
+        if (!(xn > a && xn < b)) xn = 0.5 * (a + b);
+        x = xn;
+    }
+    return b;
+}
+
+// Step length along the unit direction (eq. (linesearch) with the quadratic
+// fallback reading): 1 = smallest positive root of G', 2 = maximiser of the
+// quadratic part, 0 = none (the caller applies the minimum step).
+__device__ __forceinline__ int line_step(const double c[5], double &s) {
+    s = 0.0;
+    if (!(c[1] > 0.0)) return 0;
+    // G''(s) = 2 c2 + 6 c3 s + 12 c4 s^2: its positive roots split s > 0 into
+    // intervals where G' is monotone.
+    double crit[2];
+    int nc = 0;
+    const double qa = 12.0 * c[4], qb = 6.0 * c[3], qc = 2.0 * c[2];
+    if (qa != 0.0) {
+        const double disc = qb * qb - 4.0 * qa * qc;
+        if (disc >= 0.0) {
+            const double sq = sqrt(disc);
+            // numerically stable pair of roots
+            const double qq = -0.5 * (qb + (qb >= 0.0 ? sq : -sq));
+            double r1 = (qq != 0.0) ? qc / qq : 0.0, r2 = qq / qa;
+            if (r1 > r2) { const double t = r1; r1 = r2; r2 = t; }
+            if (r1 > 0.0) crit[nc++] = r1;
+            if (r2 > 0.0 && r2 != r1) crit[nc++] = r2;
+        }
+    } else if (qb != 0.0) {
+        const double r = -qc / qb;
+        if (r > 0.0) crit[nc++] = r;
+    }
+    double lo = 0.0;
+    for (int k = 0; k < nc; ++k) {
+        if (dG(c, crit[k]) <= 0.0) {
+            s = bracketed_root(c, lo, crit[k]);
+            return 1;
+        }
+        lo = crit[k];
+    }
+    const double lead = (c[4] != 0.0) ? c[4] : (c[3] != 0.0) ? c[3] : c[2];
+    if (lead < 0.0) {
+        double hi = (lo > 0.0) ? 2.0 * lo : 1e-30;
+        for (int it = 0; it < 4000 && dG(c, hi) > 0.0; ++it) hi *= 2.0;
+        if (dG(c, hi) <= 0.0) {
+            s = bracketed_root(c, lo, hi);
+            return 1;
+        }
+    }
+    if (c[2] < 0.0) {
+        s = c[1] / (-2.0 * c[2]);
+        return 2;
+    }
+    return 0;
+}
+
+// First-order solver, line pass done: step mu * g with mu = max(min_step, s / |g|).
+__device__ __forceinline__ void finish_line(PairDev &P, State &St, const double *tot, int stage) {
+    double c[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) c[k] = P.sigma2 * tot[k];
+    double s;
+    const int kind = line_step(c, s);
+    if (kind != 1) ++St.damped;
+    const double s_min = P.min_step * St.gnorm;
+    if (!(s > s_min)) s = s_min;
+    double xi[6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) xi[a] = s * St.dir[a];
+    St.phase = 0;
+    apply_step(P, St, xi, stage);
+}
+
 // Lane layout of the pair kernel: a wave serves kGroupsPerWave neighbouring
 // source points (sorted order), kGroupLanes lanes each.  Every point lists the
 // contiguous x-rows of target cells that meet its cutoff ball; its lanes walk
@@ -357,19 +589,26 @@ __device__ __forceinline__ void finish_iteration(PairDev &P, State &St, const do
 // idles at row ends.  The 16 partial sums of a point are combined with xor
 // shuffles.
 template <typename Real>
+__device__ __forceinline__ void group_sum(Real &v) {
+#pragma unroll
+    for (int off = kGroupLanes / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+}
+
+template <typename Real, int Mode>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_iterate(PairDev *pairs,
                                                                                           const BlockTask *tasks) {
+    constexpr int NS = ModeInfo<Mode>::sums;
     const BlockTask task = tasks[blockIdx.x];
     PairDev &P = pairs[task.pair];
     State &St = *P.st;
-    if (St.done) return;
+    if (St.done || St.phase != (Mode == kModeLine ? 1 : 0)) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int grp = lane / kGroupLanes, q = lane % kGroupLanes;
     const int stage = St.stage;
     const double ell = P.ell[stage];
     const Grid G = *P.t_grid[stage];
     const int *cells = P.t_cells[stage];
-    const int nt = P.n_t, ns = P.n_s;
+    const int ns = P.n_s;
     constexpr bool kExact = sizeof(Real) == 8;   // FP64: recentre the original coordinates in FP64
     const float4 *trec = reinterpret_cast<const float4 *>(P.t_sorted[stage]);
     const double c0 = P.centre[0], c1 = P.centre[1], c2 = P.centre[2];
@@ -418,6 +657,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     const double rc = P.cutoff_scale * ell;
     const Real rc2 = (Real)(rc * rc);
     const Real kexp = (Real)(-1.4426950408889634 / (ell * ell));   // f = exp2(q * inv_det * kexp)
+    const Real k2 = (Real)(2.0 / (ell * ell));
+    LineDir<Real> ld = {};
+    if constexpr (Mode == kModeLine) {
+        // Direction in the recentred frame: w' = w, v' = v - c x w.
+        const double w[3] = {St.dir[0], St.dir[1], St.dir[2]};
+        const double v[3] = {St.dir[3] - (c1 * w[2] - c2 * w[1]), St.dir[4] - (c2 * w[0] - c0 * w[2]),
+                             St.dir[5] - (c0 * w[1] - c1 * w[0])};
+        double e[3] = {w[1] * y2 - w[2] * y1 + v[0], w[2] * y0 - w[0] * y2 + v[1], w[0] * y1 - w[1] * y0 + v[2]};
+        for (int k = 0; k < 4; ++k) {
+            for (int a = 0; a < 3; ++a) ld.e[k][a] = (Real)e[a];
+            const double n[3] = {w[1] * e[2] - w[2] * e[1], w[2] * e[0] - w[0] * e[2], w[0] * e[1] - w[1] * e[0]};
+            e[0] = n[0]; e[1] = n[1]; e[2] = n[2];
+        }
+    }
 
     // Candidate rows of this point: the x-rows of cells (fixed cy, cz) that meet
     // the ball of radius rcm = 1.001 * cutoff around y, each clipped to the x
@@ -471,9 +724,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 const Real xx = kExact ? (Real)((double)rcc.y - c0) : (Real)ra.x;
                 const Real xy = kExact ? (Real)((double)rcc.z - c1) : (Real)ra.y;
                 const Real xz = kExact ? (Real)((double)rcc.w - c2) : (Real)ra.z;
-                pair_term<Real>(s, cnt, xx - yx, xy - yy, xz - yz, (Real)ra.w + p00, (Real)rb.x + p01,
-                                (Real)rb.y + p02, (Real)rb.z + p11, (Real)rb.w + p12, (Real)rcc.x + p22, rc2,
-                                kexp);
+                pair_term<Real, Mode>(s, cnt, xx - yx, xy - yy, xz - yz, (Real)ra.w + p00, (Real)rb.x + p01,
+                                      (Real)rb.y + p02, (Real)rb.z + p11, (Real)rb.w + p12, (Real)rcc.x + p22, rc2,
+                                      kexp, k2, ld);
                 o += kGroupLanes;
                 while (r < nb && o >= rl) {
                     o -= rl;
@@ -485,84 +738,119 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     }
 
     // Combine the 16 lanes of each point.
-#pragma unroll
-    for (int off = kGroupLanes / 2; off >= 1; off >>= 1) {
-        s.F += __shfl_xor(s.F, off, 64);
-        s.A0 += __shfl_xor(s.A0, off, 64); s.A1 += __shfl_xor(s.A1, off, 64); s.A2 += __shfl_xor(s.A2, off, 64);
-        s.B00 += __shfl_xor(s.B00, off, 64); s.B01 += __shfl_xor(s.B01, off, 64);
-        s.B02 += __shfl_xor(s.B02, off, 64); s.B11 += __shfl_xor(s.B11, off, 64);
-        s.B12 += __shfl_xor(s.B12, off, 64); s.B22 += __shfl_xor(s.B22, off, 64);
+    group_sum(s.F);
+    if constexpr (Mode == kModeLine) {
+        group_sum(s.L1); group_sum(s.L2); group_sum(s.L3); group_sum(s.L4);
+    } else {
+        group_sum(s.A0); group_sum(s.A1); group_sum(s.A2);
+        group_sum(s.B00); group_sum(s.B01); group_sum(s.B02);
+        group_sum(s.B11); group_sum(s.B12); group_sum(s.B22);
+        if constexpr (Mode == kModeExact) {
+            group_sum(s.Q00); group_sum(s.Q01); group_sum(s.Q02);
+            group_sum(s.Q11); group_sum(s.Q12); group_sum(s.Q22);
+        }
     }
 
-    // Finish the source point (lane 0 of its group): the 28 sums, recentred frame.
-    __shared__ Real sh_pts[kPointsPerBlock][kNumSums];
+    // Finish the source point (lane 0 of its group): the pass's sums, recentred frame.
+    __shared__ Real sh_pts[kPointsPerBlock][NS];
     __shared__ unsigned sh_cnt[kBlock / 64];
     if (q == 0) {
-        Real v[kNumSums];
-        const Real k2 = valid ? (Real)(2.0 / (ell * ell)) : (Real)0;
-        const Real a0 = k2 * s.A0, a1 = k2 * s.A1, a2 = k2 * s.A2;
-        const Real b00 = k2 * s.B00, b01 = k2 * s.B01, b02 = k2 * s.B02;
-        const Real b11 = k2 * s.B11, b12 = k2 * s.B12, b22 = k2 * s.B22;
-        v[0] = valid ? s.F : (Real)0;
-        // g_w = -y x a, g_v = -a
-        v[1] = -(yy * a2 - yz * a1);
-        v[2] = -(yz * a0 - yx * a2);
-        v[3] = -(yx * a1 - yy * a0);
-        v[4] = -a0; v[5] = -a1; v[6] = -a2;
-        // Y = y^, M = Y B; H blocks: top-left Y B Y, top-right -Y B, bottom-right -B
-        const Real B[3][3] = {{b00, b01, b02}, {b01, b11, b12}, {b02, b12, b22}};
-        const Real Y[3][3] = {{0, -yz, yy}, {yz, 0, -yx}, {-yy, yx, 0}};
-        Real M[3][3];
-        for (int r = 0; r < 3; ++r)
-            for (int c = 0; c < 3; ++c) M[r][c] = Y[r][0] * B[0][c] + Y[r][1] * B[1][c] + Y[r][2] * B[2][c];
-        for (int r = 0; r < 3; ++r)
-            for (int c = r; c < 3; ++c) v[7 + ut(r, c)] = M[r][0] * Y[0][c] + M[r][1] * Y[1][c] + M[r][2] * Y[2][c];
-        for (int r = 0; r < 3; ++r)
-            for (int c = 0; c < 3; ++c) v[7 + ut(r, 3 + c)] = -M[r][c];
-        for (int r = 0; r < 3; ++r)
-            for (int c = r; c < 3; ++c) v[7 + ut(3 + r, 3 + c)] = -B[r][c];
+        Real v[NS];
+        if constexpr (Mode == kModeLine) {
+            v[0] = valid ? s.F : (Real)0;
+            v[1] = valid ? s.L1 : (Real)0;
+            v[2] = valid ? s.L2 : (Real)0;
+            v[3] = valid ? s.L3 : (Real)0;
+            v[4] = valid ? s.L4 : (Real)0;
+        } else {
+            const Real kk = valid ? k2 : (Real)0;
+            const Real a0 = kk * s.A0, a1 = kk * s.A1, a2 = kk * s.A2;
+            const Real b00 = kk * s.B00, b01 = kk * s.B01, b02 = kk * s.B02;
+            const Real b11 = kk * s.B11, b12 = kk * s.B12, b22 = kk * s.B22;
+            v[0] = valid ? s.F : (Real)0;
+            // g_w = -y x a, g_v = -a
+            v[1] = -(yy * a2 - yz * a1);
+            v[2] = -(yz * a0 - yx * a2);
+            v[3] = -(yx * a1 - yy * a0);
+            v[4] = -a0; v[5] = -a1; v[6] = -a2;
+            // Y = y^, M = Y B; H blocks: top-left Y B Y, top-right -Y B, bottom-right -B
+            const Real B[3][3] = {{b00, b01, b02}, {b01, b11, b12}, {b02, b12, b22}};
+            const Real Y[3][3] = {{0, -yz, yy}, {yz, 0, -yx}, {-yy, yx, 0}};
+            Real M[3][3];
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) M[r][c] = Y[r][0] * B[0][c] + Y[r][1] * B[1][c] + Y[r][2] * B[2][c];
+            for (int r = 0; r < 3; ++r)
+                for (int c = r; c < 3; ++c) v[7 + ut(r, c)] = M[r][0] * Y[0][c] + M[r][1] * Y[1][c] + M[r][2] * Y[2][c];
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) v[7 + ut(r, 3 + c)] = -M[r][c];
+            for (int r = 0; r < 3; ++r)
+                for (int c = r; c < 3; ++c) v[7 + ut(3 + r, 3 + c)] = -B[r][c];
+            if constexpr (Mode == kModeExact) {
+                // T1 = J^T Q J = [[-Y Q Y, Y Q], [-Q Y, Q]], Q = (2/ell^2)^2 * sum (f/det^2) u' u'^T
+                const Real k4 = kk * kk;
+                const Real Qm[3][3] = {{k4 * s.Q00, k4 * s.Q01, k4 * s.Q02},
+                                       {k4 * s.Q01, k4 * s.Q11, k4 * s.Q12},
+                                       {k4 * s.Q02, k4 * s.Q12, k4 * s.Q22}};
+                Real N[3][3];
+                for (int r = 0; r < 3; ++r)
+                    for (int c = 0; c < 3; ++c) N[r][c] = Y[r][0] * Qm[0][c] + Y[r][1] * Qm[1][c] + Y[r][2] * Qm[2][c];
+                for (int r = 0; r < 3; ++r)
+                    for (int c = r; c < 3; ++c)
+                        v[kNumSums + ut(r, c)] = -(N[r][0] * Y[0][c] + N[r][1] * Y[1][c] + N[r][2] * Y[2][c]);
+                for (int r = 0; r < 3; ++r)
+                    for (int c = 0; c < 3; ++c) v[kNumSums + ut(r, 3 + c)] = N[r][c];
+                for (int r = 0; r < 3; ++r)
+                    for (int c = r; c < 3; ++c) v[kNumSums + ut(3 + r, 3 + c)] = Qm[r][c];
+                // sum_j y_j a_j^T
+                const Real yv[3] = {yx, yy, yz}, av[3] = {a0, a1, a2};
+                for (int r = 0; r < 3; ++r)
+                    for (int c = 0; c < 3; ++c) v[kNumSums + 21 + 3 * r + c] = yv[r] * av[c];
+            }
+        }
         const int slot = wave * kGroupsPerWave + grp;
 #pragma unroll
-        for (int k = 0; k < kNumSums; ++k) sh_pts[slot][k] = v[k];
+        for (int k = 0; k < NS; ++k) sh_pts[slot][k] = v[k];
     }
     cnt = wave_sum(cnt);
     if (lane == 0) sh_cnt[wave] = cnt;
     __syncthreads();
     Real *part = reinterpret_cast<Real *>(P.partials) + (size_t)task.block * kPartialStride;
-    if (tid < kNumSums) {
+    if (tid < NS) {
         Real acc = 0;
         for (int pnt = 0; pnt < kPointsPerBlock; ++pnt) acc += sh_pts[pnt][tid];
         part[tid] = acc;
     }
-    if (tid == kNumSums) {
+    if (tid == NS) {
         unsigned long long c = 0;
         for (int w = 0; w < kBlock / 64; ++w) c += sh_cnt[w];
-        *reinterpret_cast<unsigned long long *>(part + kNumSums) = c;
+        *reinterpret_cast<unsigned long long *>(part + NS + (NS & 1) * (sizeof(Real) == 4)) = c;
     }
-
 }
 
 // Cross-block reduction of one pair's block sums, split over kReduceSplit
 // blocks per pair.  Block s takes the pair-kernel blocks b = s (mod
-// kReduceSplit); in it, thread t adds component t % 32 (the 28 sums and the
-// pair count) over every 32nd of those blocks with a Kahan-compensated sum in
-// the pair-term precision, and the 32 slices are added in FP64 in a fixed
+// kReduceSplit); in it, thread t adds component t % W (the NS sums and the
+// pair count) over every (1024 / W)-th of those blocks with a Kahan-compensated
+// sum in the pair-term precision, and the slices are added in FP64 in a fixed
 // order.  The step kernel adds the kReduceSplit results, again in fixed order.
 constexpr int kReduceThreads = 1024;
-constexpr int kSlices = kReduceThreads / 32;
 
-template <typename Real>
+template <typename Real, int Mode>
 __global__ __launch_bounds__(kReduceThreads) void k_reduce(PairDev *pairs) {
+    constexpr int NS = ModeInfo<Mode>::sums;
+    constexpr int W = (NS + 1 <= 32) ? 32 : 64;
+    constexpr int kSlices = kReduceThreads / W;
+    constexpr int kCountAt = NS + (NS & 1) * (sizeof(Real) == 4);   // 8-byte aligned slot of the pair count
     PairDev &P = pairs[blockIdx.y];
     State &St = *P.st;
-    if (St.done) return;
+    if (St.done || St.phase != (Mode == kModeLine ? 1 : 0)) return;
     const int split = blockIdx.x;
-    const int tid = threadIdx.x, ck = tid & 31, slice = tid >> 5;
+    const int tid = threadIdx.x, ck = tid % W, slice = tid / W;
     const Real *parts = reinterpret_cast<const Real *>(P.partials);
-    __shared__ double sh[kSlices][33];
+    __shared__ double sh[kSlices][W + 1];
     __shared__ unsigned long long sh_c[kSlices];
     const int nb = P.n_blocks, step = kSlices * kReduceSplit;
-    if (ck < kNumSums) {
+    if (ck < NS) {
         Real sm = 0, cp = 0;
         for (int b = split + kReduceSplit * slice; b < nb; b += step) {
             const Real y = parts[(size_t)b * kPartialStride + ck] - cp;
@@ -571,18 +859,18 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(PairDev *pairs) {
             sm = t;
         }
         sh[slice][ck] = (double)sm - (double)cp;
-    } else if (ck == kNumSums) {
+    } else if (ck == NS) {
         unsigned long long c = 0;
         for (int b = split + kReduceSplit * slice; b < nb; b += step)
-            c += *reinterpret_cast<const unsigned long long *>(parts + (size_t)b * kPartialStride + kNumSums);
+            c += *reinterpret_cast<const unsigned long long *>(parts + (size_t)b * kPartialStride + kCountAt);
         sh_c[slice] = c;
     }
     __syncthreads();
-    if (tid < kNumSums) {
+    if (tid < NS) {
         double acc = 0.0;
         for (int sl = 0; sl < kSlices; ++sl) acc += sh[sl][tid];
         St.sub[split][tid] = acc;
-    } else if (tid == kNumSums) {
+    } else if (tid == NS) {
         unsigned long long c = 0;
         for (int sl = 0; sl < kSlices; ++sl) c += sh_c[sl];
         St.sub_pairs[split] = c;
@@ -590,16 +878,20 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(PairDev *pairs) {
 }
 
 // The FP64 step of one pair, on one lane (its registers are not shared with
-// any wide kernel).  A pair that finishes decrements the batch's count of
-// active pairs, which the host polls.
+// any wide kernel).  Step kinds: 0 Gauss-Newton, 1 Newton, 2 first-order
+// direction (after a gradient pass), 3 first-order line step.  A pair that
+// finishes decrements the batch's count of active pairs, which the host polls.
+template <int Kind>
 __global__ __launch_bounds__(64) void k_step(PairDev *pairs, int *active) {
+    constexpr int Mode = Kind == 1 ? kModeExact : Kind == 3 ? kModeLine : kModeGN;
+    constexpr int NS = ModeInfo<Mode>::sums;
     PairDev &P = pairs[blockIdx.x];
     State &St = *P.st;
-    if (St.done || threadIdx.x != 0) return;
-    double tot[kNumSums];
+    if (St.done || threadIdx.x != 0 || St.phase != (Mode == kModeLine ? 1 : 0)) return;
+    double tot[NS];
     unsigned long long c = 0;
 #pragma unroll
-    for (int k = 0; k < kNumSums; ++k) {
+    for (int k = 0; k < NS; ++k) {
         double acc = 0.0;
 #pragma unroll
         for (int sp = 0; sp < kReduceSplit; ++sp) acc += St.sub[sp][k];
@@ -607,7 +899,9 @@ __global__ __launch_bounds__(64) void k_step(PairDev *pairs, int *active) {
     }
 #pragma unroll
     for (int sp = 0; sp < kReduceSplit; ++sp) c += St.sub_pairs[sp];
-    finish_iteration(P, St, tot, c, St.stage);
+    if constexpr (Kind == 0 || Kind == 1) finish_iteration(P, St, tot, c, St.stage, Kind == 1);
+    else if constexpr (Kind == 2) finish_direction(P, St, tot, c, St.stage);
+    else finish_line(P, St, tot, St.stage);
     if (St.done) atomicSub(active, 1);
 }
 
@@ -621,18 +915,40 @@ __global__ void k_count_active(const PairDev *pairs, int n_pairs, int *active) {
     if (threadIdx.x == 0) *active = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
+template <typename Real, int Mode, int Kind>
+static void launch_pass(PairDev *pairs, int n_pairs, BlockTask *tasks, int n_tasks, int *active, hipStream_t s,
+                        hipEvent_t *&ev) {
+    if (ev) hipEventRecord(*ev++, s);
+    hipLaunchKernelGGL((k_iterate<Real, Mode>), dim3(n_tasks), dim3(kBlock), 0, s, pairs, tasks);
+    if (ev) hipEventRecord(*ev++, s);
+    hipLaunchKernelGGL((k_reduce<Real, Mode>), dim3(kReduceSplit, n_pairs), dim3(kReduceThreads), 0, s, pairs);
+    hipLaunchKernelGGL((k_step<Kind>), dim3(n_pairs), dim3(64), 0, s, pairs, active);
+}
+
+template <typename Real>
+static void launch_iteration(PairDev *pairs, int n_pairs, BlockTask *tasks, int n_tasks, int solver, int *active,
+                             hipStream_t s, hipEvent_t *&ev) {
+    if (solver == GCVO_SOLVER_NEWTON) {
+        launch_pass<Real, kModeExact, 1>(pairs, n_pairs, tasks, n_tasks, active, s, ev);
+    } else if (solver == GCVO_SOLVER_FIRST_ORDER) {
+        launch_pass<Real, kModeGN, 2>(pairs, n_pairs, tasks, n_tasks, active, s, ev);
+        launch_pass<Real, kModeLine, 3>(pairs, n_pairs, tasks, n_tasks, active, s, ev);
+    } else {
+        launch_pass<Real, kModeGN, 0>(pairs, n_pairs, tasks, n_tasks, active, s, ev);
+    }
+}
+
+int passes_per_iteration(int solver) { return solver == GCVO_SOLVER_FIRST_ORDER ? 2 : 1; }
+
 hipError_t launch_iterations(PairDev *pairs, int n_pairs, BlockTask *tasks, int n_tasks, int n_iters,
-                             int precision, int *active, hipStream_t s) {
+                             int precision, int solver, int *active, hipStream_t s, hipEvent_t *events) {
     if (n_tasks <= 0) return hipSuccess;
+    hipEvent_t *ev = events;
     for (int it = 0; it < n_iters; ++it) {
-        if (precision == GCVO_PRECISION_FP64) {
-            hipLaunchKernelGGL(k_iterate<double>, dim3(n_tasks), dim3(kBlock), 0, s, pairs, tasks);
-            hipLaunchKernelGGL(k_reduce<double>, dim3(kReduceSplit, n_pairs), dim3(kReduceThreads), 0, s, pairs);
-        } else {
-            hipLaunchKernelGGL(k_iterate<float>, dim3(n_tasks), dim3(kBlock), 0, s, pairs, tasks);
-            hipLaunchKernelGGL(k_reduce<float>, dim3(kReduceSplit, n_pairs), dim3(kReduceThreads), 0, s, pairs);
-        }
-        hipLaunchKernelGGL(k_step, dim3(n_pairs), dim3(64), 0, s, pairs, active);
+        if (precision == GCVO_PRECISION_FP64)
+            launch_iteration<double>(pairs, n_pairs, tasks, n_tasks, solver, active, s, ev);
+        else
+            launch_iteration<float>(pairs, n_pairs, tasks, n_tasks, solver, active, s, ev);
     }
     return hipGetLastError();
 }

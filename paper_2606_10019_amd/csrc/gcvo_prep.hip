@@ -186,6 +186,9 @@ __global__ void k_setup(PairDev *pairs, int n_pairs) {
     S.xi_l1 = 0.0;
     S.pairs_last = 0;
     S.iter = S.stage = S.stage_iter = S.converged = S.damped = 0;
+    S.phase = 0;
+    S.gnorm = 0.0;
+    for (int a = 0; a < 6; ++a) S.dir[a] = 0.0;
     for (int s = 0; s < kMaxStages; ++s) S.stage_iters[s] = 0;
     S.status = P.nonfinite ? GCVO_ERR_INVALID : GCVO_OK;
     S.done = P.nonfinite ? 1 : 0;

@@ -30,6 +30,9 @@ GCVO_ERR_HIP = -6
 GCVO_ERR_CAPACITY = -7
 GCVO_PRECISION_FP32 = 0
 GCVO_PRECISION_FP64 = 1
+GCVO_SOLVER_GN = 0
+GCVO_SOLVER_NEWTON = 1
+GCVO_SOLVER_FIRST_ORDER = 2
 GCVO_MAX_STAGES = 16
 
 EXPORTED = ["gcvo_default_params", "gcvo_workspace_size", "gcvo_register", "gcvo_batch_workspace_size",
@@ -49,7 +52,8 @@ class gcvo_params(ctypes.Structure):
                 ("anneal_factor", ctypes.c_double), ("cutoff_scale", ctypes.c_double),
                 ("knn", ctypes.c_int), ("eig_ratio_min", ctypes.c_double), ("sigma2", ctypes.c_double),
                 ("max_iters", ctypes.c_int), ("max_iters_per_stage", ctypes.c_int),
-                ("tol", ctypes.c_double), ("stage_tol", ctypes.c_double), ("precision", ctypes.c_int)]
+                ("tol", ctypes.c_double), ("stage_tol", ctypes.c_double), ("precision", ctypes.c_int),
+                ("solver", ctypes.c_int), ("min_step", ctypes.c_double)]
 
 
 class gcvo_info(ctypes.Structure):
