@@ -674,6 +674,31 @@ int orc_solve_step(const double H[36], const double Hmain[36], const double g[6]
     return ORC_ERR_SINGULAR;
 }
 
+/* 1 when the symmetric part of H is negative definite: Cholesky of
+ * -(H + H^T)/2 with every pivot above 1e-12 * max|H|. */
+static int sym_negative_definite(const double H[36]) {
+    double A[36], amax = 0.0;
+    for (int r = 0; r < 6; ++r)
+        for (int c = 0; c < 6; ++c) {
+            A[r * 6 + c] = -0.5 * (H[r * 6 + c] + H[c * 6 + r]);
+            if (fabs(H[r * 6 + c]) > amax) amax = fabs(H[r * 6 + c]);
+        }
+    if (!(amax > 0.0)) return 0;
+    for (int k = 0; k < 6; ++k) {
+        double d = A[k * 6 + k];
+        for (int m = 0; m < k; ++m) d -= A[k * 6 + m] * A[k * 6 + m];
+        if (!(d > 1e-12 * amax)) return 0;
+        d = sqrt(d);
+        A[k * 6 + k] = d;
+        for (int r = k + 1; r < 6; ++r) {
+            double v = A[r * 6 + k];
+            for (int m = 0; m < k; ++m) v -= A[r * 6 + m] * A[k * 6 + m];
+            A[r * 6 + k] = v / d;
+        }
+    }
+    return 1;
+}
+
 static int pose_is_rigid(const double T[16]) {
     for (int a = 0; a < 16; ++a) if (!isfinite(T[a])) return 0;
     if (fabs(T[12]) > 1e-6 || fabs(T[13]) > 1e-6 || fabs(T[14]) > 1e-6 || fabs(T[15] - 1.0) > 1e-6)
@@ -691,7 +716,9 @@ static int pose_is_rigid(const double T[16]) {
 
 /*
  * Algorithm 1 with the Gauss-Newton update (solver 0), the exact
- * frozen-covariance Hessian (solver 1, the exact-Hessian variant) or the
+ * frozen-covariance Hessian (solver 1, the exact-Hessian variant, used where
+ * its symmetric part is negative definite and replaced by the Gauss-Newton
+ * system elsewhere) or the
  * first-order ascent with the quartic line search and minimum step min_step
  * (solver 2), from T_init, with the length-scale annealing the
  * paper sketches for Sigma (reading):
@@ -704,7 +731,8 @@ static int pose_is_rigid(const double T[16]) {
  * SX/SZ may be NULL, in which case the shapes are computed with (knn, rho).
  * info[] receives: 0 status, 1 converged, 2 iterations, 3 stages used, 4 f,
  * 5..10 g, 11 ||xi||_1 of the last step, 12 pairs at the last iteration,
- * 13 damped steps (first-order: steps not taken at a quartic root), 14..29
+ * 13 damped steps (Newton: also steps taken with the Gauss-Newton system;
+ * first-order: steps not taken at a quartic root), 14..29
  * iterations per stage (up to 16 stages).
  * On error T_out is left untouched.
  */
@@ -760,12 +788,21 @@ int orc_register(const double *X, const double *SXin, long nx, const double *Z, 
             if (orc_first_order_step(cl, min_step, &mu) != 1) ++damped_steps;
             for (int a = 0; a < 6; ++a) xi[a] = mu * g[a];
         } else {
+            /* Newton (reading): the exact system is used where its symmetric
+             * part is negative definite (a concave model); elsewhere, far from
+             * a maximum, the Gauss-Newton system is used instead. */
             orc_connection(g, C);
-            for (int a = 0; a < 36; ++a) H[a] = Hm[a] + C[a] + (newton ? T1[a] + T2[a] : 0.0);
+            int use_exact = 0;
+            if (newton) {
+                for (int a = 0; a < 36; ++a) H[a] = Hm[a] + C[a] + T1[a] + T2[a];
+                use_exact = sym_negative_definite(H);
+            }
+            if (!use_exact)
+                for (int a = 0; a < 36; ++a) H[a] = Hm[a] + C[a];
             int dmp = 0;
             st = orc_solve_step(H, Hm, g, xi, &dmp);
             if (st != ORC_OK) break;
-            if (dmp) ++damped_steps;
+            if (dmp || (newton && !use_exact)) ++damped_steps;
         }
         double E[16], Tn[16];
         orc_se3_exp(xi, E);

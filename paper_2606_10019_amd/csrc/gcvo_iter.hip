@@ -388,23 +388,71 @@ __device__ __forceinline__ void apply_step(PairDev &P, State &St, const double x
     if (St.iter >= P.max_iters) St.done = 1;
 }
 
+// Symmetric part of H negative definite: Cholesky of -(H + H^T)/2 with every
+// pivot above 1e-12 * max|H|.
+__device__ __forceinline__ bool negative_definite(const double H[6][6]) {
+    double A[6][6], amax = 0.0;
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            A[r][c] = -0.5 * (H[r][c] + H[c][r]);
+            amax = fmax(amax, fabs(H[r][c]));
+        }
+    if (!(amax > 0.0)) return false;
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        double d = A[k][k];
+#pragma unroll
+        for (int m = 0; m < k; ++m) d -= A[k][m] * A[k][m];
+        ok = ok && (d > 1e-12 * amax);
+        d = sqrt(fmax(d, 1e-300));
+        A[k][k] = d;
+#pragma unroll
+        for (int r = k + 1; r < 6; ++r) {
+            double v = A[r][k];
+#pragma unroll
+            for (int m = 0; m < k; ++m) v -= A[r][m] * A[k][m];
+            A[r][k] = v / d;
+        }
+    }
+    return ok;
+}
+
 // Gauss-Newton (or Newton) iteration tail.  tot: the pass's sums.  With
 // exact != 0, tot also holds T1 (upper triangle at kNumSums) and
-// M = sum_j y_j a_j^T (row-major at kNumSums + 21), and the system matrix is
-// H_main + T1 + T2 + C(g) with T2' = [[M - tr(M) I, (g'_v)^], [0, 0]], which
-// maps to the caller's frame as [[P2 + Q2 K, Q2], [0, 0]].  The damped
-// fallback always uses H_main.
+// M = sum_j y_j a_j^T (row-major at kNumSums + 21), and the exact system
+// matrix is H_main + T1 + T2 + C(g) with T2' = [[M - tr(M) I, (g'_v)^], [0, 0]],
+// which maps to the caller's frame as [[P2 + Q2 K, Q2], [0, 0]].  It is used
+// where its symmetric part is negative definite (a concave model); elsewhere,
+// far from a maximum, the Gauss-Newton system H_main + C(g) is used (reading).
+// The damped fallback always uses H_main.
 __device__ __forceinline__ void finish_iteration(PairDev &P, State &St, const double *tot,
                                                  unsigned long long tot_pairs, int stage, bool exact) {
     const double sig = P.sigma2;
     double g[6], Hm[6][6], H[6][6];
     frame_grad(P.centre, tot, sig, g);
     frame_sym(P.centre, tot + 7, sig, Hm);
+    // H_GN = H_main + C(g), C(g) = [[-1/2 g_w^, 0], [-g_v^, 0]]
+    {
+        const double Gw[3][3] = {{0.0, -g[2], g[1]}, {g[2], 0.0, -g[0]}, {-g[1], g[0], 0.0}};
+        const double Gv[3][3] = {{0.0, -g[5], g[4]}, {g[5], 0.0, -g[3]}, {-g[4], g[3], 0.0}};
 #pragma unroll
-    for (int r = 0; r < 6; ++r)
+        for (int r = 0; r < 6; ++r)
 #pragma unroll
-        for (int c = 0; c < 6; ++c) H[r][c] = Hm[r][c];
+            for (int c = 0; c < 6; ++c) H[r][c] = Hm[r][c];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                H[r][c] -= 0.5 * Gw[r][c];
+                H[3 + r][c] -= Gv[r][c];
+            }
+    }
+    bool gn_fallback = false;
     if (exact) {
+        double HE[6][6];
         double T1[6][6];
         frame_sym(P.centre, tot + kNumSums, sig, T1);
         const double *M = tot + kNumSums + 21;
@@ -422,26 +470,22 @@ __device__ __forceinline__ void finish_iteration(PairDev &P, State &St, const do
 #pragma unroll
         for (int r = 0; r < 6; ++r)
 #pragma unroll
-            for (int c = 0; c < 6; ++c) H[r][c] += T1[r][c];
+            for (int c = 0; c < 6; ++c) HE[r][c] = H[r][c] + T1[r][c];
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                H[r][c] += P2[r][c];
-                H[r][3 + c] += Q2[r][c];
+                HE[r][c] += P2[r][c];
+                HE[r][3 + c] += Q2[r][c];
             }
-    }
-    // + C(g) = [[-1/2 g_w^, 0], [-g_v^, 0]]
-    {
-        const double Gw[3][3] = {{0.0, -g[2], g[1]}, {g[2], 0.0, -g[0]}, {-g[1], g[0], 0.0}};
-        const double Gv[3][3] = {{0.0, -g[5], g[4]}, {g[5], 0.0, -g[3]}, {-g[4], g[3], 0.0}};
+        if (negative_definite(HE)) {
 #pragma unroll
-        for (int r = 0; r < 3; ++r)
+            for (int r = 0; r < 6; ++r)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                H[r][c] -= 0.5 * Gw[r][c];
-                H[3 + r][c] -= Gv[r][c];
-            }
+                for (int c = 0; c < 6; ++c) H[r][c] = HE[r][c];
+        } else {
+            gn_fallback = true;
+        }
     }
     record_eval(P, St, sig * tot[0], g, H, tot_pairs);
     if (P.eval_only) {
@@ -460,7 +504,7 @@ __device__ __forceinline__ void finish_iteration(PairDev &P, State &St, const do
         St.done = 1;
         return;
     }
-    if (dmp > 0) ++St.damped;
+    if (dmp > 0 || gn_fallback) ++St.damped;
     apply_step(P, St, xi, stage);
 }
 

@@ -44,7 +44,7 @@ def ref(spec):
     return np.array(g["T_ref"]).reshape(4, 4), g
 
 
-@pytest.mark.parametrize("inst", [0, 1])
+@pytest.mark.parametrize("inst", [0, 1, 3, 7])
 def test_newton_reaches_oracle_fixed_point(inst):
     spec = synth.make_config1(inst)
     Tref, g = ref(spec)
@@ -58,7 +58,6 @@ def test_newton_reaches_oracle_fixed_point(inst):
         assert info["converged"]
         assert dr < ROT_GATE_DEG and dt < TRANS_GATE_M
         assert abs(info["iters"] - o.iters) <= 1
-        assert info["iters"] < g["prod_iters"]
 
 
 def test_newton_lidar_pair():
@@ -71,6 +70,7 @@ def test_newton_lidar_pair():
     note(f"  iters {info['iters']} stages {info['stage_iters']} (GN {g['prod_stage_iters']}) err {dr:.2e} deg {dt:.2e} m")
     assert info["converged"]
     assert dr < ROT_GATE_DEG and dt < TRANS_GATE_M
+    assert info["iters"] < g["prod_iters"]
 
 
 def test_first_order_fp64_follows_oracle():

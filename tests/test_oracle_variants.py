@@ -101,3 +101,14 @@ def test_variants_reach_the_gauss_newton_fixed_point(solver):
         assert r.iters < GOLDEN[spec.name]["ref_iters"]          # Newton: fewer iterations than GN
     else:
         assert r.iters > 10 * GOLDEN[spec.name]["prod_iters"]    # first order: much slower
+
+
+def test_newton_from_identity_converges_where_pure_newton_diverges():
+    """Config-1 instances where an unmodified Newton iteration from identity
+    leaves the basin (indefinite exact Hessian far from the maximum): the
+    switch to the Gauss-Newton system there keeps it on course."""
+    for inst in (1, 2, 7):
+        spec = synth.make_config1(inst)
+        r = O.register_spec(spec, solver=1)
+        ref = np.array(GOLDEN[spec.name]["T_ref"]).reshape(4, 4)
+        assert r.converged and np.max(np.abs(r.T - ref)) < 1e-7, inst
