@@ -10,10 +10,16 @@ device memory before the timed region; poses are on the host when it ends.
 value = registrations/s counting only registrations whose pose lies within
 1e-3 deg / 1e-5 m of the FP64 oracle's fixed point for the same input.
 
-roofline: the pair kernel (transform, pair terms, per-point finish, block
-reduction, last-block solve), FP32 VALU bound.  A second pass over the same
-steps brackets every launch of that kernel with HIP events on the stream it runs
-on; algorithmic FLOP = 76 per pair within the cutoff + 230 per source point.
+roofline: the pair kernel k_iterate (transform, pair terms, per-point finish,
+block partial sums), FP32 VALU bound.  A second pass over the same steps
+brackets every launch of that kernel with HIP events on the stream it runs on;
+algorithmic FLOP = 76 per pair within the cutoff + 230 per source point.
+
+Further legs (reported under config): the same pairs registered together by one
+batch call; the RGB-D precision pair with FP32 and FP64 kernels; the
+exact-Hessian solver; the learned warm start on held-out large-motion pairs
+against the plain single-pair path; optionally (--objects) the 256 object
+pairs in one batch call.
 
 cpu_baseline: the FP64 oracle, as it stands, registering one of the same pairs
 on the host's cores.
@@ -104,6 +110,95 @@ def objects_leg(gcvo, synth, golden, dev, rot_err_deg, trans_err_m, n_pairs=256)
     return out
 
 
+def _make_c5_eval(i):
+    from paper_2606_10019_amd import synth
+    return synth.make_config5(i, "eval")
+
+
+def warmstart_leg(gcvo, synth, dev, rot_err_deg, trans_err_m, n_pairs=64, workers=16):
+    """Held-out large-motion LiDAR pairs (yaw up to 15 deg, up to 3 m): the plain
+    single-pair path from identity, the plain batch from identity, and the
+    batched warm start (network prediction, refine, objective fallback), each
+    counted at 1e-3 deg / 1e-5 m of plain G-CVO's fixed point from the true
+    motion."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    import torch
+    from paper_2606_10019_amd import warmstart
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        specs = list(ex.map(_make_c5_eval, range(n_pairs), chunksize=2))
+    print(f"[bench] warm start: generated {n_pairs} pairs in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    ps = warmstart.PairSet.from_specs(specs, dev)
+    params = [gcvo.params_from_spec(s) for s in specs]
+    refs, rinfo = gcvo.gcvo_register_batch(ps.targets, ps.tgt_off, ps.sources, ps.src_off,
+                                           np.array([s.T_true for s in specs]), params)
+    keep = [k for k in range(n_pairs) if rinfo[k]["converged"]]
+    net = warmstart.Network.load(device=dev)
+
+    def in_gate(T, infos):
+        return sum(1 for k in keep if infos[k]["converged"] and rot_err_deg(T[k], refs[k]) <= 1e-3
+                   and trans_err_m(T[k], refs[k]) <= 1e-5)
+
+    clouds = [(ps.targets[ps.tgt_off[k]:ps.tgt_off[k + 1]], ps.sources[ps.src_off[k]:ps.src_off[k + 1]])
+              for k in range(n_pairs)]
+    ws = gcvo.workspace(max(gcvo.gcvo_workspace_size(len(s.target), len(s.source), p)
+                            for s, p in zip(specs, params)), dev)
+    warmstart.register_warm(net, ps, params)            # warm-up of every path
+    gcvo.gcvo_register(clouds[0][0], clouds[0][1], None, params[0], ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    single = [gcvo.gcvo_register(tg, sr, None, p, ws=ws) for (tg, sr), p in zip(clouds, params)]
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    n_single = in_gate([T for T, _ in single], [i for _, i in single])
+    t0 = time.perf_counter()
+    Tb, ib = gcvo.gcvo_register_batch(ps.targets, ps.tgt_off, ps.sources, ps.src_off, None, params)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    n_batch = in_gate(Tb, ib)
+    t0 = time.perf_counter()
+    Tw, iw, rec = warmstart.register_warm(net, ps, params)
+    torch.cuda.synchronize()
+    t_warm = time.perf_counter() - t0
+    n_warm = in_gate(Tw, iw)
+    out = {"workload": f"lidar_pair_large_motion_15deg_3m_{n_pairs}pairs", "pairs_with_reference": len(keep),
+           "plain_single": {"in_gate": n_single, "seconds": t_single, "registrations_per_s": n_single / t_single},
+           "plain_batched": {"in_gate": n_batch, "seconds": t_batch, "registrations_per_s": n_batch / t_batch},
+           "warm_batched": {"in_gate": n_warm, "seconds": t_warm, "registrations_per_s": n_warm / t_warm,
+                            "fallbacks": len(rec["fallback"]),
+                            "mean_iterations": float(np.mean([i["iters"] for i in iw]))},
+           "gain_warm_batched_over_plain_single": (n_warm / t_warm) / max(n_single / t_single, 1e-12)}
+    print(f"[bench] warm start: single plain {n_single}/{len(keep)} in {t_single:.3f} s; batched plain {n_batch} in "
+          f"{t_batch:.3f} s; batched warm {n_warm} in {t_warm:.3f} s ({len(rec['fallback'])} fallbacks)",
+          file=sys.stderr, flush=True)
+    return out
+
+
+def solver_leg(gcvo, specs, clouds, params, refs, ws, rot_err_deg, trans_err_m, reps=4):
+    """The LiDAR pairs with the exact-Hessian (Newton) solver: time and
+    iterations per registration next to Gauss-Newton's, same gate."""
+    import torch
+    out = {}
+    for name, solver in (("gauss_newton", gcvo.GCVO_SOLVER_GN), ("newton_exact_hessian", gcvo.GCVO_SOLVER_NEWTON)):
+        ps = [gcvo.params_from_spec(s, solver=solver) for s in specs]
+        gcvo.gcvo_register(clouds[0][0], clouds[0][1], None, ps[0], ws=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = [gcvo.gcvo_register(clouds[k % len(specs)][0], clouds[k % len(specs)][1], None, ps[k % len(specs)],
+                                  ws=ws) for k in range(reps)]
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        ok = sum(1 for k, (T, i) in enumerate(res) if i["converged"] and rot_err_deg(T, refs[k % len(specs)]) <= 1e-3
+                 and trans_err_m(T, refs[k % len(specs)]) <= 1e-5)
+        out[name] = {"ms_per_registration": 1e3 * dt, "in_gate": ok, "registrations": reps,
+                     "mean_iterations": float(np.mean([i["iters"] for _, i in res]))}
+    print(f"[bench] solvers: {json.dumps(out)}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +206,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true", help="skip the RGB-D FP32/FP64 precision leg")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched LiDAR leg")
+    ap.add_argument("--no-warmstart", action="store_true", help="skip the warm-start leg")
+    ap.add_argument("--no-solvers", action="store_true", help="skip the Newton-solver leg")
     ap.add_argument("--objects", action="store_true",
                     help="add the 256 object-pair batch leg (one gcvo_register_batch call)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -200,6 +298,9 @@ def main():
               "gate", file=sys.stderr, flush=True)
 
     precision = None if args.no_precision else precision_leg(gcvo, synth, golden, dev, rot_err_deg, trans_err_m)
+    solvers = None if args.no_solvers else solver_leg(gcvo, specs, clouds, params, refs, ws, rot_err_deg,
+                                                      trans_err_m)
+    warm = None if args.no_warmstart else warmstart_leg(gcvo, synth, dev, rot_err_deg, trans_err_m)
     objects = objects_leg(gcvo, synth, golden, dev, rot_err_deg, trans_err_m) if args.objects else None
 
     # Roofline pass: the same steps with every pair-kernel launch bracketed by events.
@@ -250,7 +351,8 @@ def main():
                    "registrations_in_gate": passed, "mean_iterations": float(np.mean(iters)),
                    "kernel_pairs_per_s": pairs_per_s,
                    "pct_fp32_valu_peak": 100.0 * achieved / FP32_VALU_PEAK_TFLOPS,
-                   "batched": batch, "precision": precision, "objects": objects},
+                   "batched": batch, "precision": precision, "solvers": solvers, "warmstart": warm,
+                   "objects": objects},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": None,
                      "kernel": "k_iterate<float>", "avg_launch_us": avg_launch_us,

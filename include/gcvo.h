@@ -85,11 +85,13 @@ extern "C" {
  *   NEWTON       exact frozen-covariance Hessian: H = H_main + T1 + T2 + C(g),
  *                T1 = sum f (J^T u)(J^T u)^T (product rule on f_ij), T2 =
  *                -sum f [u^ J; 0] (derivative of J_j), u = Sigma^{-1} r
- *                (eq. (direction_derivative_gradf) with Sigma frozen).  Used
- *                where the symmetric part of that system is negative definite
- *                (a concave model); elsewhere, far from a maximum where pure
- *                Newton steps diverge, the step is the Gauss-Newton one
- *                (reading).  The damped fallback uses H_main as for GN.
+ *                (eq. (direction_derivative_gradf) with Sigma frozen).  Its
+ *                step replaces the Gauss-Newton step where that system's
+ *                symmetric part is negative definite (a concave model), the
+ *                step ascends, and it is at most twice as long as the
+ *                Gauss-Newton step (reading: far from a maximum, pure Newton
+ *                steps leave the basin).  The damped fallback uses H_main as
+ *                for GN.
  *   FIRST_ORDER  T <- T exp(mu g^) (eq. (fo_update)) with mu from the quartic
  *                expansion of f along g (eq. (linesearch), App. "Line search";
  *                coefficients re-derived by expanding the kernel exponent along

@@ -716,9 +716,9 @@ static int pose_is_rigid(const double T[16]) {
 
 /*
  * Algorithm 1 with the Gauss-Newton update (solver 0), the exact
- * frozen-covariance Hessian (solver 1, the exact-Hessian variant, used where
- * its symmetric part is negative definite and replaced by the Gauss-Newton
- * system elsewhere) or the
+ * frozen-covariance Hessian (solver 1, the exact-Hessian variant, whose step
+ * replaces the Gauss-Newton step where the exact model is concave and the step
+ * stays within twice the Gauss-Newton step's length) or the
  * first-order ascent with the quartic line search and minimum step min_step
  * (solver 2), from T_init, with the length-scale annealing the
  * paper sketches for Sigma (reading):
@@ -788,20 +788,35 @@ int orc_register(const double *X, const double *SXin, long nx, const double *Z, 
             if (orc_first_order_step(cl, min_step, &mu) != 1) ++damped_steps;
             for (int a = 0; a < 6; ++a) xi[a] = mu * g[a];
         } else {
-            /* Newton (reading): the exact system is used where its symmetric
-             * part is negative definite (a concave model); elsewhere, far from
-             * a maximum, the Gauss-Newton system is used instead. */
             orc_connection(g, C);
-            int use_exact = 0;
-            if (newton) {
-                for (int a = 0; a < 36; ++a) H[a] = Hm[a] + C[a] + T1[a] + T2[a];
-                use_exact = sym_negative_definite(H);
-            }
-            if (!use_exact)
-                for (int a = 0; a < 36; ++a) H[a] = Hm[a] + C[a];
+            for (int a = 0; a < 36; ++a) H[a] = Hm[a] + C[a];
             int dmp = 0;
             st = orc_solve_step(H, Hm, g, xi, &dmp);
             if (st != ORC_OK) break;
+            int use_exact = 0;
+            if (newton) {
+                /* Newton (reading): the exact step replaces the Gauss-Newton
+                 * step where the exact system's symmetric part is negative
+                 * definite (a concave model), the step is an ascent direction,
+                 * and it is at most twice as long as the Gauss-Newton step (a
+                 * trust region borrowed from it).  Far from a maximum, pure
+                 * Newton steps leave the basin. */
+                double HE[36], mg[6], xn[6];
+                for (int a = 0; a < 36; ++a) HE[a] = H[a] + T1[a] + T2[a];
+                for (int a = 0; a < 6; ++a) mg[a] = -g[a];
+                if (sym_negative_definite(HE) && solve_lu(HE, mg, xn, 6, 1e-12)) {
+                    double gx = 0.0, nn = 0.0, ng = 0.0;
+                    for (int a = 0; a < 6; ++a) {
+                        gx += g[a] * xn[a];
+                        nn += xn[a] * xn[a];
+                        ng += xi[a] * xi[a];
+                    }
+                    if (gx > 0.0 && nn <= 4.0 * ng) {
+                        memcpy(xi, xn, sizeof xn);
+                        use_exact = 1;
+                    }
+                }
+            }
             if (dmp || (newton && !use_exact)) ++damped_steps;
         }
         double E[16], Tn[16];

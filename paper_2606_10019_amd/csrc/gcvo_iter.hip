@@ -35,6 +35,7 @@
 // the connection term (eq. (connection_se3)), solves in FP64 (damped Gauss-Newton
 // or Newton system, or the line-search root), retracts T <- T exp(xi^)
 // (eq. (gn_update)) and advances the stage/stop logic.
+#include <hip/hip_ext.h>
 #include <math.h>
 
 #include "gcvo_dev.h"
@@ -424,10 +425,11 @@ __device__ __forceinline__ bool negative_definite(const double H[6][6]) {
 // exact != 0, tot also holds T1 (upper triangle at kNumSums) and
 // M = sum_j y_j a_j^T (row-major at kNumSums + 21), and the exact system
 // matrix is H_main + T1 + T2 + C(g) with T2' = [[M - tr(M) I, (g'_v)^], [0, 0]],
-// which maps to the caller's frame as [[P2 + Q2 K, Q2], [0, 0]].  It is used
-// where its symmetric part is negative definite (a concave model); elsewhere,
-// far from a maximum, the Gauss-Newton system H_main + C(g) is used (reading).
-// The damped fallback always uses H_main.
+// which maps to the caller's frame as [[P2 + Q2 K, Q2], [0, 0]].  Reading: the
+// exact step replaces the (damped) Gauss-Newton step where the exact system's
+// symmetric part is negative definite, the step is an ascent direction, and it
+// is at most twice as long as the Gauss-Newton step; far from a maximum, pure
+// Newton steps leave the basin.  The damped fallback always uses H_main.
 __device__ __forceinline__ void finish_iteration(PairDev &P, State &St, const double *tot,
                                                  unsigned long long tot_pairs, int stage, bool exact) {
     const double sig = P.sigma2;
@@ -450,43 +452,6 @@ __device__ __forceinline__ void finish_iteration(PairDev &P, State &St, const do
                 H[3 + r][c] -= Gv[r][c];
             }
     }
-    bool gn_fallback = false;
-    if (exact) {
-        double HE[6][6];
-        double T1[6][6];
-        frame_sym(P.centre, tot + kNumSums, sig, T1);
-        const double *M = tot + kNumSums + 21;
-        const double tr = M[0] + M[4] + M[8];
-        const double c0 = P.centre[0], c1 = P.centre[1], c2 = P.centre[2];
-        const double K[3][3] = {{0.0, c2, -c1}, {-c2, 0.0, c0}, {c1, -c0, 0.0}};
-        const double Q2[3][3] = {{0.0, -g[5], g[4]}, {g[5], 0.0, -g[3]}, {-g[4], g[3], 0.0}};   // (g_v)^
-        double P2[3][3];
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                P2[r][c] = sig * (M[3 * r + c] - (r == c ? tr : 0.0)) + Q2[r][0] * K[0][c] + Q2[r][1] * K[1][c] +
-                           Q2[r][2] * K[2][c];
-#pragma unroll
-        for (int r = 0; r < 6; ++r)
-#pragma unroll
-            for (int c = 0; c < 6; ++c) HE[r][c] = H[r][c] + T1[r][c];
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                HE[r][c] += P2[r][c];
-                HE[r][3 + c] += Q2[r][c];
-            }
-        if (negative_definite(HE)) {
-#pragma unroll
-            for (int r = 0; r < 6; ++r)
-#pragma unroll
-                for (int c = 0; c < 6; ++c) H[r][c] = HE[r][c];
-        } else {
-            gn_fallback = true;
-        }
-    }
     record_eval(P, St, sig * tot[0], g, H, tot_pairs);
     if (P.eval_only) {
         St.done = 1;
@@ -504,7 +469,51 @@ __device__ __forceinline__ void finish_iteration(PairDev &P, State &St, const do
         St.done = 1;
         return;
     }
-    if (dmp > 0 || gn_fallback) ++St.damped;
+    bool used_exact = false;
+    if (exact) {
+        double HE[6][6];
+        {
+            double T1[6][6];
+            frame_sym(P.centre, tot + kNumSums, sig, T1);
+            const double *M = tot + kNumSums + 21;
+            const double tr = M[0] + M[4] + M[8];
+            const double c0 = P.centre[0], c1 = P.centre[1], c2 = P.centre[2];
+            const double K[3][3] = {{0.0, c2, -c1}, {-c2, 0.0, c0}, {c1, -c0, 0.0}};
+            const double Q2[3][3] = {{0.0, -g[5], g[4]}, {g[5], 0.0, -g[3]}, {-g[4], g[3], 0.0}};   // (g_v)^
+#pragma unroll
+            for (int r = 0; r < 6; ++r)
+#pragma unroll
+                for (int c = 0; c < 6; ++c) HE[r][c] = H[r][c] + T1[r][c];
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    HE[r][c] += sig * (M[3 * r + c] - (r == c ? tr : 0.0)) + Q2[r][0] * K[0][c] +
+                                Q2[r][1] * K[1][c] + Q2[r][2] * K[2][c];
+                    HE[r][3 + c] += Q2[r][c];
+                }
+        }
+        if (negative_definite(HE)) {
+            double b[6], xn[6];
+#pragma unroll
+            for (int a = 0; a < 6; ++a) b[a] = -g[a];
+            if (solve6(HE, b, xn, 1e-12)) {
+                double gx = 0.0, nn = 0.0, ng = 0.0;
+#pragma unroll
+                for (int a = 0; a < 6; ++a) {
+                    gx += g[a] * xn[a];
+                    nn += xn[a] * xn[a];
+                    ng += xi[a] * xi[a];
+                }
+                if (gx > 0.0 && nn <= 4.0 * ng) {
+#pragma unroll
+                    for (int a = 0; a < 6; ++a) xi[a] = xn[a];
+                    used_exact = true;
+                }
+            }
+        }
+    }
+    if (dmp > 0 || (exact && !used_exact)) ++St.damped;
     apply_step(P, St, xi, stage);
 }
 
@@ -962,9 +971,14 @@ __global__ void k_count_active(const PairDev *pairs, int n_pairs, int *active) {
 template <typename Real, int Mode, int Kind>
 static void launch_pass(PairDev *pairs, int n_pairs, BlockTask *tasks, int n_tasks, int *active, hipStream_t s,
                         hipEvent_t *&ev) {
-    if (ev) hipEventRecord(*ev++, s);
-    hipLaunchKernelGGL((k_iterate<Real, Mode>), dim3(n_tasks), dim3(kBlock), 0, s, pairs, tasks);
-    if (ev) hipEventRecord(*ev++, s);
+    if (ev) {
+        // events attached to the dispatch itself: they time the kernel, not the queue
+        hipExtLaunchKernelGGL((k_iterate<Real, Mode>), dim3(n_tasks), dim3(kBlock), 0, s, ev[0], ev[1], 0u, pairs,
+                              tasks);
+        ev += 2;
+    } else {
+        hipLaunchKernelGGL((k_iterate<Real, Mode>), dim3(n_tasks), dim3(kBlock), 0, s, pairs, tasks);
+    }
     hipLaunchKernelGGL((k_reduce<Real, Mode>), dim3(kReduceSplit, n_pairs), dim3(kReduceThreads), 0, s, pairs);
     hipLaunchKernelGGL((k_step<Kind>), dim3(n_pairs), dim3(64), 0, s, pairs, active);
 }
