@@ -203,6 +203,9 @@ struct ModeInfo {
     static constexpr int sums = Mode == kModeGN ? kNumSums : Mode == kModeExact ? kSumsExact : kSumsLine;
 };
 
+typedef float __attribute__((ext_vector_type(4))) vf4;
+typedef const vf4 __attribute__((address_space(1))) *GRec4;
+
 template <typename Real>
 struct PairSums {
     Real F, A0, A1, A2, B00, B01, B02, B11, B12, B22;   // Gauss-Newton terms
@@ -663,7 +666,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     const int *cells = P.t_cells[stage];
     const int ns = P.n_s;
     constexpr bool kExact = sizeof(Real) == 8;   // FP64: recentre the original coordinates in FP64
-    const float4 *trec = reinterpret_cast<const float4 *>(P.t_sorted[stage]);
+    // Target records through a global-address-space pointer: global (not
+    // flat) loads, which do not wait on LDS traffic.
+    const GRec4 trec = (GRec4)(P.t_sorted[stage]);
     const double c0 = P.centre[0], c1 = P.centre[1], c2 = P.centre[2];
 
     // Recentred pose T' = C^{-1} T C: R' = R, t' = R c + t - c.
@@ -771,20 +776,31 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 o -= rl;
                 if (++r < nb) { rs = rs_t[grp][r]; rl = rl_t[grp][r]; }
             }
+            // The whole 48-byte record of the next candidate is requested
+            // before the current one is evaluated (one memory round trip per
+            // candidate, overlapped with the pair arithmetic).
+            vf4 na = {}, nb4 = {}, nc = {};
+            if (r < nb) {
+                const GRec4 rec = trec + 3 * (size_t)(rs + o);
+                na = rec[0]; nb4 = rec[1]; nc = rec[2];
+            }
             while (r < nb) {
-                const float4 *rec = trec + 3 * (size_t)(rs + o);
-                const float4 ra = rec[0], rb = rec[1], rcc = rec[2];
+                const vf4 ra = na, rb = nb4, rcc = nc;
+                o += kGroupLanes;
+                while (r < nb && o >= rl) {
+                    o -= rl;
+                    if (++r < nb) { rs = rs_t[grp][r]; rl = rl_t[grp][r]; }
+                }
+                if (r < nb) {
+                    const GRec4 rec = trec + 3 * (size_t)(rs + o);
+                    na = rec[0]; nb4 = rec[1]; nc = rec[2];
+                }
                 const Real xx = kExact ? (Real)((double)rcc.y - c0) : (Real)ra.x;
                 const Real xy = kExact ? (Real)((double)rcc.z - c1) : (Real)ra.y;
                 const Real xz = kExact ? (Real)((double)rcc.w - c2) : (Real)ra.z;
                 pair_term<Real, Mode>(s, cnt, xx - yx, xy - yy, xz - yz, (Real)ra.w + p00, (Real)rb.x + p01,
                                       (Real)rb.y + p02, (Real)rb.z + p11, (Real)rb.w + p12, (Real)rcc.x + p22, rc2,
                                       kexp, k2, ld);
-                o += kGroupLanes;
-                while (r < nb && o >= rl) {
-                    o -= rl;
-                    if (++r < nb) { rs = rs_t[grp][r]; rl = rl_t[grp][r]; }
-                }
             }
             __builtin_amdgcn_wave_barrier();
         }
