@@ -11,8 +11,9 @@
  *   - per-point covariance from the n nearest points (Sec. "Anisotropic
  *     covariance", eq. (kernel)/(covariance)) with the eigenvalue bound of
  *     Remark 1, found by brute-force distance ranking;
- *   - the objective f(T) = sum_ij k(x_i, T^{-1} z_j) (eq. (rkhs_loss)) as a
- *     literal double loop over all (i, j), restricted to pairs within the cutoff;
+ *   - the objective f(T) = sum_ij c_ij k(x_i, T^{-1} z_j) (eq. (rkhs_loss)) as a
+ *     literal double loop over all (i, j), restricted to pairs within the cutoff,
+ *     with c_ij = <l^X_i, l^Z_j> from per-point label vectors (1 without labels);
  *   - the Riemannian gradient of Lemma 1 (eq. (gradient));
  *   - the Gauss-Newton Hessian -sum f J^T Sigma^{-1} J (eq. (hessian_gn)) plus
  *     the connection term of eq. (connection_se3);
@@ -285,10 +286,33 @@ static void shape6_to_mat(const double s[6], double S[9]) {
  * source point's slice is summed into its own slot and the slots are added in
  * j order, so the result does not depend on the thread count.
  */
+/* Label weight c_ij = <l^X_i, l^Z_j> of eq. (rkhs_loss) (pose-invariant
+ * per-point features, row-major [n][dim]); 1 without labels. */
+static double label_weight(const double *LX, const double *LZ, int dim, long i, long j) {
+    if (!LX || !LZ || dim <= 0) return 1.0;
+    double c = 0.0;
+    for (int d = 0; d < dim; ++d) c += LX[(size_t)i * dim + d] * LZ[(size_t)j * dim + d];
+    return c;
+}
+
+int orc_eval_l(const double *X, const double *SX, const double *LX, long nx, const double *Z, const double *SZ,
+               const double *LZ, long nz, int label_dim, const double T[16], const double *R_shape, double ell,
+               double cutoff, double sigma2, double *f_out, double g_out[6], double Hmain_out[36],
+               double *T1_out, double *T2_out, long long *npairs_out);
+
 int orc_eval(const double *X, const double *SX, long nx, const double *Z, const double *SZ, long nz,
              const double T[16], const double *R_shape, double ell, double cutoff, double sigma2,
              double *f_out, double g_out[6], double Hmain_out[36], double *T1_out, double *T2_out,
              long long *npairs_out) {
+    return orc_eval_l(X, SX, NULL, nx, Z, SZ, NULL, nz, 0, T, R_shape, ell, cutoff, sigma2, f_out, g_out, Hmain_out,
+                      T1_out, T2_out, npairs_out);
+}
+
+/* The same sums with every pair weighted by its label weight c_ij. */
+int orc_eval_l(const double *X, const double *SX, const double *LX, long nx, const double *Z, const double *SZ,
+               const double *LZ, long nz, int label_dim, const double T[16], const double *R_shape, double ell,
+               double cutoff, double sigma2, double *f_out, double g_out[6], double Hmain_out[36],
+               double *T1_out, double *T2_out, long long *npairs_out) {
     if (!X || !SX || !Z || !SZ || !T || nx < 0 || nz < 0 || !(ell > 0.0) || !f_out || !g_out ||
         !Hmain_out)
         return ORC_ERR_INVALID;
@@ -337,7 +361,7 @@ int orc_eval(const double *X, const double *SX, long nx, const double *Z, const 
             double u[3];
             matmul(Sinv, r3, u, 3, 3, 1);
             double quad = r3[0] * u[0] + r3[1] * u[1] + r3[2] * u[2];
-            double fij = sigma2 * exp(-0.5 * quad);
+            double fij = label_weight(LX, LZ, label_dim, i, j) * sigma2 * exp(-0.5 * quad);
             double Jtu[6], SinvJ[18], JtSJ[36];
             matmul(Jt, u, Jtu, 6, 3, 1);
             matmul(Sinv, J, SinvJ, 3, 3, 6);
@@ -455,9 +479,19 @@ void orc_se3_exp(const double xi[6], double T[16]) {
  * c[0] = sum f_ij, c[k] = sum f_ij g^k_ij (k = 1..4): G(t) ~ sum_k c[k] t^k.
  * Same pair set and loop order as orc_eval.
  */
+int orc_line_coeffs_l(const double *X, const double *SX, const double *LX, long nx, const double *Z,
+                      const double *SZ, const double *LZ, long nz, int label_dim, const double T[16], double ell,
+                      double cutoff, double sigma2, const double xi[6], double c_out[5], long long *npairs_out);
+
 int orc_line_coeffs(const double *X, const double *SX, long nx, const double *Z, const double *SZ, long nz,
                     const double T[16], double ell, double cutoff, double sigma2, const double xi[6],
                     double c_out[5], long long *npairs_out) {
+    return orc_line_coeffs_l(X, SX, NULL, nx, Z, SZ, NULL, nz, 0, T, ell, cutoff, sigma2, xi, c_out, npairs_out);
+}
+
+int orc_line_coeffs_l(const double *X, const double *SX, const double *LX, long nx, const double *Z,
+                      const double *SZ, const double *LZ, long nz, int label_dim, const double T[16], double ell,
+                      double cutoff, double sigma2, const double xi[6], double c_out[5], long long *npairs_out) {
     if (!X || !SX || !Z || !SZ || !T || !xi || !c_out || nx < 0 || nz < 0 || !(ell > 0.0))
         return ORC_ERR_INVALID;
     double *slot = (double *)calloc((size_t)(nz > 0 ? nz : 1) * 5, sizeof(double));
@@ -501,7 +535,7 @@ int orc_line_coeffs(const double *X, const double *SX, long nx, const double *Z,
             matmul(P, e[1], Pe1, 3, 3, 1);
             matmul(P, e[2], Pe2, 3, 3, 1);
             double quad = r3[0] * Pr[0] + r3[1] * Pr[1] + r3[2] * Pr[2];
-            double fij = sigma2 * exp(-0.5 * quad);
+            double fij = label_weight(LX, LZ, label_dim, i, j) * sigma2 * exp(-0.5 * quad);
             double e1Pr = 0, e2Pr = 0, e3Pr = 0, e4Pr = 0, e1Pe1 = 0, e2Pe2 = 0, e1Pe2 = 0, e3Pe1 = 0;
             for (int a = 0; a < 3; ++a) {
                 e1Pr += e[1][a] * Pr[a];
@@ -736,11 +770,28 @@ static int pose_is_rigid(const double T[16]) {
  * iterations per stage (up to 16 stages).
  * On error T_out is left untouched.
  */
+int orc_register_l(const double *X, const double *SXin, const double *LX, long nx, const double *Z,
+                   const double *SZin, const double *LZ, long nz, int label_dim, const double T_init[16],
+                   double ell, double ell_min, double alpha, double cutoff_scale, int knn, double rho,
+                   double sigma2, int max_iters, int max_iters_per_stage, double tol, double stage_tol, int solver,
+                   double min_step, double T_out[16], double info[32]);
+
 int orc_register(const double *X, const double *SXin, long nx, const double *Z, const double *SZin,
                  long nz, const double T_init[16], double ell, double ell_min, double alpha,
                  double cutoff_scale, int knn, double rho, double sigma2, int max_iters,
                  int max_iters_per_stage, double tol, double stage_tol, int solver, double min_step,
                  double T_out[16], double info[32]) {
+    return orc_register_l(X, SXin, NULL, nx, Z, SZin, NULL, nz, 0, T_init, ell, ell_min, alpha, cutoff_scale, knn,
+                          rho, sigma2, max_iters, max_iters_per_stage, tol, stage_tol, solver, min_step, T_out,
+                          info);
+}
+
+/* The registration with label weights c_ij (eq. (rkhs_loss)); labels may be NULL. */
+int orc_register_l(const double *X, const double *SXin, const double *LX, long nx, const double *Z,
+                   const double *SZin, const double *LZ, long nz, int label_dim, const double T_init[16],
+                   double ell, double ell_min, double alpha, double cutoff_scale, int knn, double rho,
+                   double sigma2, int max_iters, int max_iters_per_stage, double tol, double stage_tol, int solver,
+                   double min_step, double T_out[16], double info[32]) {
     const int newton = (solver == 1), first_order = (solver == 2);
     for (int a = 0; a < 32; ++a) info[a] = 0.0;
     if (!X || !Z || !T_init || !T_out || nx < 0 || nz < 0 || !(ell > 0.0) || !(ell_min > 0.0) ||
@@ -775,15 +826,16 @@ int orc_register(const double *X, const double *SXin, long nx, const double *Z, 
     long long np = 0;
     while (it < max_iters) {
         double Hm[36], T1[36], T2[36], C[36], H[36];
-        st = orc_eval(X, sx, nx, Z, sz, nz, T, NULL, cur_ell, cutoff_scale * cur_ell, sigma2, &f, g, Hm,
-                      newton ? T1 : NULL, newton ? T2 : NULL, &np);
+        st = orc_eval_l(X, sx, LX, nx, Z, sz, LZ, nz, label_dim, T, NULL, cur_ell, cutoff_scale * cur_ell, sigma2,
+                        &f, g, Hm, newton ? T1 : NULL, newton ? T2 : NULL, &np);
         if (st != ORC_OK) break;
         if (np == 0) { st = ORC_ERR_NO_PAIRS; break; }
         double xi[6];
         if (first_order) {
             /* gradient ascent along g with the line-search step (eq. (fo_update)) */
             double cl[5], mu;
-            st = orc_line_coeffs(X, sx, nx, Z, sz, nz, T, cur_ell, cutoff_scale * cur_ell, sigma2, g, cl, NULL);
+            st = orc_line_coeffs_l(X, sx, LX, nx, Z, sz, LZ, nz, label_dim, T, cur_ell, cutoff_scale * cur_ell,
+                                   sigma2, g, cl, NULL);
             if (st != ORC_OK) break;
             if (orc_first_order_step(cl, min_step, &mu) != 1) ++damped_steps;
             for (int a = 0; a < 6; ++a) xi[a] = mu * g[a];

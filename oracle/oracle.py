@@ -64,6 +64,13 @@ def lib() -> ctypes.CDLL:
         L.orc_line_coeffs.argtypes = [_dp, _dp, ctypes.c_long, _dp, _dp, ctypes.c_long, _dp, ctypes.c_double,
                                       ctypes.c_double, ctypes.c_double, _dp, _dp, _llp]
         L.orc_first_order_step.argtypes = [_dp, ctypes.c_double, _dp]
+        L.orc_eval_l.argtypes = [_dp, _dp, _dp, ctypes.c_long, _dp, _dp, _dp, ctypes.c_long, ctypes.c_int, _dp, _dp,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, _dp, _dp, _dp, _dp, _llp]
+        L.orc_register_l.argtypes = [_dp, _dp, _dp, ctypes.c_long, _dp, _dp, _dp, ctypes.c_long, ctypes.c_int, _dp,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                     ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                     ctypes.c_double, _dp, _dp]
         L.orc_num_threads.argtypes = []
         _lib = L
     return _lib
@@ -121,9 +128,23 @@ class Eval:
         return self.Hmain + connection(self.g)
 
 
+def _labels(LX, LZ, nx, nz):
+    if LX is None and LZ is None:
+        return None, None, 0
+    LX, LZ = _d(LX), _d(LZ)
+    LX = LX.reshape(nx, -1)
+    LZ = LZ.reshape(nz, -1)
+    if LX.shape[1] != LZ.shape[1]:
+        raise ValueError("label dimensions differ")
+    return np.ascontiguousarray(LX), np.ascontiguousarray(LZ), LX.shape[1]
+
+
 def evaluate(X, SX, Z, SZ, T, ell: float, cutoff: float | None, sigma2: float = 1.0,
-             R_shape=None, with_t: bool = False) -> Eval:
+             R_shape=None, with_t: bool = False, LX=None, LZ=None) -> Eval:
+    """f, g, H_main (and T1, T2) at T; LX, LZ: optional per-point label vectors
+    [n, d] whose inner products weight the pairs."""
     X, SX, Z, SZ, T = _d(X), _d(SX), _d(Z), _d(SZ), _d(T)
+    LX, LZ, dim = _labels(LX, LZ, len(X), len(Z))
     Rs = None if R_shape is None else _d(R_shape)
     f = ctypes.c_double()
     g = np.zeros(6)
@@ -131,9 +152,9 @@ def evaluate(X, SX, Z, SZ, T, ell: float, cutoff: float | None, sigma2: float = 
     T1 = np.zeros((6, 6)) if with_t else None
     T2 = np.zeros((6, 6)) if with_t else None
     npairs = ctypes.c_longlong()
-    st = lib().orc_eval(_p(X), _p(SX), len(X), _p(Z), _p(SZ), len(Z), _p(T), _p(Rs), float(ell),
-                        float(cutoff) if cutoff is not None else -1.0, float(sigma2),
-                        ctypes.byref(f), _p(g), _p(H), _p(T1), _p(T2), ctypes.byref(npairs))
+    st = lib().orc_eval_l(_p(X), _p(SX), _p(LX), len(X), _p(Z), _p(SZ), _p(LZ), len(Z), dim, _p(T), _p(Rs),
+                          float(ell), float(cutoff) if cutoff is not None else -1.0, float(sigma2),
+                          ctypes.byref(f), _p(g), _p(H), _p(T1), _p(T2), ctypes.byref(npairs))
     if st:
         raise OracleError(st, "orc_eval")
     return Eval(f.value, g, H, T1, T2, npairs.value)
@@ -204,9 +225,11 @@ def register(X, Z, T_init=None, *, SX=None, SZ=None, length_scale: float, length
              anneal_factor: float = 0.5, cutoff_scale: float = 3.0, knn: int = 10,
              eig_ratio_min: float = 0.01, sigma2: float = 1.0, max_iters: int = 30,
              max_iters_per_stage: int = 30, tol: float = 1e-6, stage_tol: float = 1e-4,
-             newton: bool = False, solver: int | None = None, min_step: float = 1e-10) -> RegResult:
+             newton: bool = False, solver: int | None = None, min_step: float = 1e-10, LX=None,
+             LZ=None) -> RegResult:
     """solver: 0 Gauss-Newton, 1 exact frozen-covariance Hessian (newton=True),
-    2 first-order ascent with the quartic line search."""
+    2 first-order ascent with the quartic line search.  LX, LZ: optional
+    per-point label vectors weighting the pairs."""
     solver = (1 if newton else 0) if solver is None else int(solver)
     X, Z = _d(X), _d(Z)
     T0 = np.eye(4) if T_init is None else _d(T_init)
@@ -215,7 +238,8 @@ def register(X, Z, T_init=None, *, SX=None, SZ=None, length_scale: float, length
     SZp = None if SZ is None else _d(SZ)
     Tout = np.zeros((4, 4))
     info = np.zeros(32)
-    st = lib().orc_register(_p(X), _p(SXp), len(X), _p(Z), _p(SZp), len(Z), _p(T0),
+    LXp, LZp, dim = _labels(LX, LZ, len(X), len(Z))
+    st = lib().orc_register_l(_p(X), _p(SXp), _p(LXp), len(X), _p(Z), _p(SZp), _p(LZp), len(Z), dim, _p(T0),
                             float(length_scale), float(lmin), float(anneal_factor), float(cutoff_scale),
                             int(knn), float(eig_ratio_min), float(sigma2), int(max_iters),
                             int(max_iters_per_stage), float(tol), float(stage_tol), solver, float(min_step),
