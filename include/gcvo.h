@@ -107,6 +107,7 @@ extern "C" {
 #define GCVO_MAX_KNN 16
 #define GCVO_MAX_STAGES 16
 #define GCVO_MAX_POINTS (1LL << 26) /* per cloud */
+#define GCVO_MAX_LABEL_DIM 4        /* entries of a label vector (the *_labeled calls) */
 
 typedef struct gcvo_params {
     double length_scale;      /* ell of the first stage, metres (> 0)                                   */
@@ -114,7 +115,9 @@ typedef struct gcvo_params {
     double anneal_factor;     /* alpha in (0, 1]; must be < 1 when min < length_scale                    */
     double cutoff_scale;      /* pair cutoff radius = cutoff_scale * ell (> 0; 3 in the paper's setups)  */
     int knn;                  /* n nearest points per covariance, self included, 2..GCVO_MAX_KNN (10)    */
-    double eig_ratio_min;     /* rho in (0, 1]: floor of lambda / lambda_max per point (Remark 1)         */
+    double eig_ratio_min;     /* rho in (0, 1]: floor of lambda / lambda_max per point (Remark 1); rho = 1:
+                                 every shape is the identity (isotropic kernel, Remark 3), no neighbours
+                                 are searched and Gauss-Newton uses the isotropic pair kernel            */
     double sigma2;            /* kernel amplitude sigma^2 (> 0; 1)                                       */
     int max_iters;            /* total Gauss-Newton iterations over all stages (>= 1)                    */
     int max_iters_per_stage;  /* iterations before a non-final stage is ended (>= 1)                     */
@@ -196,6 +199,39 @@ int gcvo_eval_fgh(const float *tgt_xyz, const float *tgt_shape6, long long n_tgt
                   const float *src_shape6, long long n_src, const double *T, double length_scale,
                   double cutoff, double sigma2, int precision, double *f, double *g, double *H,
                   long long *n_pairs, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Labelled pairs (eq. (rkhs_loss)): every point carries a label vector l in
+ * R^label_dim (1 <= label_dim <= GCVO_MAX_LABEL_DIM: intensities, colours,
+ * semantic class scores, one-hot classes), and each pair's kernel is weighted
+ * by the label inner product c_ij = <l^X_i, l^Z_j>:
+ *     f(T) = sum_{i,j} c_ij k(x_i, T^{-1} z_j).
+ * The gradient and every Hessian carry the same weight (c_ij does not depend
+ * on T).  Labels are caller-owned DEVICE memory, float32, [n][label_dim], in
+ * the order of the points; they are used as given (negative weights allowed,
+ * non-finite entries make the results non-finite).
+ *
+ * gcvo_register_batch_labeled: gcvo_register_batch with labels; pair k's labels
+ * are tgt_label[tgt_off[k] .. tgt_off[k+1]) and src_label[src_off[k] ..
+ * src_off[k+1]) (rows of label_dim floats).  Registering one labelled pair is a
+ * batch of one.  gcvo_eval_fgh_labeled: gcvo_eval_fgh with labels.
+ * The *_workspace_size_labeled functions size them (0 if invalid); other
+ * arguments, outputs and errors are those of the unlabelled calls, and
+ * label_dim outside 1..GCVO_MAX_LABEL_DIM is GCVO_ERR_INVALID.
+ */
+size_t gcvo_batch_workspace_size_labeled(int n_pairs, const long long *tgt_off, const long long *src_off,
+                                         const gcvo_params *p, int shared_params, int label_dim);
+int gcvo_register_batch_labeled(int n_pairs, const float *tgt_xyz, const float *tgt_label,
+                                const long long *tgt_off, const float *src_xyz, const float *src_label,
+                                const long long *src_off, int label_dim, const double *T_init,
+                                const gcvo_params *p, int shared_params, double *T_out, gcvo_info *info,
+                                void *workspace, size_t workspace_bytes, void *stream);
+size_t gcvo_eval_workspace_size_labeled(long long n_tgt, long long n_src, int label_dim);
+int gcvo_eval_fgh_labeled(const float *tgt_xyz, const float *tgt_shape6, const float *tgt_label, long long n_tgt,
+                          const float *src_xyz, const float *src_shape6, const float *src_label, long long n_src,
+                          int label_dim, const double *T, double length_scale, double cutoff, double sigma2,
+                          int precision, double *f, double *g, double *H, long long *n_pairs, void *workspace,
+                          size_t workspace_bytes, void *stream);
 
 /* Bytes of device workspace gcvo_point_shapes needs; 0 if invalid. */
 size_t gcvo_shapes_workspace_size(long long n);

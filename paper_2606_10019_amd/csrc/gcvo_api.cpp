@@ -94,7 +94,13 @@ struct PairInput {
     const float *tgt_shape = nullptr, *src_shape = nullptr;   // Eval
     float *shape_out = nullptr;                               // Shapes
     double eval_ell = 0.0, eval_cutoff = 0.0;                 // Eval
+    const float *tgt_label = nullptr, *src_label = nullptr;   // [n][label_dim] or null
+    int label_dim = 0;
 };
+
+// Register mode with eig_ratio_min = 1: every shape is the identity (Remark 3),
+// so no neighbourhoods are computed.
+bool isotropic(Mode mode, const PairInput &I) { return mode == Mode::Register && I.p.eig_ratio_min >= 1.0; }
 
 struct Plan {
     size_t bytes = 0;
@@ -108,6 +114,8 @@ struct Plan {
     char *desc_begin = nullptr;
     size_t desc_bytes = 0;
     int max_n = 0, max_job_n = 0, max_cells = 0;
+    bool labels = false;   // the pairs carry label vectors
+    bool iso = false;      // every pair is isotropic
 };
 
 // Lays out (base == nullptr: sizes) every device array of a batch.
@@ -121,7 +129,7 @@ void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &p
     for (int k = 0; k < np; ++k) {
         if (mode == Mode::Register) {
             nst[k] = stage_schedule(in[k].p, &ells[(size_t)k * kMaxStages]);
-            n_jobs += 3 + nst[k];
+            n_jobs += (isotropic(mode, in[k]) ? 1 : 3) + nst[k];
         } else if (mode == Mode::Eval) {
             nst[k] = 1;
             ells[(size_t)k * kMaxStages] = in[k].eval_ell;
@@ -139,6 +147,9 @@ void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &p
     pl.d_tasks = A.take<BlockTask>(std::max(n_tasks, 1));
     pl.desc_bytes = A.off - desc_start;
     pl.d_active = A.take<int>(1);
+    pl.labels = np > 0 && in[0].label_dim > 0;
+    pl.iso = np > 0;
+    for (int k = 0; k < np; ++k) pl.iso = pl.iso && isotropic(mode, in[k]);
     if (base) {
         pl.pairs.assign(np, PairDev{});
         pl.jobs.assign(std::max(n_jobs, 1), SortJob{});
@@ -155,6 +166,11 @@ void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &p
         P.src_xyz = I.src;
         P.n_t = nt;
         P.n_s = ns;
+        const bool iso = isotropic(mode, I);
+        P.iso = iso ? 1 : 0;
+        P.label_dim = (mode == Mode::Shapes) ? 0 : I.label_dim;
+        P.tgt_label = I.tgt_label;
+        P.src_label = I.src_label;
         P.n_stages = nst[k];
         for (int s = 0; s < nst[k]; ++s) P.ell[s] = ells[(size_t)k * kMaxStages + s];
         P.knn = I.p.knn;
@@ -177,11 +193,12 @@ void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &p
             P.s_shape = const_cast<float *>(I.src_shape);
             P.shapes_given = 1;
             P.eval_only = 1;
-        } else if (mode == Mode::Register) {
+        } else if (mode == Mode::Register && !iso) {
             P.t_shape = A.take<float>(6 * (size_t)nt);
             P.s_shape = A.take<float>(6 * (size_t)ns);
         }
         if (mode != Mode::Shapes) P.s_sorted = A.take<float>(kSortedRows * (size_t)ns);
+        if (P.label_dim > 0) P.s_lab = A.take<float4>((size_t)ns);
         P.st = A.take<State>(1);
         P.iter_pairs = A.take<long long>((size_t)std::max(I.p.max_iters, 1));
         P.n_blocks = (ns + kPointsPerBlock - 1) / kPointsPerBlock;
@@ -212,7 +229,7 @@ void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &p
         const int knn_cells_t = (int)std::min<long long>(16LL * nt + 64, (1 << 30) - 1);
         const int knn_cells_s = (int)std::min<long long>(16LL * ns + 64, (1 << 30) - 1);
         const int stage_cells = knn_cells_t;
-        if (mode == Mode::Register || mode == Mode::Shapes) {
+        if ((mode == Mode::Register && !iso) || mode == Mode::Shapes) {
             SortJob J = make_job(kJobKnnTarget, nt, P.t_orig, knn_cells_t);
             J.want_shapes = 1;
             J.shape_out = (mode == Mode::Shapes) ? I.shape_out : P.t_shape;
@@ -220,7 +237,7 @@ void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &p
             if (base) pl.jobs[job] = J;
             ++job;
         }
-        if (mode == Mode::Register) {
+        if (mode == Mode::Register && !iso) {
             SortJob J = make_job(kJobKnnSource, ns, P.s_orig, knn_cells_s);
             J.want_shapes = 1;
             J.shape_out = P.s_shape;
@@ -238,6 +255,7 @@ void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &p
             for (int s = 0; s < nst[k]; ++s) {
                 SortJob Js = make_job(kJobStage + s, nt, P.t_rec, stage_cells);
                 P.t_sorted[s] = A.take<float>(kSortedRows * (size_t)nt);
+                if (P.label_dim > 0) P.t_lab[s] = A.take<float4>((size_t)nt);
                 P.t_cells[s] = Js.cell_start;
                 P.t_grid[s] = Js.grid;
                 if (base) pl.jobs[job] = Js;
@@ -362,12 +380,14 @@ int run_iterations(Plan &pl, int max_iters, int precision, int solver, hipStream
     if (launch_count_active(pl.d_pairs, np, pl.d_active, s) != hipSuccess) rc = GCVO_ERR_HIP;
     auto enqueue = [&](int c) -> hipError_t {
         if (!g_prof.on)
-            return launch_iterations(pl.d_pairs, np, pl.d_tasks, n_tasks, c, precision, solver, pl.d_active, s);
+            return launch_iterations(pl.d_pairs, np, pl.d_tasks, n_tasks, c, precision, solver, pl.labels, pl.iso,
+                                     pl.d_active, s);
         const int per = 2 * passes_per_iteration(solver);
         std::vector<hipEvent_t> ev((size_t)per * c);
         for (size_t i = 0; i < ev.size(); ++i)
             if (!(ev[i] = prof_event((size_t)per * launched + i))) return hipErrorOutOfMemory;
-        return launch_iterations(pl.d_pairs, np, pl.d_tasks, n_tasks, c, precision, solver, pl.d_active, s, ev.data());
+        return launch_iterations(pl.d_pairs, np, pl.d_tasks, n_tasks, c, precision, solver, pl.labels, pl.iso,
+                                 pl.d_active, s, ev.data());
     };
     while (rc == GCVO_OK && launched < max_iters) {
         const int c = std::min(kChunk, max_iters - launched);
@@ -464,7 +484,7 @@ void gcvo_default_params(gcvo_params *p) {
     p->min_step = 1e-10;
 }
 
-int gcvo_abi_version(void) { return 101; }
+int gcvo_abi_version(void) { return 102; }
 
 void gcvo_profile_enable(int on) { g_prof.on = on != 0; }
 
@@ -529,9 +549,14 @@ int gcvo_register(const float *tgt_xyz, long long n_tgt, const float *src_xyz, l
     return GCVO_OK;
 }
 
-size_t gcvo_batch_workspace_size(int n_pairs, const long long *tgt_off, const long long *src_off,
-                                 const gcvo_params *p, int shared_params) {
+}  // extern "C"
+
+namespace {
+
+size_t batch_workspace(int n_pairs, const long long *tgt_off, const long long *src_off, const gcvo_params *p,
+                       int shared_params, int label_dim) {
     if (n_pairs < 1 || !tgt_off || !src_off || !p) return 0;
+    if (label_dim < 0 || label_dim > GCVO_MAX_LABEL_DIM) return 0;
     std::vector<PairInput> in;
     for (int k = 0; k < n_pairs; ++k) {
         const gcvo_params &pk = shared_params ? p[0] : p[k];
@@ -539,6 +564,7 @@ size_t gcvo_batch_workspace_size(int n_pairs, const long long *tgt_off, const lo
         if (!params_ok(&pk) || nt < 0 || ns < 0 || nt > GCVO_MAX_POINTS || ns > GCVO_MAX_POINTS) return 0;
         if (nt < pk.knn || ns < pk.knn) continue;   // such pairs are reported, not run
         in.push_back(PairInput{nullptr, nullptr, nt, ns, pk, {}});
+        in.back().label_dim = label_dim;
     }
     if (in.empty()) return 256;
     Plan pl;
@@ -546,10 +572,13 @@ size_t gcvo_batch_workspace_size(int n_pairs, const long long *tgt_off, const lo
     return pl.bytes;
 }
 
-int gcvo_register_batch(int n_pairs, const float *tgt_xyz, const long long *tgt_off, const float *src_xyz,
-                        const long long *src_off, const double *T_init, const gcvo_params *p, int shared_params,
-                        double *T_out, gcvo_info *info, void *workspace, size_t workspace_bytes, void *stream) {
+int register_batch(int n_pairs, const float *tgt_xyz, const float *tgt_label, const long long *tgt_off,
+                   const float *src_xyz, const float *src_label, const long long *src_off, int label_dim,
+                   const double *T_init, const gcvo_params *p, int shared_params, double *T_out, gcvo_info *info,
+                   void *workspace, size_t workspace_bytes, void *stream) {
     if (n_pairs < 1 || !tgt_xyz || !tgt_off || !src_xyz || !src_off || !p || !T_out) return GCVO_ERR_INVALID;
+    if (label_dim < 0 || label_dim > GCVO_MAX_LABEL_DIM || (label_dim > 0 && (!tgt_label || !src_label)))
+        return GCVO_ERR_INVALID;
     std::vector<PairInput> in(n_pairs);
     int knn = p[0].knn, prec = p[0].precision, solver = p[0].solver, max_it = 0;
     for (int k = 0; k < n_pairs; ++k) {
@@ -562,6 +591,11 @@ int gcvo_register_batch(int n_pairs, const float *tgt_xyz, const long long *tgt_
         if (!pose_ok(T0)) return GCVO_ERR_INVALID;
         in[k] = PairInput{tgt_xyz + 3 * tgt_off[k], src_xyz + 3 * src_off[k], nt, ns, pk, {}};
         std::memcpy(in[k].T0, T0, sizeof in[k].T0);
+        if (label_dim > 0) {
+            in[k].tgt_label = tgt_label + (size_t)label_dim * tgt_off[k];
+            in[k].src_label = src_label + (size_t)label_dim * src_off[k];
+            in[k].label_dim = label_dim;
+        }
         max_it = std::max(max_it, pk.max_iters);
     }
     // Pairs too small to register fail individually; the rest run.
@@ -594,24 +628,28 @@ int gcvo_register_batch(int n_pairs, const float *tgt_xyz, const long long *tgt_
     return GCVO_OK;
 }
 
-size_t gcvo_eval_workspace_size(long long n_tgt, long long n_src) {
+size_t eval_workspace(long long n_tgt, long long n_src, int label_dim) {
     if (n_tgt < 0 || n_src < 0 || n_tgt > GCVO_MAX_POINTS || n_src > GCVO_MAX_POINTS) return 0;
+    if (label_dim < 0 || label_dim > GCVO_MAX_LABEL_DIM) return 0;
     std::vector<PairInput> in(1);
     gcvo_params p;
     gcvo_default_params(&p);
     in[0] = PairInput{nullptr, nullptr, n_tgt, n_src, p, {}};
     in[0].eval_ell = 1.0;
     in[0].eval_cutoff = 3.0;
+    in[0].label_dim = label_dim;
     Plan pl;
     build_plan(nullptr, Mode::Eval, in, pl);
     return pl.bytes;
 }
 
-int gcvo_eval_fgh(const float *tgt_xyz, const float *tgt_shape6, long long n_tgt, const float *src_xyz,
-                  const float *src_shape6, long long n_src, const double *T, double length_scale, double cutoff,
-                  double sigma2, int precision, double *f, double *g, double *H, long long *n_pairs,
-                  void *workspace, size_t workspace_bytes, void *stream) {
+int eval_fgh(const float *tgt_xyz, const float *tgt_shape6, const float *tgt_label, long long n_tgt,
+             const float *src_xyz, const float *src_shape6, const float *src_label, long long n_src, int label_dim,
+             const double *T, double length_scale, double cutoff, double sigma2, int precision, double *f, double *g,
+             double *H, long long *n_pairs, void *workspace, size_t workspace_bytes, void *stream) {
     if (!T || !f || !g || !H || n_tgt < 0 || n_src < 0) return GCVO_ERR_INVALID;
+    if (label_dim < 0 || label_dim > GCVO_MAX_LABEL_DIM) return GCVO_ERR_INVALID;
+    if (label_dim > 0 && ((n_tgt > 0 && !tgt_label) || (n_src > 0 && !src_label))) return GCVO_ERR_INVALID;
     if ((n_tgt > 0 && (!tgt_xyz || !tgt_shape6)) || (n_src > 0 && (!src_xyz || !src_shape6))) return GCVO_ERR_INVALID;
     if (!pose_ok(T) || !(std::isfinite(length_scale) && length_scale > 0.0) || !(cutoff > 0.0) ||
         !(std::isfinite(sigma2) && sigma2 > 0.0))
@@ -636,6 +674,9 @@ int gcvo_eval_fgh(const float *tgt_xyz, const float *tgt_shape6, long long n_tgt
     in[0].src_shape = src_shape6;
     in[0].eval_ell = length_scale;
     in[0].eval_cutoff = cutoff;
+    in[0].tgt_label = tgt_label;
+    in[0].src_label = src_label;
+    in[0].label_dim = label_dim;
     hipStream_t s = (hipStream_t)stream;
     Plan sizing;
     build_plan(nullptr, Mode::Eval, in, sizing);
@@ -646,7 +687,7 @@ int gcvo_eval_fgh(const float *tgt_xyz, const float *tgt_shape6, long long n_tgt
     if (rc) return rc;
     HIP_OK(launch_count_active(pl.d_pairs, 1, pl.d_active, s));
     HIP_OK(launch_iterations(pl.d_pairs, 1, pl.d_tasks, (int)pl.tasks.size(), 1, precision, GCVO_SOLVER_GN,
-                             pl.d_active, s));
+                             pl.labels, false, pl.d_active, s));
     State st;
     HIP_OK(hipMemcpyAsync(&st, pl.pairs[0].st, sizeof st, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
@@ -656,6 +697,63 @@ int gcvo_eval_fgh(const float *tgt_xyz, const float *tgt_shape6, long long n_tgt
     std::memcpy(H, st.H, 36 * sizeof(double));
     if (n_pairs) *n_pairs = st.pairs_last;
     return GCVO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t gcvo_batch_workspace_size(int n_pairs, const long long *tgt_off, const long long *src_off,
+                                 const gcvo_params *p, int shared_params) {
+    return batch_workspace(n_pairs, tgt_off, src_off, p, shared_params, 0);
+}
+
+int gcvo_register_batch(int n_pairs, const float *tgt_xyz, const long long *tgt_off, const float *src_xyz,
+                        const long long *src_off, const double *T_init, const gcvo_params *p, int shared_params,
+                        double *T_out, gcvo_info *info, void *workspace, size_t workspace_bytes, void *stream) {
+    return register_batch(n_pairs, tgt_xyz, nullptr, tgt_off, src_xyz, nullptr, src_off, 0, T_init, p,
+                          shared_params, T_out, info, workspace, workspace_bytes, stream);
+}
+
+size_t gcvo_batch_workspace_size_labeled(int n_pairs, const long long *tgt_off, const long long *src_off,
+                                         const gcvo_params *p, int shared_params, int label_dim) {
+    if (label_dim < 1) return 0;
+    return batch_workspace(n_pairs, tgt_off, src_off, p, shared_params, label_dim);
+}
+
+int gcvo_register_batch_labeled(int n_pairs, const float *tgt_xyz, const float *tgt_label,
+                                const long long *tgt_off, const float *src_xyz, const float *src_label,
+                                const long long *src_off, int label_dim, const double *T_init,
+                                const gcvo_params *p, int shared_params, double *T_out, gcvo_info *info,
+                                void *workspace, size_t workspace_bytes, void *stream) {
+    if (label_dim < 1) return GCVO_ERR_INVALID;
+    return register_batch(n_pairs, tgt_xyz, tgt_label, tgt_off, src_xyz, src_label, src_off, label_dim, T_init, p,
+                          shared_params, T_out, info, workspace, workspace_bytes, stream);
+}
+
+size_t gcvo_eval_workspace_size(long long n_tgt, long long n_src) { return eval_workspace(n_tgt, n_src, 0); }
+
+int gcvo_eval_fgh(const float *tgt_xyz, const float *tgt_shape6, long long n_tgt, const float *src_xyz,
+                  const float *src_shape6, long long n_src, const double *T, double length_scale, double cutoff,
+                  double sigma2, int precision, double *f, double *g, double *H, long long *n_pairs,
+                  void *workspace, size_t workspace_bytes, void *stream) {
+    return eval_fgh(tgt_xyz, tgt_shape6, nullptr, n_tgt, src_xyz, src_shape6, nullptr, n_src, 0, T, length_scale,
+                    cutoff, sigma2, precision, f, g, H, n_pairs, workspace, workspace_bytes, stream);
+}
+
+size_t gcvo_eval_workspace_size_labeled(long long n_tgt, long long n_src, int label_dim) {
+    if (label_dim < 1) return 0;
+    return eval_workspace(n_tgt, n_src, label_dim);
+}
+
+int gcvo_eval_fgh_labeled(const float *tgt_xyz, const float *tgt_shape6, const float *tgt_label, long long n_tgt,
+                          const float *src_xyz, const float *src_shape6, const float *src_label, long long n_src,
+                          int label_dim, const double *T, double length_scale, double cutoff, double sigma2,
+                          int precision, double *f, double *g, double *H, long long *n_pairs, void *workspace,
+                          size_t workspace_bytes, void *stream) {
+    if (label_dim < 1) return GCVO_ERR_INVALID;
+    return eval_fgh(tgt_xyz, tgt_shape6, tgt_label, n_tgt, src_xyz, src_shape6, src_label, n_src, label_dim, T,
+                    length_scale, cutoff, sigma2, precision, f, g, H, n_pairs, workspace, workspace_bytes, stream);
 }
 
 size_t gcvo_shapes_workspace_size(long long n) {

@@ -92,7 +92,10 @@ struct State {
 struct PairDev {
     // caller inputs
     const float *tgt_xyz, *src_xyz;   // AoS [n][3]
+    const float *tgt_label, *src_label;   // AoS [n][label_dim] label vectors, or null
     int n_t, n_s;
+    int label_dim;                    // 0: no labels (c_ij = 1)
+    int iso;                          // 1: every shape is the identity (eig_ratio_min >= 1; no kNN)
     // solver parameters
     double ell[kMaxStages];
     int n_stages;
@@ -118,6 +121,8 @@ struct PairDev {
     // {x, y, z, s00 | s01, s02, s11, s12 | s22, x0, y0, z0} (three float4).
     float *s_sorted;                  // source, in Morton order
     float *t_sorted[kMaxStages];      // target, in each stage grid's order
+    float4 *s_lab;                    // source labels padded to 4 with zeros, Morton order (labels only)
+    float4 *t_lab[kMaxStages];        // target labels in each stage grid's order (labels only)
     int *t_cells[kMaxStages];         // cell_start of each stage grid
     Grid *t_grid[kMaxStages];
     SortJob *job_knn_t, *job_knn_s, *job_order_s, *job_stage0;   // job_stage0[s] for s < n_stages
@@ -171,8 +176,12 @@ hipError_t launch_prepare(PairDev *pairs_dev, int n_pairs, int max_n, SortJob *j
 // decrement it.
 // With `events` non-null, every pair-kernel launch is bracketed by two of them
 // (2 * passes_per_iteration(solver) * n_iters events, recorded in order).
+// labels: the pairs carry label vectors (all pairs of a batch or none);
+// iso: every pair's shapes are the identity (the isotropic pair kernel is used
+// for Gauss-Newton).
 hipError_t launch_iterations(PairDev *pairs_dev, int n_pairs, BlockTask *tasks_dev, int n_tasks, int n_iters,
-                             int precision, int solver, int *active, hipStream_t s, hipEvent_t *events = nullptr);
+                             int precision, int solver, bool labels, bool iso, int *active, hipStream_t s,
+                             hipEvent_t *events = nullptr);
 // Pair-kernel passes per solver iteration (2 for the first-order solver).
 int passes_per_iteration(int solver);
 // Count pairs not yet done into *active (device int).

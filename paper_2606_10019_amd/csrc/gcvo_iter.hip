@@ -196,11 +196,13 @@ __device__ __forceinline__ void twist_exp(const double xi[6], double E[4][4]) {
 
 // ------------------------------------------------------------------ pair kernel
 
-constexpr int kModeGN = 0, kModeExact = 1, kModeLine = 2;
+constexpr int kModeGN = 0, kModeExact = 1, kModeLine = 2, kModeIso = 3;
 
 template <int Mode>
 struct ModeInfo {
-    static constexpr int sums = Mode == kModeGN ? kNumSums : Mode == kModeExact ? kSumsExact : kSumsLine;
+    static constexpr int sums = (Mode == kModeGN || Mode == kModeIso) ? kNumSums
+                                : Mode == kModeExact                  ? kSumsExact
+                                                                      : kSumsLine;
 };
 
 typedef float __attribute__((ext_vector_type(4))) vf4;
@@ -219,12 +221,23 @@ struct LineDir {
     Real e[4][3];
 };
 
+// One pair already known to lie within the cutoff; cw is its label weight c_ij
+// (1 without labels).  Isotropic pairs (all shapes the identity, Remark 3):
+// S_ij = 2I, adj = 4I, det = 8, so (f/det) C r = f r / 2 and (f/det) C = f/2 I
+// with f = exp(-|r|^2 / (2 ell^2)): the same sums from a handful of operations.
 template <typename Real, int Mode>
-__device__ __forceinline__ void pair_term(PairSums<Real> &s, unsigned &cnt, Real rx, Real ry, Real rz,
-                                          Real s00, Real s01, Real s02, Real s11, Real s12, Real s22,
-                                          Real rc2, Real kexp, Real k2, const LineDir<Real> &ld) {
-    const Real d2 = rx * rx + ry * ry + rz * rz;
-    if (d2 <= rc2) {
+__device__ __forceinline__ void pair_heavy(PairSums<Real> &s, Real rx, Real ry, Real rz, Real s00, Real s01,
+                                           Real s02, Real s11, Real s12, Real s22, Real kexp, Real k2,
+                                           const LineDir<Real> &ld, Real cw) {
+    if constexpr (Mode == kModeIso) {
+        const Real f = cw * Fast<Real>::exp2((rx * rx + ry * ry + rz * rz) * (kexp * (Real)0.5));
+        const Real hf = (Real)0.5 * f;
+        s.F += f;
+        s.A0 += hf * rx; s.A1 += hf * ry; s.A2 += hf * rz;
+        s.B00 += hf;
+        return;
+    }
+    {
         const Real c00 = s11 * s22 - s12 * s12;
         const Real c01 = s02 * s12 - s01 * s22;
         const Real c02 = s01 * s12 - s02 * s11;
@@ -237,7 +250,7 @@ __device__ __forceinline__ void pair_term(PairSums<Real> &s, unsigned &cnt, Real
         const Real uy = c01 * rx + c11 * ry + c12 * rz;
         const Real uz = c02 * rx + c12 * ry + c22 * rz;
         const Real q = rx * ux + ry * uy + rz * uz;
-        const Real f = Fast<Real>::exp2(q * (inv * kexp));
+        const Real f = cw * Fast<Real>::exp2(q * (inv * kexp));
         s.F += f;
         if constexpr (Mode == kModeLine) {
             // P = Sigma^{-1} = sc * C
@@ -279,7 +292,6 @@ __device__ __forceinline__ void pair_term(PairSums<Real> &s, unsigned &cnt, Real
                 s.Q11 += qy * uy; s.Q12 += qy * uz; s.Q22 += qz * uz;
             }
         }
-        ++cnt;
     }
 }
 
@@ -650,7 +662,7 @@ __device__ __forceinline__ void group_sum(Real &v) {
     for (int off = kGroupLanes / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
 }
 
-template <typename Real, int Mode>
+template <typename Real, int Mode, bool kLab>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_iterate(PairDev *pairs,
                                                                                           const BlockTask *tasks) {
     constexpr int NS = ModeInfo<Mode>::sums;
@@ -712,6 +724,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         p11 = (Real)Sp[1][1]; p12 = (Real)Sp[1][2]; p22 = (Real)Sp[2][2];
     }
     const Real yx = (Real)y0, yy = (Real)y1, yz = (Real)y2;
+    // label vector of the source point (zero-padded to 4)
+    vf4 lz = {0.0f, 0.0f, 0.0f, 0.0f};
+    if constexpr (kLab) {
+        if (valid) {
+            const float4 l = P.s_lab[j];
+            lz = vf4{l.x, l.y, l.z, l.w};
+        }
+    }
+    typedef const vf4 __attribute__((address_space(1))) *GLab;
+    const GLab tlab = kLab ? (GLab)(P.t_lab[stage]) : (GLab)nullptr;
     const double rc = P.cutoff_scale * ell;
     const Real rc2 = (Real)(rc * rc);
     const Real kexp = (Real)(-1.4426950408889634 / (ell * ell));   // f = exp2(q * inv_det * kexp)
@@ -779,13 +801,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             // The whole 48-byte record of the next candidate is requested
             // before the current one is evaluated (one memory round trip per
             // candidate, overlapped with the pair arithmetic).
-            vf4 na = {}, nb4 = {}, nc = {};
+            // Isotropic FP32 passes need only the recentred coordinates (first 16 bytes).
+            constexpr bool kXyzOnly = (Mode == kModeIso) && !kExact;
+            vf4 na = {}, nb4 = {}, nc = {}, nl = {};
             if (r < nb) {
                 const GRec4 rec = trec + 3 * (size_t)(rs + o);
-                na = rec[0]; nb4 = rec[1]; nc = rec[2];
+                na = rec[0];
+                if constexpr (!kXyzOnly) { nb4 = rec[1]; nc = rec[2]; }
+                if constexpr (kLab) nl = tlab[rs + o];
             }
             while (r < nb) {
-                const vf4 ra = na, rb = nb4, rcc = nc;
+                const vf4 ra = na, rb = nb4, rcc = nc, lx = nl;
                 o += kGroupLanes;
                 while (r < nb && o >= rl) {
                     o -= rl;
@@ -793,14 +819,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 }
                 if (r < nb) {
                     const GRec4 rec = trec + 3 * (size_t)(rs + o);
-                    na = rec[0]; nb4 = rec[1]; nc = rec[2];
+                    na = rec[0];
+                    if constexpr (!kXyzOnly) { nb4 = rec[1]; nc = rec[2]; }
+                    if constexpr (kLab) nl = tlab[rs + o];
                 }
                 const Real xx = kExact ? (Real)((double)rcc.y - c0) : (Real)ra.x;
                 const Real xy = kExact ? (Real)((double)rcc.z - c1) : (Real)ra.y;
                 const Real xz = kExact ? (Real)((double)rcc.w - c2) : (Real)ra.z;
-                pair_term<Real, Mode>(s, cnt, xx - yx, xy - yy, xz - yz, (Real)ra.w + p00, (Real)rb.x + p01,
-                                      (Real)rb.y + p02, (Real)rb.z + p11, (Real)rb.w + p12, (Real)rcc.x + p22, rc2,
-                                      kexp, k2, ld);
+                const Real rx = xx - yx, ry = xy - yy, rz = xz - yz;
+                if (rx * rx + ry * ry + rz * rz <= rc2) {
+                    Real cw = (Real)1;
+                    if constexpr (kLab)
+                        cw = (Real)lx.x * (Real)lz.x + (Real)lx.y * (Real)lz.y + (Real)lx.z * (Real)lz.z +
+                             (Real)lx.w * (Real)lz.w;
+                    pair_heavy<Real, Mode>(s, rx, ry, rz, (Real)ra.w + p00, (Real)rb.x + p01, (Real)rb.y + p02,
+                                           (Real)rb.z + p11, (Real)rb.w + p12, (Real)rcc.x + p22, kexp, k2, ld, cw);
+                    ++cnt;
+                }
             }
             __builtin_amdgcn_wave_barrier();
         }
@@ -810,6 +845,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     group_sum(s.F);
     if constexpr (Mode == kModeLine) {
         group_sum(s.L1); group_sum(s.L2); group_sum(s.L3); group_sum(s.L4);
+    } else if constexpr (Mode == kModeIso) {
+        group_sum(s.A0); group_sum(s.A1); group_sum(s.A2);
+        group_sum(s.B00);
     } else {
         group_sum(s.A0); group_sum(s.A1); group_sum(s.A2);
         group_sum(s.B00); group_sum(s.B01); group_sum(s.B02);
@@ -834,8 +872,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         } else {
             const Real kk = valid ? k2 : (Real)0;
             const Real a0 = kk * s.A0, a1 = kk * s.A1, a2 = kk * s.A2;
-            const Real b00 = kk * s.B00, b01 = kk * s.B01, b02 = kk * s.B02;
-            const Real b11 = kk * s.B11, b12 = kk * s.B12, b22 = kk * s.B22;
+            const Real b00 = kk * s.B00;
+            const Real b01 = (Mode == kModeIso) ? (Real)0 : kk * s.B01, b02 = (Mode == kModeIso) ? (Real)0 : kk * s.B02;
+            const Real b11 = (Mode == kModeIso) ? b00 : kk * s.B11, b12 = (Mode == kModeIso) ? (Real)0 : kk * s.B12;
+            const Real b22 = (Mode == kModeIso) ? b00 : kk * s.B22;
             v[0] = valid ? s.F : (Real)0;
             // g_w = -y x a, g_v = -a
             v[1] = -(yy * a2 - yz * a1);
@@ -984,45 +1024,51 @@ __global__ void k_count_active(const PairDev *pairs, int n_pairs, int *active) {
     if (threadIdx.x == 0) *active = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
-template <typename Real, int Mode, int Kind>
+template <typename Real, int Mode, int Kind, bool kLab>
 static void launch_pass(PairDev *pairs, int n_pairs, BlockTask *tasks, int n_tasks, int *active, hipStream_t s,
                         hipEvent_t *&ev) {
     if (ev) {
         // events attached to the dispatch itself: they time the kernel, not the queue
-        hipExtLaunchKernelGGL((k_iterate<Real, Mode>), dim3(n_tasks), dim3(kBlock), 0, s, ev[0], ev[1], 0u, pairs,
-                              tasks);
+        hipExtLaunchKernelGGL((k_iterate<Real, Mode, kLab>), dim3(n_tasks), dim3(kBlock), 0, s, ev[0], ev[1], 0u,
+                              pairs, tasks);
         ev += 2;
     } else {
-        hipLaunchKernelGGL((k_iterate<Real, Mode>), dim3(n_tasks), dim3(kBlock), 0, s, pairs, tasks);
+        hipLaunchKernelGGL((k_iterate<Real, Mode, kLab>), dim3(n_tasks), dim3(kBlock), 0, s, pairs, tasks);
     }
     hipLaunchKernelGGL((k_reduce<Real, Mode>), dim3(kReduceSplit, n_pairs), dim3(kReduceThreads), 0, s, pairs);
     hipLaunchKernelGGL((k_step<Kind>), dim3(n_pairs), dim3(64), 0, s, pairs, active);
 }
 
-template <typename Real>
-static void launch_iteration(PairDev *pairs, int n_pairs, BlockTask *tasks, int n_tasks, int solver, int *active,
-                             hipStream_t s, hipEvent_t *&ev) {
+template <typename Real, bool kLab>
+static void launch_iteration(PairDev *pairs, int n_pairs, BlockTask *tasks, int n_tasks, int solver, bool iso,
+                             int *active, hipStream_t s, hipEvent_t *&ev) {
     if (solver == GCVO_SOLVER_NEWTON) {
-        launch_pass<Real, kModeExact, 1>(pairs, n_pairs, tasks, n_tasks, active, s, ev);
+        launch_pass<Real, kModeExact, 1, kLab>(pairs, n_pairs, tasks, n_tasks, active, s, ev);
     } else if (solver == GCVO_SOLVER_FIRST_ORDER) {
-        launch_pass<Real, kModeGN, 2>(pairs, n_pairs, tasks, n_tasks, active, s, ev);
-        launch_pass<Real, kModeLine, 3>(pairs, n_pairs, tasks, n_tasks, active, s, ev);
+        launch_pass<Real, kModeGN, 2, kLab>(pairs, n_pairs, tasks, n_tasks, active, s, ev);
+        launch_pass<Real, kModeLine, 3, kLab>(pairs, n_pairs, tasks, n_tasks, active, s, ev);
+    } else if (iso) {
+        launch_pass<Real, kModeIso, 0, kLab>(pairs, n_pairs, tasks, n_tasks, active, s, ev);
     } else {
-        launch_pass<Real, kModeGN, 0>(pairs, n_pairs, tasks, n_tasks, active, s, ev);
+        launch_pass<Real, kModeGN, 0, kLab>(pairs, n_pairs, tasks, n_tasks, active, s, ev);
     }
 }
 
 int passes_per_iteration(int solver) { return solver == GCVO_SOLVER_FIRST_ORDER ? 2 : 1; }
 
 hipError_t launch_iterations(PairDev *pairs, int n_pairs, BlockTask *tasks, int n_tasks, int n_iters,
-                             int precision, int solver, int *active, hipStream_t s, hipEvent_t *events) {
+                             int precision, int solver, bool labels, bool iso, int *active, hipStream_t s,
+                             hipEvent_t *events) {
     if (n_tasks <= 0) return hipSuccess;
     hipEvent_t *ev = events;
     for (int it = 0; it < n_iters; ++it) {
-        if (precision == GCVO_PRECISION_FP64)
-            launch_iteration<double>(pairs, n_pairs, tasks, n_tasks, solver, active, s, ev);
-        else
-            launch_iteration<float>(pairs, n_pairs, tasks, n_tasks, solver, active, s, ev);
+        if (precision == GCVO_PRECISION_FP64) {
+            if (labels) launch_iteration<double, true>(pairs, n_pairs, tasks, n_tasks, solver, iso, active, s, ev);
+            else launch_iteration<double, false>(pairs, n_pairs, tasks, n_tasks, solver, iso, active, s, ev);
+        } else {
+            if (labels) launch_iteration<float, true>(pairs, n_pairs, tasks, n_tasks, solver, iso, active, s, ev);
+            else launch_iteration<float, false>(pairs, n_pairs, tasks, n_tasks, solver, iso, active, s, ev);
+        }
     }
     return hipGetLastError();
 }

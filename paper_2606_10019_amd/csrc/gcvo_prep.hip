@@ -607,20 +607,35 @@ __global__ __launch_bounds__(kBlock) void k_gather(SortJob *jobs, const PairDev 
     const float *rec = src ? P.s_rec : P.t_rec;
     const float *org = src ? P.s_orig : P.t_orig;
     const float *shp = src ? P.s_shape : P.t_shape;
+    // shape of point p (the identity for isotropic pairs, whose shapes are not computed)
+    float sh[6];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) sh[e] = P.iso ? ((e == 0 || e == 3 || e == 5) ? 1.0f : 0.0f) : shp[(size_t)e * n + p];
+    // label vector of point p, zero-padded to 4
+    float4 lab = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (P.label_dim > 0) {
+        const float *l = (src ? P.src_label : P.tgt_label) + (size_t)P.label_dim * p;
+        lab.x = l[0];
+        if (P.label_dim > 1) lab.y = l[1];
+        if (P.label_dim > 2) lab.z = l[2];
+        if (P.label_dim > 3) lab.w = l[3];
+    }
     if (src) {   // source: structure of arrays, read once per point and iteration
         float *out = P.s_sorted;
 #pragma unroll
         for (int d = 0; d < 3; ++d) out[(size_t)d * n + pos] = rec[(size_t)d * n + p];
 #pragma unroll
-        for (int e = 0; e < 6; ++e) out[(size_t)(3 + e) * n + pos] = shp[(size_t)e * n + p];
+        for (int e = 0; e < 6; ++e) out[(size_t)(3 + e) * n + pos] = sh[e];
 #pragma unroll
         for (int d = 0; d < 3; ++d) out[(size_t)(9 + d) * n + pos] = org[(size_t)d * n + p];
+        if (P.label_dim > 0) P.s_lab[pos] = lab;
     } else {     // target: 48-byte records, three float4 loads per candidate
-        float4 *out = reinterpret_cast<float4 *>(P.t_sorted[J.kind - kJobStage]) + 3 * (size_t)pos;
-        out[0] = make_float4(rec[p], rec[(size_t)n + p], rec[2 * (size_t)n + p], shp[p]);
-        out[1] = make_float4(shp[(size_t)n + p], shp[2 * (size_t)n + p], shp[3 * (size_t)n + p],
-                             shp[4 * (size_t)n + p]);
-        out[2] = make_float4(shp[5 * (size_t)n + p], org[p], org[(size_t)n + p], org[2 * (size_t)n + p]);
+        const int stage = J.kind - kJobStage;
+        float4 *out = reinterpret_cast<float4 *>(P.t_sorted[stage]) + 3 * (size_t)pos;
+        out[0] = make_float4(rec[p], rec[(size_t)n + p], rec[2 * (size_t)n + p], sh[0]);
+        out[1] = make_float4(sh[1], sh[2], sh[3], sh[4]);
+        out[2] = make_float4(sh[5], org[p], org[(size_t)n + p], org[2 * (size_t)n + p]);
+        if (P.label_dim > 0) P.t_lab[stage][pos] = lab;
     }
 }
 

@@ -34,13 +34,15 @@ GCVO_SOLVER_GN = 0
 GCVO_SOLVER_NEWTON = 1
 GCVO_SOLVER_FIRST_ORDER = 2
 GCVO_MAX_STAGES = 16
+GCVO_MAX_LABEL_DIM = 4
 
 EXPORTED = ["gcvo_default_params", "gcvo_workspace_size", "gcvo_register", "gcvo_batch_workspace_size",
             "gcvo_register_batch", "gcvo_eval_workspace_size", "gcvo_eval_fgh", "gcvo_shapes_workspace_size",
             "gcvo_point_shapes", "gcvo_strerror", "gcvo_abi_version", "gcvo_profile_enable",
             "gcvo_profile_reset", "gcvo_profile_read",
             "gcvo_mlp_param_count", "gcvo_mlp_workspace_size", "gcvo_mlp_forward", "gcvo_mlp_loss_grad",
-            "gcvo_mlp_adam"]
+            "gcvo_mlp_adam", "gcvo_batch_workspace_size_labeled", "gcvo_register_batch_labeled",
+            "gcvo_eval_workspace_size_labeled", "gcvo_eval_fgh_labeled"]
 
 GCVO_MLP_N_PARAMS = 42246
 GCVO_MLP_ROT_SCALE = 0.3
@@ -113,6 +115,15 @@ def load_library() -> ctypes.CDLL:
     L.gcvo_eval_fgh.argtypes = [_P, _P, ctypes.c_longlong, _P, _P, ctypes.c_longlong, _P, ctypes.c_double,
                                 ctypes.c_double, ctypes.c_double, ctypes.c_int, _P, _P, _P, _P, _P,
                                 ctypes.c_size_t, _P]
+    L.gcvo_batch_workspace_size_labeled.argtypes = [ctypes.c_int, _P, _P, pp, ctypes.c_int, ctypes.c_int]
+    L.gcvo_batch_workspace_size_labeled.restype = ctypes.c_size_t
+    L.gcvo_register_batch_labeled.argtypes = [ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.c_int, _P, pp,
+                                              ctypes.c_int, _P, ctypes.POINTER(gcvo_info), _P, ctypes.c_size_t, _P]
+    L.gcvo_eval_workspace_size_labeled.argtypes = [ctypes.c_longlong, ctypes.c_longlong, ctypes.c_int]
+    L.gcvo_eval_workspace_size_labeled.restype = ctypes.c_size_t
+    L.gcvo_eval_fgh_labeled.argtypes = [_P, _P, _P, ctypes.c_longlong, _P, _P, _P, ctypes.c_longlong, ctypes.c_int,
+                                        _P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int, _P, _P,
+                                        _P, _P, _P, ctypes.c_size_t, _P]
     L.gcvo_shapes_workspace_size.argtypes = [ctypes.c_longlong]
     L.gcvo_shapes_workspace_size.restype = ctypes.c_size_t
     L.gcvo_point_shapes.argtypes = [_P, ctypes.c_longlong, ctypes.c_int, ctypes.c_double, _P, _P,
@@ -193,6 +204,15 @@ def _shape6(t, n: int, name: str):
     return t.contiguous()
 
 
+def _labels(t, n: int, name: str):
+    """Label rows: float32 CUDA [n, d], 1 <= d <= GCVO_MAX_LABEL_DIM."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or t.dim() != 2 \
+            or t.shape[0] != n or not 1 <= t.shape[1] <= GCVO_MAX_LABEL_DIM:
+        raise TypeError(f"{name} must be a float32 CUDA tensor [{n}, d], 1 <= d <= {GCVO_MAX_LABEL_DIM}")
+    return t.contiguous()
+
+
 def workspace(nbytes: int, device=None):
     """A device byte buffer from torch's allocator (256-byte aligned)."""
     torch = _torch()
@@ -251,12 +271,7 @@ def _param_array(params, n_pairs):
     return 0, ctypes.cast(arr, ctypes.POINTER(gcvo_params))
 
 
-def gcvo_register_batch(targets, tgt_off, sources, src_off, T_init=None, params=None, ws=None, stream=None):
-    """Register len(tgt_off) - 1 pairs held in two concatenated clouds.
-
-    targets / sources: float32 CUDA [sum, 3]; tgt_off / src_off: int64 host
-    offsets.  Returns (T [n_pairs, 4, 4], list of info dicts).
-    """
+def _register_batch(targets, tgt_labels, tgt_off, sources, src_labels, src_off, T_init, params, ws, stream):
     L = load_library()
     targets = _cloud(targets, "targets")
     sources = _cloud(sources, "sources")
@@ -266,20 +281,63 @@ def gcvo_register_batch(targets, tgt_off, sources, src_off, T_init=None, params=
     p = params if params is not None else default_params()
     shared, parr = _param_array(p, n_pairs)
     T0 = None if T_init is None else np.ascontiguousarray(np.asarray(T_init, np.float64).reshape(n_pairs, 16))
-    need = L.gcvo_batch_workspace_size(n_pairs, to.ctypes.data_as(_P), so.ctypes.data_as(_P), parr, shared)
+    T0p = T0.ctypes.data_as(_P) if T0 is not None else None
+    T_out = np.zeros((n_pairs, 4, 4))
+    infos = (gcvo_info * n_pairs)()
+    if tgt_labels is None:
+        name = "gcvo_register_batch"
+        need = L.gcvo_batch_workspace_size(n_pairs, to.ctypes.data_as(_P), so.ctypes.data_as(_P), parr, shared)
+    else:
+        name = "gcvo_register_batch_labeled"
+        tl = _labels(tgt_labels, targets.shape[0], "tgt_labels")
+        sl = _labels(src_labels, sources.shape[0], "src_labels")
+        if tl.shape[1] != sl.shape[1]:
+            raise TypeError("tgt_labels and src_labels must have the same width")
+        dim = int(tl.shape[1])
+        need = L.gcvo_batch_workspace_size_labeled(n_pairs, to.ctypes.data_as(_P), so.ctypes.data_as(_P), parr,
+                                                   shared, dim)
     if ws is None:
         holder, wptr, wbytes = workspace(max(need, 256), targets.device)
     else:
         holder, wptr, wbytes = ws
-    T_out = np.zeros((n_pairs, 4, 4))
-    infos = (gcvo_info * n_pairs)()
-    st = L.gcvo_register_batch(n_pairs, _ptr(targets), to.ctypes.data_as(_P), _ptr(sources), so.ctypes.data_as(_P),
-                               T0.ctypes.data_as(_P) if T0 is not None else None, parr, shared,
-                               T_out.ctypes.data_as(_P), infos, ctypes.c_void_p(wptr), wbytes, _stream_handle(stream))
+    if tgt_labels is None:
+        st = L.gcvo_register_batch(n_pairs, _ptr(targets), to.ctypes.data_as(_P), _ptr(sources),
+                                   so.ctypes.data_as(_P), T0p, parr, shared, T_out.ctypes.data_as(_P), infos,
+                                   ctypes.c_void_p(wptr), wbytes, _stream_handle(stream))
+    else:
+        st = L.gcvo_register_batch_labeled(n_pairs, _ptr(targets), _ptr(tl), to.ctypes.data_as(_P), _ptr(sources),
+                                           _ptr(sl), so.ctypes.data_as(_P), dim, T0p, parr, shared,
+                                           T_out.ctypes.data_as(_P), infos, ctypes.c_void_p(wptr), wbytes,
+                                           _stream_handle(stream))
     del holder
     if st != GCVO_OK:
-        raise GcvoError(st, "gcvo_register_batch")
+        raise GcvoError(st, name)
     return T_out, [i.to_dict() for i in infos]
+
+
+def gcvo_register_batch(targets, tgt_off, sources, src_off, T_init=None, params=None, ws=None, stream=None):
+    """Register len(tgt_off) - 1 pairs held in two concatenated clouds.
+
+    targets / sources: float32 CUDA [sum, 3]; tgt_off / src_off: int64 host
+    offsets.  Returns (T [n_pairs, 4, 4], list of info dicts).
+    """
+    return _register_batch(targets, None, tgt_off, sources, None, src_off, T_init, params, ws, stream)
+
+
+def gcvo_register_batch_labeled(targets, tgt_labels, tgt_off, sources, src_labels, src_off, T_init=None,
+                                params=None, ws=None, stream=None):
+    """gcvo_register_batch with per-point label vectors (float32 CUDA [sum, d],
+    d <= 4) weighting each pair by <l^X_i, l^Z_j>."""
+    return _register_batch(targets, tgt_labels, tgt_off, sources, src_labels, src_off, T_init, params, ws, stream)
+
+
+def gcvo_batch_workspace_size_labeled(tgt_off, src_off, params, label_dim: int) -> int:
+    L = load_library()
+    to = np.ascontiguousarray(tgt_off, dtype=np.int64)
+    so = np.ascontiguousarray(src_off, dtype=np.int64)
+    shared, parr = _param_array(params, len(to) - 1)
+    return int(L.gcvo_batch_workspace_size_labeled(len(to) - 1, to.ctypes.data_as(_P), so.ctypes.data_as(_P), parr,
+                                                   shared, int(label_dim)))
 
 
 @dataclass
@@ -290,8 +348,8 @@ class EvalResult:
     npairs: int
 
 
-def gcvo_eval_fgh(target, tgt_shape6, source, src_shape6, T, length_scale: float, cutoff: float,
-                  sigma2: float = 1.0, precision: int = GCVO_PRECISION_FP32, ws=None, stream=None) -> EvalResult:
+def _eval_fgh(target, tgt_shape6, tgt_labels, source, src_shape6, src_labels, T, length_scale, cutoff, sigma2,
+              precision, ws, stream) -> EvalResult:
     L = load_library()
     target = _cloud(target, "target")
     source = _cloud(source, "source")
@@ -299,7 +357,16 @@ def gcvo_eval_fgh(target, tgt_shape6, source, src_shape6, T, length_scale: float
     ts = _shape6(tgt_shape6, nt, "tgt_shape6")
     ss = _shape6(src_shape6, ns, "src_shape6")
     Tm = _pose(T)
-    need = L.gcvo_eval_workspace_size(nt, ns)
+    if tgt_labels is None:
+        dim = 0
+        need = L.gcvo_eval_workspace_size(nt, ns)
+    else:
+        tl = _labels(tgt_labels, nt, "tgt_labels")
+        sl = _labels(src_labels, ns, "src_labels")
+        if tl.shape[1] != sl.shape[1]:
+            raise TypeError("tgt_labels and src_labels must have the same width")
+        dim = int(tl.shape[1])
+        need = L.gcvo_eval_workspace_size_labeled(nt, ns, dim)
     if ws is None:
         holder, wptr, wbytes = workspace(max(need, 256), target.device)
     else:
@@ -308,14 +375,38 @@ def gcvo_eval_fgh(target, tgt_shape6, source, src_shape6, T, length_scale: float
     g = np.zeros(6)
     H = np.zeros((6, 6))
     npairs = ctypes.c_longlong()
-    st = L.gcvo_eval_fgh(_ptr(target), _ptr(ts), nt, _ptr(source), _ptr(ss), ns, Tm.ctypes.data_as(_P),
-                         float(length_scale), float(cutoff), float(sigma2), int(precision), ctypes.byref(f),
-                         g.ctypes.data_as(_P), H.ctypes.data_as(_P), ctypes.byref(npairs), ctypes.c_void_p(wptr),
-                         wbytes, _stream_handle(stream))
+    tail = (Tm.ctypes.data_as(_P), float(length_scale), float(cutoff), float(sigma2), int(precision), ctypes.byref(f),
+            g.ctypes.data_as(_P), H.ctypes.data_as(_P), ctypes.byref(npairs), ctypes.c_void_p(wptr), wbytes,
+            _stream_handle(stream))
+    if dim == 0:
+        name = "gcvo_eval_fgh"
+        st = L.gcvo_eval_fgh(_ptr(target), _ptr(ts), nt, _ptr(source), _ptr(ss), ns, *tail)
+    else:
+        name = "gcvo_eval_fgh_labeled"
+        st = L.gcvo_eval_fgh_labeled(_ptr(target), _ptr(ts), _ptr(tl), nt, _ptr(source), _ptr(ss), _ptr(sl), ns, dim,
+                                     *tail)
     del holder
     if st != GCVO_OK:
-        raise GcvoError(st, "gcvo_eval_fgh")
+        raise GcvoError(st, name)
     return EvalResult(f.value, g, H, npairs.value)
+
+
+def gcvo_eval_fgh(target, tgt_shape6, source, src_shape6, T, length_scale: float, cutoff: float,
+                  sigma2: float = 1.0, precision: int = GCVO_PRECISION_FP32, ws=None, stream=None) -> EvalResult:
+    return _eval_fgh(target, tgt_shape6, None, source, src_shape6, None, T, length_scale, cutoff, sigma2, precision,
+                     ws, stream)
+
+
+def gcvo_eval_fgh_labeled(target, tgt_shape6, tgt_labels, source, src_shape6, src_labels, T, length_scale: float,
+                          cutoff: float, sigma2: float = 1.0, precision: int = GCVO_PRECISION_FP32, ws=None,
+                          stream=None) -> EvalResult:
+    """gcvo_eval_fgh with per-point label vectors weighting each pair."""
+    return _eval_fgh(target, tgt_shape6, tgt_labels, source, src_shape6, src_labels, T, length_scale, cutoff, sigma2,
+                     precision, ws, stream)
+
+
+def gcvo_eval_workspace_size_labeled(n_tgt: int, n_src: int, label_dim: int) -> int:
+    return int(load_library().gcvo_eval_workspace_size_labeled(n_tgt, n_src, label_dim))
 
 
 def gcvo_point_shapes(xyz, knn: int = 10, rho: float = 0.01, ws=None, stream=None):

@@ -592,6 +592,37 @@ def config4_sizes(n_pairs: int = 256, n_lo: int = 1000, n_hi: int = 50000) -> li
     return out
 
 
+# --------------------------------------------------------------------------
+# Per-point labels (intensity / colour channels or semantic classes) for the
+# labelled objective.  A label is a function of the point's position on the
+# underlying surface, so corresponding target and source points carry the same
+# label up to the sampling: source points are surface points, target points are
+# mapped back by T_true first.
+# --------------------------------------------------------------------------
+
+def label_field(P: np.ndarray, dim: int, kind: str, seed: int = 0) -> np.ndarray:
+    """float32 [n, dim] labels at surface points P [n, 3].
+
+    kind "colour": channel c is 0.5 + 0.4 sin(w_c . p + phase_c) with |w_c| = 2 rad/m
+    (smooth, in (0.1, 0.9)); kind "class": one-hot of the channel with the largest
+    such value (a partition into dim regions)."""
+    rng = np.random.default_rng(9_000_001 + seed)
+    W = np.stack([2.0 * random_unit(rng) for _ in range(dim)])
+    phase = rng.uniform(0.0, 2.0 * np.pi, size=dim)
+    L = 0.5 + 0.4 * np.sin(np.asarray(P, np.float64) @ W.T + phase)
+    if kind == "class":
+        L = np.eye(dim)[np.argmax(L, axis=1)]
+    elif kind != "colour":
+        raise ValueError(f"unknown label kind {kind!r}")
+    return np.ascontiguousarray(L, np.float32)
+
+
+def pair_labels(spec: PairSpec, dim: int, kind: str, seed: int = 0):
+    """(target labels, source labels) of a pair, both float32 [n, dim]."""
+    surf_t = transform_points(spec.T_true, spec.target.astype(np.float64))
+    return (label_field(surf_t, dim, kind, seed), label_field(spec.source.astype(np.float64), dim, kind, seed))
+
+
 def make_pair(config: int, instance: int = 0) -> PairSpec:
     return CONFIGS[config](instance)
 

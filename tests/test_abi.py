@@ -31,7 +31,7 @@ def test_struct_layouts_match_header():
     # sizes implied by the header's field order on x86-64
     assert ctypes.sizeof(gcvo.gcvo_params) == 8 * 4 + 8 + 8 * 2 + 8 + 8 * 2 + 8 + 8
     assert ctypes.sizeof(gcvo.gcvo_info) == 4 * 4 + 8 + 8 + 48 + 8 + 4 * 16
-    assert gcvo.load_library().gcvo_abi_version() == 101
+    assert gcvo.load_library().gcvo_abi_version() == 102
 
 
 def test_default_params_and_strerror():
@@ -103,3 +103,38 @@ def test_mlp_sizes():
     assert gcvo.gcvo_mlp_workspace_size(0, 1024) == 0
     assert gcvo.gcvo_mlp_workspace_size(4, 0) == 0
     assert gcvo.gcvo_mlp_workspace_size(4, 1 << 20) == 0
+
+
+def test_labeled_and_isotropic_sizes_and_validation():
+    import numpy as np
+    L = gcvo.load_library()
+    p = gcvo.default_params()
+    off = np.array([0, 2000], dtype=np.int64)
+    plain = gcvo.gcvo_batch_workspace_size(off, off, p)
+    lab = gcvo.gcvo_batch_workspace_size_labeled(off, off, p, 3)
+    assert lab > plain                       # label rows per source point and per stage
+    assert gcvo.gcvo_batch_workspace_size_labeled(off, off, p, 0) == 0
+    assert gcvo.gcvo_batch_workspace_size_labeled(off, off, p, gcvo.GCVO_MAX_LABEL_DIM + 1) == 0
+    # rho = 1: no neighbourhoods, so no kNN grids or shape arrays
+    iso = gcvo.default_params(eig_ratio_min=1.0)
+    assert 0 < gcvo.gcvo_workspace_size(2000, 2000, iso) < gcvo.gcvo_workspace_size(2000, 2000, p)
+    assert L.gcvo_eval_workspace_size_labeled(100, 100, 2) > L.gcvo_eval_workspace_size(100, 100)
+    assert L.gcvo_eval_workspace_size_labeled(100, 100, 5) == 0
+    T = np.zeros((1, 16))
+    info = (gcvo.gcvo_info * 1)()
+    op = off.ctypes.data_as(ctypes.c_void_p)
+    # labelled calls without labels, or with a bad width, fail before any device work
+    for dim, tl in ((2, None), (0, 16), (5, 16)):
+        st = L.gcvo_register_batch_labeled(1, ctypes.c_void_p(16), tl, op, ctypes.c_void_p(16), tl, op, dim, None,
+                                           ctypes.byref(p), 1, T.ctypes.data_as(ctypes.c_void_p), info, None, 0,
+                                           None)
+        assert st == gcvo.GCVO_ERR_INVALID, dim
+    f = ctypes.c_double()
+    g = np.zeros(6)
+    H = np.zeros(36)
+    I = np.eye(4).ravel()
+    st = L.gcvo_eval_fgh_labeled(ctypes.c_void_p(16), ctypes.c_void_p(16), None, 10, ctypes.c_void_p(16),
+                                 ctypes.c_void_p(16), None, 10, 2, I.ctypes.data_as(ctypes.c_void_p), 0.5, 1.5, 1.0,
+                                 0, ctypes.byref(f), g.ctypes.data_as(ctypes.c_void_p),
+                                 H.ctypes.data_as(ctypes.c_void_p), None, None, 0, None)
+    assert st == gcvo.GCVO_ERR_INVALID
