@@ -17,7 +17,8 @@ algorithmic FLOP = 76 per pair within the cutoff + 230 per source point.
 
 Further legs (reported under config): the same pairs registered together by one
 batch call; the RGB-D precision pair with FP32 and FP64 kernels; the
-exact-Hessian solver; the learned warm start on held-out large-motion pairs
+exact-Hessian solver; the LiDAR pairs with an intensity label per point and
+with the isotropic kernel; the learned warm start on held-out large-motion pairs
 against the plain single-pair path; optionally (--objects) the 256 object
 pairs in one batch call.
 
@@ -199,6 +200,52 @@ def solver_leg(gcvo, specs, clouds, params, refs, ws, rot_err_deg, trans_err_m, 
     return out
 
 
+def variants_leg(gcvo, synth, golden, specs, clouds, rot_err_deg, trans_err_m, dev, reps=8):
+    """The LiDAR pairs with a one-channel intensity label per point (pairs
+    weighted by the label product) and with the isotropic kernel (rho = 1, the
+    CVO special case): time, iterations and gate against the oracle's fixed
+    point of the same variant."""
+    import torch
+    out = {}
+    for name in ("labels_intensity", "isotropic"):
+        keys = [f"{s.name}/{name}" for s in specs]
+        if not all(k in golden for k in keys):
+            continue
+        refs = [np.array(golden[k]["T_ref"]).reshape(4, 4) for k in keys]
+        runs = []
+        for k, s in enumerate(specs):
+            g = golden[keys[k]]
+            p = gcvo.params_from_spec(s, **g["overrides"])
+            if g["labels"]:
+                LX, LZ = synth.pair_labels(s, *g["labels"])
+                lab = (torch.from_numpy(LX).to(dev), torch.from_numpy(LZ).to(dev))
+            else:
+                lab = None
+            runs.append((p, lab))
+
+        def one(k):
+            i = k % len(specs)
+            p, lab = runs[i]
+            if lab is None:
+                return gcvo.gcvo_register(clouds[i][0], clouds[i][1], None, p)
+            T, infos = gcvo.gcvo_register_batch_labeled(clouds[i][0], lab[0], [0, len(specs[i].target)],
+                                                        clouds[i][1], lab[1], [0, len(specs[i].source)], None, p)
+            return T[0], infos[0]
+
+        one(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = [one(k) for k in range(reps)]
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        ok = sum(1 for k, (T, i) in enumerate(res) if i["converged"] and rot_err_deg(T, refs[k % len(specs)]) <= 1e-3
+                 and trans_err_m(T, refs[k % len(specs)]) <= 1e-5)
+        out[name] = {"ms_per_registration": 1e3 * dt, "registrations_per_s": ok / (dt * reps), "in_gate": ok,
+                     "registrations": reps, "mean_iterations": float(np.mean([i["iters"] for _, i in res]))}
+    print(f"[bench] variants: {json.dumps(out)}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -209,6 +256,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched LiDAR leg")
     ap.add_argument("--no-warmstart", action="store_true", help="skip the warm-start leg")
     ap.add_argument("--no-solvers", action="store_true", help="skip the Newton-solver leg")
+    ap.add_argument("--no-variants", action="store_true", help="skip the labelled / isotropic leg")
     ap.add_argument("--objects", action="store_true",
                     help="add the 256 object-pair batch leg (one gcvo_register_batch call)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -300,6 +348,8 @@ def main():
     precision = None if args.no_precision else precision_leg(gcvo, synth, golden, dev, rot_err_deg, trans_err_m)
     solvers = None if args.no_solvers else solver_leg(gcvo, specs, clouds, params, refs, ws, rot_err_deg,
                                                       trans_err_m)
+    variants = None if args.no_variants else variants_leg(gcvo, synth, golden, specs, clouds, rot_err_deg,
+                                                          trans_err_m, dev)
     warm = None if args.no_warmstart else warmstart_leg(gcvo, synth, dev, rot_err_deg, trans_err_m)
     objects = objects_leg(gcvo, synth, golden, dev, rot_err_deg, trans_err_m) if args.objects else None
 
@@ -351,7 +401,8 @@ def main():
                    "registrations_in_gate": passed, "mean_iterations": float(np.mean(iters)),
                    "kernel_pairs_per_s": pairs_per_s,
                    "pct_fp32_valu_peak": 100.0 * achieved / FP32_VALU_PEAK_TFLOPS,
-                   "batched": batch, "precision": precision, "solvers": solvers, "warmstart": warm,
+                   "batched": batch, "precision": precision, "solvers": solvers, "variants": variants,
+                   "warmstart": warm,
                    "objects": objects},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": None,

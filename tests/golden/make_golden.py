@@ -30,6 +30,13 @@ OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_poses.jso
 C4_SAMPLE_MAX_N = 4000
 INSTANCES = {1: range(8), 2: range(4), 3: range(2),
              4: [i for i, n in enumerate(synth.config4_sizes()) if n <= C4_SAMPLE_MAX_N]}
+# Variants of the LiDAR pairs (stored as "<pair>/<variant>"): a one-channel
+# intensity label per point (synth.pair_labels, "colour" field) weighting the
+# pairs, and the isotropic kernel (rho = 1), which needs more iterations.
+VARIANTS = {
+    "labels_intensity": dict(labels=(1, "colour")),
+    "isotropic": dict(overrides=dict(eig_ratio_min=1.0, max_iters=400, max_iters_per_stage=100)),
+}
 
 
 def rot_err_deg(Ta, Tb):
@@ -40,6 +47,7 @@ def rot_err_deg(Ta, Tb):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--configs", type=int, nargs="*", default=[1, 2])
+    ap.add_argument("--variants", action="store_true", help="write the LiDAR variant entries only")
     args = ap.parse_args()
     data = {}
     if os.path.exists(OUT):
@@ -47,6 +55,28 @@ def main():
             data = json.load(fh)
     data["_about"] = ("FP64 oracle fixed points (final stage to ||xi||_1 < 1e-12) for the seeded "
                       "synthetic pairs; written by tests/golden/make_golden.py from oracle/ only.")
+    if args.variants:
+        for i in INSTANCES[2]:
+            spec = synth.make_pair(2, i)
+            for name, v in VARIANTS.items():
+                kw = dict(v.get("overrides", {}))
+                if "labels" in v:
+                    LX, LZ = synth.pair_labels(spec, *v["labels"])
+                    kw.update(LX=LX.astype(np.float64), LZ=LZ.astype(np.float64))
+                t0 = time.time()
+                prod = O.register_spec(spec, **kw)
+                ref = O.register_spec(spec, **{**kw, "tol": 1e-12, "max_iters": kw.get("max_iters", 200) + 300})
+                key = f"{spec.name}/{name}"
+                data[key] = dict(config=2, instance=i, variant=name, digest=spec.digest(),
+                                 overrides=v.get("overrides", {}), labels=list(v.get("labels", ())),
+                                 T_ref=ref.T.reshape(-1).tolist(), ref_iters=ref.iters, ref_converged=ref.converged,
+                                 prod_iters=prod.iters, prod_stage_iters=prod.stage_iters,
+                                 prod_converged=prod.converged)
+                print(f"{key}: iters={prod.iters} stages={prod.stage_iters} ref_iters={ref.iters} "
+                      f"ref_converged={ref.converged} ({time.time() - t0:.1f} s)", flush=True)
+                with open(OUT, "w") as fh:
+                    json.dump(data, fh, indent=1, sort_keys=True)
+        return
     for c in args.configs:
         for i in INSTANCES[c]:
             spec = synth.make_pair(c, i)
