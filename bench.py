@@ -14,6 +14,9 @@ roofline: the pair kernel k_iterate (transform, pair terms, per-point finish,
 block partial sums), FP32 VALU bound.  A second pass over the same steps
 brackets every launch of that kernel with HIP events on the stream it runs on;
 algorithmic FLOP = 76 per pair within the cutoff + 230 per source point.
+traffic: HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE
+counter summary in profiles/ (null once the kernel sources differ from the ones
+it was taken with).
 
 Further legs (reported under config): the same pairs registered together by one
 batch call; the RGB-D precision pair with FP32 and FP64 kernels; the
@@ -28,6 +31,7 @@ on the host's cores.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -38,10 +42,28 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# HBM bytes per pair-kernel launch from the committed counter summary (FETCH_SIZE
+# and WRITE_SIZE, calibrated on a plain copy); reported only while the kernel
+# sources are the ones the counters were taken with.
+HBM_PROFILE = os.path.join(ROOT, "profiles", "k_iterate_lidar_pair_64x1024_hbm.txt")
+KERNEL_SOURCES = ["gcvo_api.cpp", "gcvo_dev.h", "gcvo_iter.hip", "gcvo_prep.hip"]
 FLOP_PER_PAIR = 76
 FLOP_PER_SOURCE_POINT = 230
 FP32_VALU_PEAK_TFLOPS = 157.3
 N_INSTANCES = 4
+
+
+def measured_traffic():
+    try:
+        text = open(HBM_PROFILE).read()
+    except OSError:
+        return None
+    vals = dict(line.split(":", 1) for line in text.splitlines() if ":" in line and not line.startswith("#"))
+    csrc = os.path.join(ROOT, "paper_2606_10019_amd", "csrc")
+    digest = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read() for f in KERNEL_SOURCES)).hexdigest()
+    if vals.get("sources_sha256", "").strip() != digest:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
 
 
 def precision_leg(gcvo, synth, golden, dev, rot_err_deg, trans_err_m, reps=2):
@@ -405,7 +427,7 @@ def main():
                    "warmstart": warm,
                    "objects": objects},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": measured_traffic(),
                      "kernel": "k_iterate<float>", "avg_launch_us": avg_launch_us,
                      "launches": prof["launches"]},
         "cpu_baseline": cpu,
