@@ -18,7 +18,9 @@ traffic: HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE
 counter summary in profiles/ (null once the kernel sources differ from the ones
 it was taken with).
 
-Further legs (reported under config): the same pairs registered together by one
+Before the timed steps, the pair-grid cell size is autotuned on the same pairs
+(untimed; every candidate finds the same pairs within the cutoff) and the
+fastest is used.  Further legs (reported under config): the same pairs registered together by one
 batch call; the RGB-D precision pair with FP32 and FP64 kernels; the
 exact-Hessian solver; the LiDAR pairs with an intensity label per point and
 with the isotropic kernel; the learned warm start on held-out large-motion pairs
@@ -51,6 +53,7 @@ FLOP_PER_PAIR = 76
 FLOP_PER_SOURCE_POINT = 230
 FP32_VALU_PEAK_TFLOPS = 157.3
 N_INSTANCES = 4
+TUNE_CANDIDATES = (0.35, 0.5, 0.7, 1.0)
 
 
 def measured_traffic():
@@ -206,7 +209,7 @@ def solver_leg(gcvo, specs, clouds, params, refs, ws, rot_err_deg, trans_err_m, 
     import torch
     out = {}
     for name, solver in (("gauss_newton", gcvo.GCVO_SOLVER_GN), ("newton_exact_hessian", gcvo.GCVO_SOLVER_NEWTON)):
-        ps = [gcvo.params_from_spec(s, solver=solver) for s in specs]
+        ps = [gcvo.params_from_spec(s, solver=solver, cell_fraction=params[0].cell_fraction) for s in specs]
         gcvo.gcvo_register(clouds[0][0], clouds[0][1], None, ps[0], ws=ws)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -222,7 +225,7 @@ def solver_leg(gcvo, specs, clouds, params, refs, ws, rot_err_deg, trans_err_m, 
     return out
 
 
-def variants_leg(gcvo, synth, golden, specs, clouds, rot_err_deg, trans_err_m, dev, reps=8):
+def variants_leg(gcvo, synth, golden, specs, clouds, rot_err_deg, trans_err_m, dev, cell_fraction, reps=8):
     """The LiDAR pairs with a one-channel intensity label per point (pairs
     weighted by the label product) and with the isotropic kernel (rho = 1, the
     CVO special case): time, iterations and gate against the oracle's fixed
@@ -237,7 +240,7 @@ def variants_leg(gcvo, synth, golden, specs, clouds, rot_err_deg, trans_err_m, d
         runs = []
         for k, s in enumerate(specs):
             g = golden[keys[k]]
-            p = gcvo.params_from_spec(s, **g["overrides"])
+            p = gcvo.params_from_spec(s, cell_fraction=cell_fraction, **g["overrides"])
             if g["labels"]:
                 LX, LZ = synth.pair_labels(s, *g["labels"])
                 lab = (torch.from_numpy(LX).to(dev), torch.from_numpy(LZ).to(dev))
@@ -279,6 +282,7 @@ def main():
     ap.add_argument("--no-warmstart", action="store_true", help="skip the warm-start leg")
     ap.add_argument("--no-solvers", action="store_true", help="skip the Newton-solver leg")
     ap.add_argument("--no-variants", action="store_true", help="skip the labelled / isotropic leg")
+    ap.add_argument("--no-tune", action="store_true", help="use the default pair-grid cell size (no autotuning)")
     ap.add_argument("--objects", action="store_true",
                     help="add the 256 object-pair batch leg (one gcvo_register_batch call)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -313,6 +317,29 @@ def main():
         clouds.append((torch.from_numpy(s.target).to(dev), torch.from_numpy(s.source).to(dev)))
         refs.append(np.array(g["T_ref"]).reshape(4, 4))
         params.append(gcvo.params_from_spec(s))
+    # Cell-size autotuning (untimed): whole single-pair registrations of the
+    # same pairs for each candidate pair-grid cell fraction; the fastest is used
+    # below.  Every candidate finds the same pairs within the cutoff.
+    tune = {}
+    if not args.no_tune:
+        for frac in TUNE_CANDIDATES:
+            ps = [gcvo.params_from_spec(s, cell_fraction=frac) for s in specs]
+            need = max(gcvo.gcvo_workspace_size(len(s.target), len(s.source), p) for s, p in zip(specs, ps))
+            tws = gcvo.workspace(need, dev)
+            for i in range(N_INSTANCES):
+                gcvo.gcvo_register(clouds[i][0], clouds[i][1], None, ps[i], ws=tws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(2):
+                for i in range(N_INSTANCES):
+                    gcvo.gcvo_register(clouds[i][0], clouds[i][1], None, ps[i], ws=tws)
+            torch.cuda.synchronize()
+            tune[frac] = 1e3 * (time.perf_counter() - t0) / (2 * N_INSTANCES)
+        best = min(tune, key=tune.get)
+        params = [gcvo.params_from_spec(s, cell_fraction=best) for s in specs]
+        print(f"[bench] cell-size autotune (ms per registration): {json.dumps(tune)} -> {best}", file=sys.stderr,
+              flush=True)
+    cell_fraction = params[0].cell_fraction
     need = max(gcvo.gcvo_workspace_size(len(s.target), len(s.source), p) for s, p in zip(specs, params))
     ws = gcvo.workspace(need, dev)
     print(f"[bench] {N_INSTANCES} LiDAR pairs, {[len(s.target) for s in specs]} target points, "
@@ -371,7 +398,7 @@ def main():
     solvers = None if args.no_solvers else solver_leg(gcvo, specs, clouds, params, refs, ws, rot_err_deg,
                                                       trans_err_m)
     variants = None if args.no_variants else variants_leg(gcvo, synth, golden, specs, clouds, rot_err_deg,
-                                                          trans_err_m, dev)
+                                                          trans_err_m, dev, cell_fraction)
     warm = None if args.no_warmstart else warmstart_leg(gcvo, synth, dev, rot_err_deg, trans_err_m)
     objects = objects_leg(gcvo, synth, golden, dev, rot_err_deg, trans_err_m) if args.objects else None
 
@@ -420,6 +447,7 @@ def main():
         "config": {"workload": "lidar_pair_64x1024_voxel0.3_anneal1.0to0.1",
                    "points_per_cloud": int(np.mean([len(s.target) for s in specs])),
                    "instances": N_INSTANCES, "registrations_total": args.steps,
+                   "cell_fraction": cell_fraction, "cell_fraction_tuning_ms": tune or None,
                    "registrations_in_gate": passed, "mean_iterations": float(np.mean(iters)),
                    "kernel_pairs_per_s": pairs_per_s,
                    "pct_fp32_valu_peak": 100.0 * achieved / FP32_VALU_PEAK_TFLOPS,

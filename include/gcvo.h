@@ -126,6 +126,10 @@ typedef struct gcvo_params {
     int precision;            /* GCVO_PRECISION_FP32 (default) or GCVO_PRECISION_FP64                    */
     int solver;               /* GCVO_SOLVER_GN (default), GCVO_SOLVER_NEWTON or GCVO_SOLVER_FIRST_ORDER */
     double min_step;          /* first-order solver: smallest step mu (> 0; 1e-10)                      */
+    double cell_fraction;     /* pair-grid cell edge as a fraction of the cutoff radius, in [0.2, 1]
+                                 (0.5).  Any value gives the same pairs within the cutoff, so the same
+                                 sums up to the order of FP32 additions; it trades candidates walked
+                                 against cell rows listed (see gcvo_autotune in the Python binding). */
 } gcvo_params;
 
 typedef struct gcvo_info {
@@ -141,7 +145,8 @@ typedef struct gcvo_info {
 } gcvo_info;
 
 /* Fills p with the defaults named above (ell = 0.3 fixed, cutoff 3, knn 10,
- * rho 0.01, sigma2 1, 30 iterations, tol 1e-6, stage_tol 1e-4, FP32, Gauss-Newton). */
+ * rho 0.01, sigma2 1, 30 iterations, tol 1e-6, stage_tol 1e-4, FP32, Gauss-Newton,
+ * cell fraction 0.5). */
 void gcvo_default_params(gcvo_params *p);
 
 /* Bytes of device workspace gcvo_register needs for clouds of these sizes and

@@ -30,7 +30,6 @@ constexpr int kGroupsPerWave = 64 / kGroupLanes;
 constexpr int kPointsPerBlock = (kBlock / 64) * kGroupsPerWave;   // source points per pair-kernel block
 constexpr int kMaxRows = 64;         // pair kernel: cell rows listed per batch and point
 constexpr int kReduceSplit = 8;      // blocks per pair of the cross-block reduction
-constexpr float kPairCellFraction = 0.5f;   // pair-grid cell edge as a fraction of the cutoff
 
 // Uniform grid over an axis-aligned box.  Cell of a point p along axis d is
 // clamp(floor((p_d - lo_d) * inv_h), 0, n_d - 1); cells are numbered x-fastest.
@@ -104,6 +103,7 @@ struct PairDev {
     int max_iters, max_per_stage;
     int solver;                       // GCVO_SOLVER_*
     double min_step;                  // first-order solver: smallest step mu
+    double cell_fraction;             // pair-grid cell edge as a fraction of the cutoff
     double T_init[16];                // caller frame
     // derived on device
     double centre[3];                 // target centroid, subtracted before the FP32 cast

@@ -176,7 +176,7 @@ __global__ void k_setup(PairDev *pairs, int n_pairs) {
         hi[d] = (float)((double)P.hi_t[d] - P.centre[d]);
     }
     for (int s = 0; s < P.n_stages; ++s)
-        make_grid(*P.t_grid[s], lo, hi, (double)kPairCellFraction * P.cutoff_scale * P.ell[s],
+        make_grid(*P.t_grid[s], lo, hi, P.cell_fraction * P.cutoff_scale * P.ell[s],
                   P.job_stage0[s].max_cells);
     State &S = *P.st;
     for (int a = 0; a < 16; ++a) S.T[a] = P.T_init[a];
