@@ -18,7 +18,7 @@ traffic: HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE
 counter summary in profiles/ (null once the kernel sources differ from the ones
 it was taken with).
 
-Before the timed steps, the pair-grid cell size is autotuned on the same pairs
+Before the timed steps, the pair-grid cell shape is autotuned on the same pairs
 (untimed; every candidate finds the same pairs within the cutoff) and the
 fastest is used.  Further legs (reported under config): the same pairs registered together by one
 batch call; the RGB-D precision pair with FP32 and FP64 kernels; the
@@ -53,7 +53,7 @@ FLOP_PER_PAIR = 76
 FLOP_PER_SOURCE_POINT = 230
 FP32_VALU_PEAK_TFLOPS = 157.3
 N_INSTANCES = 4
-TUNE_CANDIDATES = (0.35, 0.5, 0.7, 1.0)
+TUNE_CANDIDATES = ((0.5, 0.5), (0.5, 0.25), (0.5, 0.125), (0.7, 0.7), (0.7, 0.25), (0.7, 0.125))   # (y-z, x)
 
 
 def measured_traffic():
@@ -209,7 +209,8 @@ def solver_leg(gcvo, specs, clouds, params, refs, ws, rot_err_deg, trans_err_m, 
     import torch
     out = {}
     for name, solver in (("gauss_newton", gcvo.GCVO_SOLVER_GN), ("newton_exact_hessian", gcvo.GCVO_SOLVER_NEWTON)):
-        ps = [gcvo.params_from_spec(s, solver=solver, cell_fraction=params[0].cell_fraction) for s in specs]
+        ps = [gcvo.params_from_spec(s, solver=solver, cell_fraction=params[0].cell_fraction,
+                                    cell_fraction_x=params[0].cell_fraction_x) for s in specs]
         gcvo.gcvo_register(clouds[0][0], clouds[0][1], None, ps[0], ws=ws)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -240,7 +241,8 @@ def variants_leg(gcvo, synth, golden, specs, clouds, rot_err_deg, trans_err_m, d
         runs = []
         for k, s in enumerate(specs):
             g = golden[keys[k]]
-            p = gcvo.params_from_spec(s, cell_fraction=cell_fraction, **g["overrides"])
+            p = gcvo.params_from_spec(s, cell_fraction=cell_fraction[0], cell_fraction_x=cell_fraction[1],
+                                      **g["overrides"])
             if g["labels"]:
                 LX, LZ = synth.pair_labels(s, *g["labels"])
                 lab = (torch.from_numpy(LX).to(dev), torch.from_numpy(LZ).to(dev))
@@ -323,7 +325,7 @@ def main():
     tune = {}
     if not args.no_tune:
         for frac in TUNE_CANDIDATES:
-            ps = [gcvo.params_from_spec(s, cell_fraction=frac) for s in specs]
+            ps = [gcvo.params_from_spec(s, cell_fraction=frac[0], cell_fraction_x=frac[1]) for s in specs]
             need = max(gcvo.gcvo_workspace_size(len(s.target), len(s.source), p) for s, p in zip(specs, ps))
             tws = gcvo.workspace(need, dev)
             for i in range(N_INSTANCES):
@@ -334,12 +336,12 @@ def main():
                 for i in range(N_INSTANCES):
                     gcvo.gcvo_register(clouds[i][0], clouds[i][1], None, ps[i], ws=tws)
             torch.cuda.synchronize()
-            tune[frac] = 1e3 * (time.perf_counter() - t0) / (2 * N_INSTANCES)
-        best = min(tune, key=tune.get)
-        params = [gcvo.params_from_spec(s, cell_fraction=best) for s in specs]
+            tune[f"{frac[0]},{frac[1]}"] = 1e3 * (time.perf_counter() - t0) / (2 * N_INSTANCES)
+        best = TUNE_CANDIDATES[min(range(len(TUNE_CANDIDATES)), key=lambda k: list(tune.values())[k])]
+        params = [gcvo.params_from_spec(s, cell_fraction=best[0], cell_fraction_x=best[1]) for s in specs]
         print(f"[bench] cell-size autotune (ms per registration): {json.dumps(tune)} -> {best}", file=sys.stderr,
               flush=True)
-    cell_fraction = params[0].cell_fraction
+    cell_fraction = [params[0].cell_fraction, params[0].cell_fraction_x]
     need = max(gcvo.gcvo_workspace_size(len(s.target), len(s.source), p) for s, p in zip(specs, params))
     ws = gcvo.workspace(need, dev)
     print(f"[bench] {N_INSTANCES} LiDAR pairs, {[len(s.target) for s in specs]} target points, "

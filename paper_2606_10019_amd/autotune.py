@@ -1,13 +1,16 @@
-"""Cell-size autotuner for the pair kernel.
+"""Cell-shape autotuner for the pair kernel.
 
-The pair grid's cell edge (``gcvo_params.cell_fraction``, a fraction of the
-cutoff radius) trades the candidates a source point walks (large cells: more
-targets outside the cutoff) against the cell rows it lists (small cells: more,
-shorter rows).  Every value finds the same pairs within the cutoff, so the
-choice changes speed, not the sums beyond the order of FP32 additions.  The
-tuner times whole registrations (one batch call over sample pairs) for each
-candidate fraction on the device and returns the fastest; the caller then
-passes it in its parameters, so results stay reproducible call to call.
+The pair grid's cells have an edge along y and z (``gcvo_params.cell_fraction``)
+and along x, the direction of the rows a source point walks
+(``cell_fraction_x``), both as fractions of the cutoff radius.  Larger cells
+make a point walk more targets outside its cutoff; smaller y-z cells add rows
+to list and switch between; smaller x cells clip each row closer to the cutoff
+ball at no extra rows but with more cells.  Every shape finds the same pairs
+within the cutoff, so the choice changes speed, not the sums beyond the order
+of FP32 additions.  The tuner times whole registrations (one batch call over
+sample pairs) for each candidate shape on the device and returns the fastest;
+the caller then passes it in its parameters, so results stay reproducible
+call to call.
 """
 from __future__ import annotations
 
@@ -16,14 +19,19 @@ import time
 
 from . import gcvo
 
-CANDIDATES = (0.25, 0.35, 0.5, 0.7, 1.0)
+# (y-z fraction, x fraction)
+CANDIDATES = ((0.35, 0.35), (0.5, 0.5), (0.5, 0.25), (0.5, 0.125), (0.7, 0.7), (0.7, 0.25), (0.7, 0.125),
+              (1.0, 0.25))
 
 
-def _with_fraction(params, frac: float):
+def _with_fraction(params, frac):
+    fyz, fx = (frac, frac) if isinstance(frac, (int, float)) else frac
+
     def one(p):
         q = gcvo.gcvo_params()
         ctypes.pointer(q)[0] = p
-        q.cell_fraction = frac
+        q.cell_fraction = fyz
+        q.cell_fraction_x = fx
         return q
     if isinstance(params, gcvo.gcvo_params):
         return one(params)
@@ -33,8 +41,9 @@ def _with_fraction(params, frac: float):
 def autotune_cell_fraction(targets, tgt_off, sources, src_off, params, candidates=CANDIDATES, reps: int = 3,
                            T_init=None):
     """Time gcvo_register_batch over the given pairs for every candidate cell
-    fraction.  Returns (best fraction, {fraction: milliseconds per call},
-    {fraction: list of info dicts of the last call})."""
+    shape (a (y-z, x) pair of fractions, or one fraction for cubic cells).
+    Returns (best candidate, {candidate: milliseconds per call},
+    {candidate: list of info dicts of the last call})."""
     import torch
     timings, infos = {}, {}
     for frac in candidates:

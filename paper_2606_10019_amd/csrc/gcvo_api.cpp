@@ -63,6 +63,7 @@ bool params_ok(const gcvo_params *p) {
         return false;
     if (p->solver == GCVO_SOLVER_FIRST_ORDER && !pos(p->min_step)) return false;
     if (!(p->cell_fraction >= 0.2 && p->cell_fraction <= 1.0)) return false;
+    if (!(p->cell_fraction_x >= 0.1 && p->cell_fraction_x <= 1.0)) return false;
     double e[kMaxStages];
     return stage_schedule(*p, e) > 0;
 }
@@ -185,6 +186,7 @@ void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &p
         P.solver = (mode == Mode::Eval) ? GCVO_SOLVER_GN : I.p.solver;
         P.min_step = I.p.min_step;
         P.cell_fraction = I.p.cell_fraction;
+        P.cell_fraction_x = I.p.cell_fraction_x;
         std::memcpy(P.T_init, I.T0, sizeof P.T_init);
         P.t_orig = A.take<float>(3 * (size_t)nt);
         P.s_orig = A.take<float>(3 * (size_t)ns);
@@ -485,9 +487,10 @@ void gcvo_default_params(gcvo_params *p) {
     p->solver = GCVO_SOLVER_GN;
     p->min_step = 1e-10;
     p->cell_fraction = 0.5;
+    p->cell_fraction_x = 0.5;
 }
 
-int gcvo_abi_version(void) { return 103; }
+int gcvo_abi_version(void) { return 104; }
 
 void gcvo_profile_enable(int on) { g_prof.on = on != 0; }
 

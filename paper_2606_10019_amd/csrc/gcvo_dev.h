@@ -43,7 +43,8 @@ struct Grid {
     int n[3];
     int ncells;
     int key_bits;   // bits needed to hold ncells - 1 (radix passes = ceil(bits / 8))
-    int pad[2];
+    float hx;       // cell edge along x (pair grids may use finer x cells; h otherwise)
+    float inv_hx;
 };
 
 // Sort of one cloud's points into one grid: keys, a stable LSD radix sort of
@@ -103,7 +104,8 @@ struct PairDev {
     int max_iters, max_per_stage;
     int solver;                       // GCVO_SOLVER_*
     double min_step;                  // first-order solver: smallest step mu
-    double cell_fraction;             // pair-grid cell edge as a fraction of the cutoff
+    double cell_fraction;             // pair-grid cell edge (y, z) as a fraction of the cutoff
+    double cell_fraction_x;           // pair-grid cell edge along x (the row direction), same unit
     double T_init[16];                // caller frame
     // derived on device
     double centre[3];                 // target centroid, subtracted before the FP32 cast

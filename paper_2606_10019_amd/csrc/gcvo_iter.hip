@@ -762,9 +762,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     {
         const float rcm = (float)(rc * (double)kCellMargin);
         const float fy0 = (float)y0, fy1 = (float)y1, fy2 = (float)y2;
-        const float gx = (fy0 - G.lo[0]) * G.inv_h, gy = (fy1 - G.lo[1]) * G.inv_h, gz = (fy2 - G.lo[2]) * G.inv_h;
-        // radius in cell units, padded for the FP32 rounding of cell coordinates
+        // cell coordinates: y, z in units of h, x in units of hx (rows run along x)
+        const float gx = (fy0 - G.lo[0]) * G.inv_hx, gy = (fy1 - G.lo[1]) * G.inv_h, gz = (fy2 - G.lo[2]) * G.inv_h;
+        // radius in y-z cell units, padded for the FP32 rounding of cell coordinates
         const float rh = rcm * G.inv_h + 4e-7f * fmaxf(fabsf(gx), fmaxf(fabsf(gy), fabsf(gz)));
+        const float xs = G.h * G.inv_hx, padx = 4e-7f * fabsf(gx);   // y-z units -> x units, x rounding
         const int y_lo = max(0, (int)floorf(gy - rh)), y_hi = min(G.n[1] - 1, (int)floorf(gy + rh));
         const int z_lo = max(0, (int)floorf(gz - rh)), z_hi = min(G.n[2] - 1, (int)floorf(gz + rh));
         const int nyr = (valid && y_lo <= y_hi && z_lo <= z_hi) ? y_hi - y_lo + 1 : 0;
@@ -781,7 +783,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 const float rem = rh * rh - dy * dy - dz * dz;
                 int b = 0, len = 0;
                 if (rem >= 0.0f) {
-                    const float ext = sqrtf(rem);
+                    const float ext = sqrtf(rem) * xs + padx;   // half-length of the ball's section, x cells
                     const int x_lo = max(0, (int)floorf(gx - ext)), x_hi = min(G.n[0] - 1, (int)floorf(gx + ext));
                     if (x_lo <= x_hi) {
                         const int row = G.n[0] * (cy + G.n[1] * cz);

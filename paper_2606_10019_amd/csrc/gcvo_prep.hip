@@ -94,7 +94,10 @@ __device__ int bits_for(int v) {   // bits needed to represent v (>= 1)
 // Grid over [lo, hi] with cell edge at least h_min, grown until it has at most
 // max_cells cells (cell counts are evaluated in FP64 so nothing overflows).  A
 // box that is not finite gets a single cell (its pair is flagged invalid).
-__device__ void make_grid(Grid &G, const float lo[3], const float hi[3], double h_min, int max_cells) {
+// Grid over [lo, hi] with cells of edge h >= h_min (x edge x_ratio * h), grown
+// until there are at most max_cells cells.
+__device__ void make_grid(Grid &G, const float lo[3], const float hi[3], double h_min, int max_cells,
+                          double x_ratio = 1.0) {
     double ext[3];
     bool finite = true;
     for (int d = 0; d < 3; ++d) {
@@ -108,7 +111,7 @@ __device__ void make_grid(Grid &G, const float lo[3], const float hi[3], double 
     for (int guard = 0; finite && guard < 400; ++guard) {
         double nd[3], nc = 1.0;
         for (int d = 0; d < 3; ++d) {
-            nd[d] = floor(ext[d] / h) + 1.0;
+            nd[d] = floor(ext[d] / (d == 0 ? x_ratio * h : h)) + 1.0;
             nc *= nd[d];
         }
         if (nc <= (double)max_cells) {
@@ -126,6 +129,8 @@ __device__ void make_grid(Grid &G, const float lo[3], const float hi[3], double 
     for (int d = 0; d < 3; ++d) G.n[d] = n[d];
     G.h = (float)h;
     G.inv_h = ok ? (float)(1.0 / h) : 0.0f;
+    G.hx = ok ? (float)(x_ratio * h) : (float)h;
+    G.inv_hx = ok ? (float)(1.0 / (x_ratio * h)) : 0.0f;
     G.ncells = n[0] * n[1] * n[2];
     G.key_bits = bits_for(G.ncells > 1 ? G.ncells - 1 : 1);
 }
@@ -163,8 +168,8 @@ __global__ void k_setup(PairDev *pairs, int n_pairs) {
             M.lo[d] = isfinite(P.lo_s[d]) ? P.lo_s[d] : 0.0f;
             M.n[d] = 1024;
         }
-        M.h = (float)h;
-        M.inv_h = (float)(1.0 / h);
+        M.h = M.hx = (float)h;
+        M.inv_h = M.inv_hx = (float)(1.0 / h);
         M.ncells = 0;
         M.key_bits = 30;
     }
@@ -177,7 +182,7 @@ __global__ void k_setup(PairDev *pairs, int n_pairs) {
     }
     for (int s = 0; s < P.n_stages; ++s)
         make_grid(*P.t_grid[s], lo, hi, P.cell_fraction * P.cutoff_scale * P.ell[s],
-                  P.job_stage0[s].max_cells);
+                  P.job_stage0[s].max_cells, P.cell_fraction_x / P.cell_fraction);
     State &S = *P.st;
     for (int a = 0; a < 16; ++a) S.T[a] = P.T_init[a];
     S.f = 0.0;
@@ -225,7 +230,7 @@ __global__ __launch_bounds__(kBlock) void k_keys(SortJob *jobs) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= J.n) return;
     const Grid G = *J.grid;
-    int cx = cell_coord(J.x[i], G.lo[0], G.inv_h, G.n[0]);
+    int cx = cell_coord(J.x[i], G.lo[0], G.inv_hx, G.n[0]);
     int cy = cell_coord(J.y[i], G.lo[1], G.inv_h, G.n[1]);
     int cz = cell_coord(J.z[i], G.lo[2], G.inv_h, G.n[2]);
     if (J.morton) {
@@ -430,6 +435,7 @@ __global__ __launch_bounds__(kBlock) void k_knn(SortJob *jobs, const PairDev *pa
     const uint32_t p = valid ? J.idx[pos] : 0u;
     const float fx = J.x[p], fy = J.y[p], fz = J.z[p];
     const double px = fx, py = fy, pz = fz;
+    // kNN grids are isotropic (inv_hx == inv_h)
     const float gx = (fx - G.lo[0]) * G.inv_h, gy = (fy - G.lo[1]) * G.inv_h, gz = (fz - G.lo[2]) * G.inv_h;
     const int *cs = J.cell_start;
     const uint32_t *idx = J.idx;

@@ -55,7 +55,8 @@ class gcvo_params(ctypes.Structure):
                 ("knn", ctypes.c_int), ("eig_ratio_min", ctypes.c_double), ("sigma2", ctypes.c_double),
                 ("max_iters", ctypes.c_int), ("max_iters_per_stage", ctypes.c_int),
                 ("tol", ctypes.c_double), ("stage_tol", ctypes.c_double), ("precision", ctypes.c_int),
-                ("solver", ctypes.c_int), ("min_step", ctypes.c_double), ("cell_fraction", ctypes.c_double)]
+                ("solver", ctypes.c_int), ("min_step", ctypes.c_double), ("cell_fraction", ctypes.c_double),
+                ("cell_fraction_x", ctypes.c_double)]
 
 
 class gcvo_info(ctypes.Structure):

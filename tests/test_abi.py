@@ -29,9 +29,9 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     # sizes implied by the header's field order on x86-64
-    assert ctypes.sizeof(gcvo.gcvo_params) == 8 * 4 + 8 + 8 * 2 + 8 + 8 * 2 + 8 + 8 + 8
+    assert ctypes.sizeof(gcvo.gcvo_params) == 8 * 4 + 8 + 8 * 2 + 8 + 8 * 2 + 8 + 8 + 8 + 8
     assert ctypes.sizeof(gcvo.gcvo_info) == 4 * 4 + 8 + 8 + 48 + 8 + 4 * 16
-    assert gcvo.load_library().gcvo_abi_version() == 103
+    assert gcvo.load_library().gcvo_abi_version() == 104
 
 
 def test_default_params_and_strerror():
@@ -60,6 +60,9 @@ def test_workspace_size_validation():
     for cf in (0.1, 1.5, float("nan")):
         assert gcvo.gcvo_workspace_size(100, 100, gcvo.default_params(cell_fraction=cf)) == 0
     assert gcvo.gcvo_workspace_size(100, 100, gcvo.default_params(cell_fraction=0.25)) > 0
+    for cf in (0.05, 1.5):
+        assert gcvo.gcvo_workspace_size(100, 100, gcvo.default_params(cell_fraction_x=cf)) == 0
+    assert gcvo.gcvo_workspace_size(100, 100, gcvo.default_params(cell_fraction_x=0.125)) > 0
     # annealing 1.0 -> 0.1 by halves: 5 stages need more space than one stage
     ann = gcvo.default_params(length_scale=1.0, length_scale_min=0.1, anneal_factor=0.5)
     assert gcvo.gcvo_workspace_size(2000, 2000, ann) > gcvo.gcvo_workspace_size(2000, 2000, gcvo.default_params(

@@ -31,14 +31,14 @@ def note(msg):
     print(f"[gpu] {msg}", flush=True)
 
 
-@pytest.mark.parametrize("frac", autotune.CANDIDATES)
+@pytest.mark.parametrize("frac", autotune.CANDIDATES + ((0.2, 0.1), (1.0, 1.0)))
 def test_every_cell_fraction_reaches_the_fixed_point(frac):
     spec = synth.make_config1(1)
     ref = GOLDEN[spec.name]
     Tref = np.array(ref["T_ref"]).reshape(4, 4)
     note(f"register config1 instance 1 with cell fraction {frac}")
     T, info = gcvo.gcvo_register(to_dev(spec.target), to_dev(spec.source), None,
-                                 gcvo.params_from_spec(spec, cell_fraction=frac))
+                                 gcvo.params_from_spec(spec, cell_fraction=frac[0], cell_fraction_x=frac[1]))
     dr, dt = rot_err_deg(T, Tref), trans_err_m(T, Tref)
     note(f"  iters {info['iters']} (oracle {ref['prod_iters']}) err {dr:.2e} deg {dt:.2e} m")
     assert info["converged"] and dr < 1e-3 and dt < 1e-5
@@ -53,7 +53,7 @@ def test_autotuner_returns_a_candidate():
     so = np.cumsum([0] + [len(s.source) for s in specs])
     note("autotune cell fraction on two config1 pairs")
     best, timings, infos = autotune.autotune_cell_fraction(tgt, to, src, so, gcvo.params_from_spec(specs[0]), reps=1)
-    note(f"  best {best}; ms per call {json.dumps(timings)}")
+    note(f"  best {best}; ms per call {json.dumps({str(k): v for k, v in timings.items()})}")
     assert best in autotune.CANDIDATES and set(timings) == set(autotune.CANDIDATES)
     assert all(v > 0 for v in timings.values())
     for frac, inf in infos.items():
