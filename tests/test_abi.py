@@ -144,3 +144,16 @@ def test_labeled_and_isotropic_sizes_and_validation():
                                  0, ctypes.byref(f), g.ctypes.data_as(ctypes.c_void_p),
                                  H.ctypes.data_as(ctypes.c_void_p), None, None, 0, None)
     assert st == gcvo.GCVO_ERR_INVALID
+
+
+def test_autotune_candidates_copy_parameters():
+    from paper_2606_10019_amd import autotune
+    p = gcvo.default_params(length_scale=0.7, knn=12)
+    q = autotune._with_fraction(p, (0.7, 0.125))
+    assert (q.cell_fraction, q.cell_fraction_x) == (0.7, 0.125)
+    assert (q.length_scale, q.knn) == (0.7, 12)
+    assert (p.cell_fraction, p.cell_fraction_x) == (0.5, 0.5)      # the caller's set is untouched
+    qs = autotune._with_fraction([p, p], 0.35)
+    assert [(x.cell_fraction, x.cell_fraction_x) for x in qs] == [(0.35, 0.35)] * 2
+    for cand in autotune.CANDIDATES:                                # every candidate is a valid parameter set
+        assert gcvo.gcvo_workspace_size(500, 500, autotune._with_fraction(p, cand)) > 0
