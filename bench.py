@@ -53,7 +53,7 @@ FLOP_PER_PAIR = 76
 FLOP_PER_SOURCE_POINT = 230
 FP32_VALU_PEAK_TFLOPS = 157.3
 N_INSTANCES = 4
-TUNE_CANDIDATES = ((0.5, 0.5), (0.5, 0.25), (0.5, 0.125), (0.7, 0.7), (0.7, 0.25), (0.7, 0.125))   # (y-z, x)
+TUNE_CANDIDATES = ((0.5, 0.125), (0.5, 0.25), (0.5, 0.5), (0.7, 0.125), (0.7, 0.25), (1.0, 0.25))   # (y-z, x)
 
 
 def measured_traffic():

@@ -129,7 +129,7 @@ typedef struct gcvo_params {
     double cell_fraction;     /* pair-grid cell edge along y and z as a fraction of the cutoff radius,
                                  in [0.2, 1] (0.5)                                                       */
     double cell_fraction_x;   /* pair-grid cell edge along x (the direction of the cell rows a point
-                                 walks), same unit, in [0.1, 1] (0.5).  Any cell shape gives the same
+                                 walks), same unit, in [0.1, 1] (0.125).  Any cell shape gives the same
                                  pairs within the cutoff, so the same sums up to the order of FP32
                                  additions; smaller x cells clip each row closer to the cutoff ball
                                  without adding rows, smaller y-z cells add rows (see the autotuner
@@ -150,7 +150,7 @@ typedef struct gcvo_info {
 
 /* Fills p with the defaults named above (ell = 0.3 fixed, cutoff 3, knn 10,
  * rho 0.01, sigma2 1, 30 iterations, tol 1e-6, stage_tol 1e-4, FP32, Gauss-Newton,
- * cell fractions 0.5). */
+ * cell fractions 0.5 across and 0.125 along the rows). */
 void gcvo_default_params(gcvo_params *p);
 
 /* Bytes of device workspace gcvo_register needs for clouds of these sizes and

@@ -20,8 +20,8 @@ import time
 from . import gcvo
 
 # (y-z fraction, x fraction)
-CANDIDATES = ((0.35, 0.35), (0.5, 0.5), (0.5, 0.25), (0.5, 0.125), (0.7, 0.7), (0.7, 0.25), (0.7, 0.125),
-              (1.0, 0.25))
+CANDIDATES = ((0.35, 0.35), (0.35, 0.125), (0.5, 0.5), (0.5, 0.25), (0.5, 0.125), (0.7, 0.7), (0.7, 0.25),
+              (0.7, 0.125), (1.0, 0.25))
 
 
 def _with_fraction(params, frac):

@@ -487,7 +487,7 @@ void gcvo_default_params(gcvo_params *p) {
     p->solver = GCVO_SOLVER_GN;
     p->min_step = 1e-10;
     p->cell_fraction = 0.5;
-    p->cell_fraction_x = 0.5;
+    p->cell_fraction_x = 0.125;
 }
 
 int gcvo_abi_version(void) { return 104; }

