@@ -15,8 +15,8 @@ block partial sums), FP32 VALU bound.  A second pass over the same steps
 brackets every launch of that kernel with HIP events on the stream it runs on;
 algorithmic FLOP = 76 per pair within the cutoff + 230 per source point.
 traffic: HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE
-counter summary in profiles/ (null once the kernel sources differ from the ones
-it was taken with).
+counter summary in profiles/ (null once the kernel sources or the cell shape
+differ from the ones it was taken with).
 
 Before the timed steps, the pair-grid cell shape is autotuned on the same pairs
 (untimed; every candidate finds the same pairs within the cutoff) and the
@@ -56,7 +56,7 @@ N_INSTANCES = 4
 TUNE_CANDIDATES = ((0.5, 0.125), (0.5, 0.25), (0.5, 0.5), (0.7, 0.125), (0.7, 0.25), (1.0, 0.25))   # (y-z, x)
 
 
-def measured_traffic():
+def measured_traffic(cell_fraction):
     try:
         text = open(HBM_PROFILE).read()
     except OSError:
@@ -65,6 +65,8 @@ def measured_traffic():
     csrc = os.path.join(ROOT, "paper_2606_10019_amd", "csrc")
     digest = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read() for f in KERNEL_SOURCES)).hexdigest()
     if vals.get("sources_sha256", "").strip() != digest:
+        return None
+    if [float(v) for v in vals.get("cell_fraction", "").split()] != list(cell_fraction):
         return None
     return float(vals["traffic_bytes_per_launch"])
 
@@ -284,7 +286,9 @@ def main():
     ap.add_argument("--no-warmstart", action="store_true", help="skip the warm-start leg")
     ap.add_argument("--no-solvers", action="store_true", help="skip the Newton-solver leg")
     ap.add_argument("--no-variants", action="store_true", help="skip the labelled / isotropic leg")
-    ap.add_argument("--no-tune", action="store_true", help="use the default pair-grid cell size (no autotuning)")
+    ap.add_argument("--no-tune", action="store_true", help="use the default pair-grid cell shape (no autotuning)")
+    ap.add_argument("--cell-fraction", type=float, nargs=2, metavar=("YZ", "X"), default=None,
+                    help="use this pair-grid cell shape (fractions of the cutoff) instead of autotuning")
     ap.add_argument("--objects", action="store_true",
                     help="add the 256 object-pair batch leg (one gcvo_register_batch call)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -323,7 +327,10 @@ def main():
     # same pairs for each candidate pair-grid cell fraction; the fastest is used
     # below.  Every candidate finds the same pairs within the cutoff.
     tune = {}
-    if not args.no_tune:
+    if args.cell_fraction:
+        params = [gcvo.params_from_spec(s, cell_fraction=args.cell_fraction[0], cell_fraction_x=args.cell_fraction[1])
+                  for s in specs]
+    elif not args.no_tune:
         for frac in TUNE_CANDIDATES:
             ps = [gcvo.params_from_spec(s, cell_fraction=frac[0], cell_fraction_x=frac[1]) for s in specs]
             need = max(gcvo.gcvo_workspace_size(len(s.target), len(s.source), p) for s, p in zip(specs, ps))
@@ -457,7 +464,7 @@ def main():
                    "warmstart": warm,
                    "objects": objects},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": measured_traffic(),
+                     "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": measured_traffic(cell_fraction),
                      "kernel": "k_iterate<float>", "avg_launch_us": avg_launch_us,
                      "launches": prof["launches"]},
         "cpu_baseline": cpu,
