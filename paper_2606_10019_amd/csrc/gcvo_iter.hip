@@ -989,27 +989,39 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(PairDev *pairs) {
 }
 
 // The FP64 step of one pair, on one lane (its registers are not shared with
-// any wide kernel).  Step kinds: 0 Gauss-Newton, 1 Newton, 2 first-order
-// direction (after a gradient pass), 3 first-order line step.  A pair that
-// finishes decrements the batch's count of active pairs, which the host polls.
+// any wide kernel).  The wave first adds the reduction splits, one sum per
+// lane with all its loads in flight at once (same order as a single lane), so
+// the step starts after one memory round trip.  Step kinds: 0 Gauss-Newton,
+// 1 Newton, 2 first-order direction (after a gradient pass), 3 first-order line
+// step.  A pair that finishes decrements the batch's count of active pairs,
+// which the host polls.
 template <int Kind>
 __global__ __launch_bounds__(64) void k_step(PairDev *pairs, int *active) {
     constexpr int Mode = Kind == 1 ? kModeExact : Kind == 3 ? kModeLine : kModeGN;
     constexpr int NS = ModeInfo<Mode>::sums;
+    static_assert(NS < 64, "one sum per lane");
     PairDev &P = pairs[blockIdx.x];
     State &St = *P.st;
-    if (St.done || threadIdx.x != 0 || St.phase != (Mode == kModeLine ? 1 : 0)) return;
-    double tot[NS];
-    unsigned long long c = 0;
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
+    if (St.done || St.phase != (Mode == kModeLine ? 1 : 0)) return;
+    __shared__ double sh_tot[NS + 1];
+    const int lane = threadIdx.x;
+    if (lane < NS) {
         double acc = 0.0;
 #pragma unroll
-        for (int sp = 0; sp < kReduceSplit; ++sp) acc += St.sub[sp][k];
-        tot[k] = acc;
-    }
+        for (int sp = 0; sp < kReduceSplit; ++sp) acc += St.sub[sp][lane];
+        sh_tot[lane] = acc;
+    } else if (lane == NS) {
+        unsigned long long c = 0;
 #pragma unroll
-    for (int sp = 0; sp < kReduceSplit; ++sp) c += St.sub_pairs[sp];
+        for (int sp = 0; sp < kReduceSplit; ++sp) c += St.sub_pairs[sp];
+        sh_tot[NS] = (double)c;
+    }
+    __syncthreads();
+    if (lane != 0) return;
+    double tot[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) tot[k] = sh_tot[k];
+    const unsigned long long c = (unsigned long long)sh_tot[NS];
     if constexpr (Kind == 0 || Kind == 1) finish_iteration(P, St, tot, c, St.stage, Kind == 1);
     else if constexpr (Kind == 2) finish_direction(P, St, tot, c, St.stage);
     else finish_line(P, St, tot, St.stage);
