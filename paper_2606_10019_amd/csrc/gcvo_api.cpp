@@ -203,19 +203,20 @@ void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &p
         }
         if (mode != Mode::Shapes) P.s_sorted = A.take<float>(kSortedRows * (size_t)ns);
         if (P.label_dim > 0) P.s_lab = A.take<float4>((size_t)ns);
-        P.st = A.take<State>(1);
         P.iter_pairs = A.take<long long>((size_t)std::max(I.p.max_iters, 1));
         P.n_blocks = (ns + kPointsPerBlock - 1) / kPointsPerBlock;
         P.first_block = task;
         P.partials = A.take<float>((size_t)std::max(P.n_blocks, 1) * kPartialStride * 2);
-        auto make_job = [&](int kind, int n, const float *x, int max_cells) {
+        // device address of this pair's descriptor (the stage grids and the state live in it)
+        PairDev *P_dev = pl.d_pairs ? pl.d_pairs + k : nullptr;
+        auto make_job = [&](int kind, int n, const float *x, int max_cells, bool own_grid = true, Grid *grid = nullptr) {
             SortJob J{};
             J.x = x;
             J.y = x ? x + n : nullptr;
             J.z = x ? x + 2 * (size_t)n : nullptr;
             J.n = n;
             J.max_cells = max_cells;
-            J.grid = A.take<Grid>(1);
+            J.grid = own_grid ? A.take<Grid>(1) : grid;
             J.keys = A.take<uint32_t>(n);
             J.keys_tmp = A.take<uint32_t>(n);
             J.idx = A.take<uint32_t>(n);
@@ -257,11 +258,11 @@ void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &p
             ++job;
             P.job_stage0 = pl.d_jobs + job;
             for (int s = 0; s < nst[k]; ++s) {
-                SortJob Js = make_job(kJobStage + s, nt, P.t_rec, stage_cells);
+                SortJob Js = make_job(kJobStage + s, nt, P.t_rec, stage_cells, false,
+                                      P_dev ? &P_dev->t_grid[s] : nullptr);
                 P.t_sorted[s] = A.take<float>(kSortedRows * (size_t)nt);
                 if (P.label_dim > 0) P.t_lab[s] = A.take<float4>((size_t)nt);
                 P.t_cells[s] = Js.cell_start;
-                P.t_grid[s] = Js.grid;
                 if (base) pl.jobs[job] = Js;
                 ++job;
             }
@@ -339,7 +340,7 @@ int profile_collect(Plan &pl, int launched, int solver, hipStream_t s) {
     long long pairs = 0, points = 0;
     for (int k = 0; k < np; ++k) {
         State st;
-        if (hipMemcpy(&st, pl.pairs[k].st, sizeof st, hipMemcpyDeviceToHost) != hipSuccess) return GCVO_ERR_HIP;
+        if (hipMemcpy(&st, &pl.d_pairs[k].st, sizeof st, hipMemcpyDeviceToHost) != hipSuccess) return GCVO_ERR_HIP;
         const int it = std::min(st.iter + ((st.status != GCVO_OK) ? 1 : 0), pl.pairs[k].max_iters);
         active = std::max(active, it);
         if (it > 0) {
@@ -453,7 +454,7 @@ int register_many(Mode mode, std::vector<PairInput> &in, double *T_out, gcvo_inf
     const int np = (int)in.size();
     std::vector<State> st(np);
     for (int k = 0; k < np; ++k)
-        HIP_OK(hipMemcpyAsync(&st[k], pl.pairs[k].st, sizeof(State), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipMemcpyAsync(&st[k], &pl.d_pairs[k].st, sizeof(State), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     int first_err = GCVO_OK;
     for (int k = 0; k < np; ++k) {
@@ -695,7 +696,7 @@ int eval_fgh(const float *tgt_xyz, const float *tgt_shape6, const float *tgt_lab
     HIP_OK(launch_iterations(pl.d_pairs, 1, pl.d_tasks, (int)pl.tasks.size(), 1, precision, GCVO_SOLVER_GN,
                              pl.labels, false, pl.d_active, s));
     State st;
-    HIP_OK(hipMemcpyAsync(&st, pl.pairs[0].st, sizeof st, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(&st, &pl.d_pairs[0].st, sizeof st, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     if (st.status != GCVO_OK) return st.status;
     *f = st.f;

@@ -126,15 +126,18 @@ struct PairDev {
     float4 *s_lab;                    // source labels padded to 4 with zeros, Morton order (labels only)
     float4 *t_lab[kMaxStages];        // target labels in each stage grid's order (labels only)
     int *t_cells[kMaxStages];         // cell_start of each stage grid
-    Grid *t_grid[kMaxStages];
+    Grid t_grid[kMaxStages];          // pair grid of each stage (held here: one load fewer per kernel)
     SortJob *job_knn_t, *job_knn_s, *job_order_s, *job_stage0;   // job_stage0[s] for s < n_stages
-    State *st;
+
     long long *iter_pairs;            // [max_iters] pairs within the cutoff at each iteration
     void *partials;                   // [n_blocks][kPartialStride] block sums (pair-term precision)
     int n_blocks;                     // pair-kernel blocks (kPointsPerBlock source points each)
     int first_block;                  // index of the pair's first BlockTask
     int shapes_given;                 // 1: t_shape / s_shape are caller memory (eval path)
     int eval_only;                    // 1: stop after one evaluation, no step
+    // Solver state, held in the descriptor so that a kernel reaches it with the
+    // descriptor's own loads (no pointer to follow).
+    State st;
 };
 
 struct BlockTask {   // one block of the pair kernel: a pair and a 256-point slice of its source

@@ -668,13 +668,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     constexpr int NS = ModeInfo<Mode>::sums;
     const BlockTask task = tasks[blockIdx.x];
     PairDev &P = pairs[task.pair];
-    State &St = *P.st;
+    State &St = P.st;
     if (St.done || St.phase != (Mode == kModeLine ? 1 : 0)) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int grp = lane / kGroupLanes, q = lane % kGroupLanes;
     const int stage = St.stage;
     const double ell = P.ell[stage];
-    const Grid G = *P.t_grid[stage];
+    const Grid G = P.t_grid[stage];
     const int *cells = P.t_cells[stage];
     const int ns = P.n_s;
     constexpr bool kExact = sizeof(Real) == 8;   // FP64: recentre the original coordinates in FP64
@@ -953,7 +953,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(PairDev *pairs) {
     constexpr int kSlices = kReduceThreads / W;
     constexpr int kCountAt = NS + (NS & 1) * (sizeof(Real) == 4);   // 8-byte aligned slot of the pair count
     PairDev &P = pairs[blockIdx.y];
-    State &St = *P.st;
+    State &St = P.st;
     if (St.done || St.phase != (Mode == kModeLine ? 1 : 0)) return;
     const int split = blockIdx.x;
     const int tid = threadIdx.x, ck = tid % W, slice = tid / W;
@@ -1001,7 +1001,7 @@ __global__ __launch_bounds__(64) void k_step(PairDev *pairs, int *active) {
     constexpr int NS = ModeInfo<Mode>::sums;
     static_assert(NS < 64, "one sum per lane");
     PairDev &P = pairs[blockIdx.x];
-    State &St = *P.st;
+    State &St = P.st;
     if (St.done || St.phase != (Mode == kModeLine ? 1 : 0)) return;
     __shared__ double sh_tot[NS + 1];
     const int lane = threadIdx.x;
@@ -1031,7 +1031,7 @@ __global__ __launch_bounds__(64) void k_step(PairDev *pairs, int *active) {
 __global__ void k_count_active(const PairDev *pairs, int n_pairs, int *active) {
     __shared__ int sh[4];
     int c = 0;
-    for (int p = threadIdx.x; p < n_pairs; p += blockDim.x) c += pairs[p].st->done ? 0 : 1;
+    for (int p = threadIdx.x; p < n_pairs; p += blockDim.x) c += pairs[p].st.done ? 0 : 1;
     c = wave_sum(c);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = c;
     __syncthreads();

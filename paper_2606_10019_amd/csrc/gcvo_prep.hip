@@ -181,9 +181,9 @@ __global__ void k_setup(PairDev *pairs, int n_pairs) {
         hi[d] = (float)((double)P.hi_t[d] - P.centre[d]);
     }
     for (int s = 0; s < P.n_stages; ++s)
-        make_grid(*P.t_grid[s], lo, hi, P.cell_fraction * P.cutoff_scale * P.ell[s],
+        make_grid(P.t_grid[s], lo, hi, P.cell_fraction * P.cutoff_scale * P.ell[s],
                   P.job_stage0[s].max_cells, P.cell_fraction_x / P.cell_fraction);
-    State &S = *P.st;
+    State &S = P.st;
     for (int a = 0; a < 16; ++a) S.T[a] = P.T_init[a];
     S.f = 0.0;
     for (int a = 0; a < 6; ++a) S.g[a] = S.xi[a] = 0.0;
