@@ -29,7 +29,7 @@ constexpr int kGroupLanes = 16;      // pair kernel: lanes serving one source po
 constexpr int kGroupsPerWave = 64 / kGroupLanes;
 constexpr int kPointsPerBlock = (kBlock / 64) * kGroupsPerWave;   // source points per pair-kernel block
 constexpr int kMaxRows = 64;         // pair kernel: cell rows listed per batch and point
-constexpr int kReduceSplit = 8;      // blocks per pair of the cross-block reduction
+constexpr int kReduceSplit = 16;     // blocks per pair of the cross-block reduction
 
 // Uniform grid over an axis-aligned box.  Cell of a point p along axis d is
 // clamp(floor((p_d - lo_d) * inv_h), 0, n_d - 1); cells are numbered x-fastest.

@@ -186,3 +186,29 @@ def test_register_batch_matches_single_pairs():
         Ts, _ = gcvo.gcvo_register(to_dev(s.target), to_dev(s.source), None, gcvo.params_from_spec(s))
         assert infos[k]["converged"]
         assert np.array_equal(T[k], Ts), k
+
+
+def test_register_batch_reports_failing_pairs_individually():
+    """One pair too small for knn and one with no pair in reach fail on their
+    own (status in info, pose left at T_init); the other pairs of the batch
+    register exactly as they do alone."""
+    good = [synth.make_config1(i, n=700) for i in (0, 1)]
+    tiny = synth.make_config1(2, n=700)
+    tiny_tgt, tiny_src = tiny.target[:6], tiny.source[:6]             # fewer points than knn = 10
+    far = synth.make_config1(3, n=700)
+    far_src = far.source + np.float32(100.0)                           # nothing within the cutoff
+    tgts = [good[0].target, tiny_tgt, far.target, good[1].target]
+    srcs = [good[0].source, tiny_src, far_src, good[1].source]
+    to = np.cumsum([0] + [len(t) for t in tgts])
+    so = np.cumsum([0] + [len(s) for s in srcs])
+    T0 = np.tile(np.eye(4), (4, 1, 1))
+    T0[:, 0, 3] = 0.01                                                 # a non-identity start, to see it kept
+    note("register_batch with a too-small pair and an out-of-reach pair")
+    T, infos = gcvo.gcvo_register_batch(to_dev(np.concatenate(tgts)), to, to_dev(np.concatenate(srcs)), so, T0,
+                                        gcvo.params_from_spec(good[0]))
+    assert infos[1]["status"] == gcvo.GCVO_ERR_TOO_FEW_POINTS and np.array_equal(T[1], T0[1])
+    assert infos[2]["status"] == gcvo.GCVO_ERR_NO_PAIRS and np.array_equal(T[2], T0[2])
+    for k, s in ((0, good[0]), (3, good[1])):
+        Ts, inf = gcvo.gcvo_register(to_dev(s.target), to_dev(s.source), T0[k], gcvo.params_from_spec(s))
+        assert infos[k]["status"] == gcvo.GCVO_OK and infos[k]["converged"]
+        assert np.array_equal(T[k], Ts) and infos[k]["iters"] == inf["iters"], k
