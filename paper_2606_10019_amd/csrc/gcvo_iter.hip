@@ -800,30 +800,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 o -= rl;
                 if (++r < nb) { rs = rs_t[grp][r]; rl = rl_t[grp][r]; }
             }
-            // The whole 48-byte record of the next candidate is requested
-            // before the current one is evaluated (one memory round trip per
-            // candidate, overlapped with the pair arithmetic).
             // Isotropic FP32 passes need only the recentred coordinates (first 16 bytes).
             constexpr bool kXyzOnly = (Mode == kModeIso) && !kExact;
-            vf4 na = {}, nb4 = {}, nc = {}, nl = {};
-            if (r < nb) {
-                const GRec4 rec = trec + 3 * (size_t)(rs + o);
-                na = rec[0];
-                if constexpr (!kXyzOnly) { nb4 = rec[1]; nc = rec[2]; }
-                if constexpr (kLab) nl = tlab[rs + o];
-            }
             while (r < nb) {
-                const vf4 ra = na, rb = nb4, rcc = nc, lx = nl;
+                vf4 ra = {}, rb = {}, rcc = {}, lx = {};
+                {
+                    const GRec4 rec = trec + 3 * (size_t)(rs + o);
+                    ra = rec[0];
+                    if constexpr (!kXyzOnly) { rb = rec[1]; rcc = rec[2]; }
+                    if constexpr (kLab) lx = tlab[rs + o];
+                }
                 o += kGroupLanes;
                 while (r < nb && o >= rl) {
                     o -= rl;
                     if (++r < nb) { rs = rs_t[grp][r]; rl = rl_t[grp][r]; }
-                }
-                if (r < nb) {
-                    const GRec4 rec = trec + 3 * (size_t)(rs + o);
-                    na = rec[0];
-                    if constexpr (!kXyzOnly) { nb4 = rec[1]; nc = rec[2]; }
-                    if constexpr (kLab) nl = tlab[rs + o];
                 }
                 const Real xx = kExact ? (Real)((double)rcc.y - c0) : (Real)ra.x;
                 const Real xy = kExact ? (Real)((double)rcc.z - c1) : (Real)ra.y;
