@@ -3,10 +3,11 @@
 // Every entry point lays its device data out in the caller's workspace with a
 // bump allocator (a sizing pass with no base pointer gives *_workspace_size),
 // uploads the POD descriptors of gcvo_dev.h in one copy, enqueues the
-// preparation kernels and then the Gauss-Newton iterations in chunks.  While a
-// chunk runs, the host waits on the previous chunk's "pairs still active" count
-// (copied to pinned host memory), so the device never idles between chunks and
-// at most one chunk of no-op launches follows convergence.
+// preparation kernels and then the Gauss-Newton iterations in chunks.  The last
+// step kernel of a chunk stores each pair's done flag in pinned host memory
+// (no copy in the stream); while a chunk runs, the host reads the previous
+// chunk's flags, so the device never idles between chunks and at most one
+// chunk of no-op launches follows convergence.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -112,7 +113,6 @@ struct Plan {
     PairDev *d_pairs = nullptr;
     SortJob *d_jobs = nullptr;
     BlockTask *d_tasks = nullptr;
-    int *d_active = nullptr;
     char *desc_begin = nullptr;
     size_t desc_bytes = 0;
     int max_n = 0, max_job_n = 0, max_cells = 0;
@@ -148,7 +148,6 @@ void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &p
     pl.d_jobs = A.take<SortJob>(std::max(n_jobs, 1));
     pl.d_tasks = A.take<BlockTask>(std::max(n_tasks, 1));
     pl.desc_bytes = A.off - desc_start;
-    pl.d_active = A.take<int>(1);
     pl.labels = np > 0 && in[0].label_dim > 0;
     pl.iso = np > 0;
     for (int k = 0; k < np; ++k) pl.iso = pl.iso && isotropic(mode, in[k]);
@@ -296,15 +295,21 @@ hipEvent_t prof_event(size_t k) {
 
 struct Pinned {
     int *flags = nullptr;
+    int cap = 0;           // ints held
     ~Pinned() = default;   // lives for the thread; released by the runtime at exit
 };
 
-int *pinned_flags() {
+// Two slots of n done flags in pinned host memory, written by the device.  A
+// larger batch gets a new buffer of twice the size; the old one is kept until
+// the process ends (the device wrote it), so a thread holds a few small buffers.
+int *pinned_flags(int n) {
     static thread_local Pinned p;
-    if (!p.flags) {
+    if (p.cap < 2 * n) {
+        const int cap = std::max(2 * n, 2 * p.cap);
         void *q = nullptr;
-        if (hipHostMalloc(&q, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess) return nullptr;
+        if (hipHostMalloc(&q, sizeof(int) * (size_t)cap, hipHostMallocDefault) != hipSuccess) return nullptr;
         p.flags = static_cast<int *>(q);
+        p.cap = cap;
     }
     return p.flags;
 }
@@ -370,7 +375,8 @@ int profile_collect(Plan &pl, int launched, int solver, hipStream_t s) {
 }
 
 int run_iterations(Plan &pl, int max_iters, int precision, int solver, hipStream_t s) {
-    int *flags = pinned_flags();
+    const int np = (int)pl.pairs.size();
+    int *flags = pinned_flags(std::max(np, 1));
     if (!flags) return GCVO_ERR_HIP;
     hipEvent_t ev[2];
     HIP_OK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
@@ -379,26 +385,23 @@ int run_iterations(Plan &pl, int max_iters, int precision, int solver, hipStream
         return GCVO_ERR_HIP;
     }
     const int n_tasks = (int)pl.tasks.size();
-    const int np = (int)pl.pairs.size();
     int launched = 0, slot = 0, rc = GCVO_OK;
     bool pending[2] = {false, false};
-    if (launch_count_active(pl.d_pairs, np, pl.d_active, s) != hipSuccess) rc = GCVO_ERR_HIP;
     auto enqueue = [&](int c) -> hipError_t {
+        int *done = flags + (size_t)slot * np;
         if (!g_prof.on)
             return launch_iterations(pl.d_pairs, np, pl.d_tasks, n_tasks, c, precision, solver, pl.labels, pl.iso,
-                                     pl.d_active, s);
+                                     done, s);
         const int per = 2 * passes_per_iteration(solver);
         std::vector<hipEvent_t> ev((size_t)per * c);
         for (size_t i = 0; i < ev.size(); ++i)
             if (!(ev[i] = prof_event((size_t)per * launched + i))) return hipErrorOutOfMemory;
         return launch_iterations(pl.d_pairs, np, pl.d_tasks, n_tasks, c, precision, solver, pl.labels, pl.iso,
-                                 pl.d_active, s, ev.data());
+                                 done, s, ev.data());
     };
     while (rc == GCVO_OK && launched < max_iters) {
         const int c = std::min(kChunk, max_iters - launched);
-        if (enqueue(c) != hipSuccess ||
-            hipMemcpyAsync(&flags[slot], pl.d_active, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipEventRecord(ev[slot], s) != hipSuccess) {
+        if (enqueue(c) != hipSuccess || hipEventRecord(ev[slot], s) != hipSuccess) {
             rc = GCVO_ERR_HIP;
             break;
         }
@@ -411,7 +414,9 @@ int run_iterations(Plan &pl, int max_iters, int precision, int solver, hipStream
                 break;
             }
             pending[other] = false;
-            if (flags[other] == 0) break;
+            bool all_done = true;
+            for (int k = 0; k < np && all_done; ++k) all_done = flags[(size_t)other * np + k] != 0;
+            if (all_done) break;
         }
         slot = other;
     }
@@ -692,9 +697,8 @@ int eval_fgh(const float *tgt_xyz, const float *tgt_shape6, const float *tgt_lab
     build_plan(workspace, Mode::Eval, in, pl);
     int rc = upload_and_prepare(pl, 0, s);
     if (rc) return rc;
-    HIP_OK(launch_count_active(pl.d_pairs, 1, pl.d_active, s));
     HIP_OK(launch_iterations(pl.d_pairs, 1, pl.d_tasks, (int)pl.tasks.size(), 1, precision, GCVO_SOLVER_GN,
-                             pl.labels, false, pl.d_active, s));
+                             pl.labels, false, nullptr, s));
     State st;
     HIP_OK(hipMemcpyAsync(&st, &pl.d_pairs[0].st, sizeof st, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));

@@ -176,20 +176,18 @@ __device__ __forceinline__ float wave_max(float v) {
 hipError_t launch_prepare(PairDev *pairs_dev, int n_pairs, int max_n, SortJob *jobs_dev, int n_jobs,
                           int max_job_n, int max_cells, int knn, hipStream_t s);
 // Enqueue n_iters solver iterations (each a no-op for pairs already done) of
-// the given solver (GCVO_SOLVER_*; all pairs of a batch share it).  `active`
-// (device int) must hold the number of pairs not yet done; pairs that finish
-// decrement it.
+// the given solver (GCVO_SOLVER_*; all pairs of a batch share it).  With
+// host_done non-null (pinned host memory, n_pairs ints), the last pass stores
+// every pair's done flag there.
 // With `events` non-null, every pair-kernel launch is bracketed by two of them
 // (2 * passes_per_iteration(solver) * n_iters events, recorded in order).
 // labels: the pairs carry label vectors (all pairs of a batch or none);
 // iso: every pair's shapes are the identity (the isotropic pair kernel is used
 // for Gauss-Newton).
 hipError_t launch_iterations(PairDev *pairs_dev, int n_pairs, BlockTask *tasks_dev, int n_tasks, int n_iters,
-                             int precision, int solver, bool labels, bool iso, int *active, hipStream_t s,
+                             int precision, int solver, bool labels, bool iso, int *host_done, hipStream_t s,
                              hipEvent_t *events = nullptr);
 // Pair-kernel passes per solver iteration (2 for the first-order solver).
 int passes_per_iteration(int solver);
-// Count pairs not yet done into *active (device int).
-hipError_t launch_count_active(PairDev *pairs_dev, int n_pairs, int *active, hipStream_t s);
 
 }  // namespace gcvo

@@ -983,16 +983,20 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(PairDev *pairs) {
 // lane with all its loads in flight at once (same order as a single lane), so
 // the step starts after one memory round trip.  Step kinds: 0 Gauss-Newton,
 // 1 Newton, 2 first-order direction (after a gradient pass), 3 first-order line
-// step.  A pair that finishes decrements the batch's count of active pairs,
-// which the host polls.
+// step.  At the last pass of a chunk of iterations the host passes host_done
+// (pinned host memory, one int per pair), and every pair stores its done flag
+// there for the host to poll.
 template <int Kind>
-__global__ __launch_bounds__(64) void k_step(PairDev *pairs, int *active) {
+__global__ __launch_bounds__(64) void k_step(PairDev *pairs, int *host_done) {
     constexpr int Mode = Kind == 1 ? kModeExact : Kind == 3 ? kModeLine : kModeGN;
     constexpr int NS = ModeInfo<Mode>::sums;
     static_assert(NS < 64, "one sum per lane");
     PairDev &P = pairs[blockIdx.x];
     State &St = P.st;
-    if (St.done || St.phase != (Mode == kModeLine ? 1 : 0)) return;
+    if (St.done || St.phase != (Mode == kModeLine ? 1 : 0)) {
+        if (host_done && threadIdx.x == 0) host_done[blockIdx.x] = St.done;
+        return;
+    }
     __shared__ double sh_tot[NS + 1];
     const int lane = threadIdx.x;
     if (lane < NS) {
@@ -1015,21 +1019,11 @@ __global__ __launch_bounds__(64) void k_step(PairDev *pairs, int *active) {
     if constexpr (Kind == 0 || Kind == 1) finish_iteration(P, St, tot, c, St.stage, Kind == 1);
     else if constexpr (Kind == 2) finish_direction(P, St, tot, c, St.stage);
     else finish_line(P, St, tot, St.stage);
-    if (St.done) atomicSub(active, 1);
-}
-
-__global__ void k_count_active(const PairDev *pairs, int n_pairs, int *active) {
-    __shared__ int sh[4];
-    int c = 0;
-    for (int p = threadIdx.x; p < n_pairs; p += blockDim.x) c += pairs[p].st.done ? 0 : 1;
-    c = wave_sum(c);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = c;
-    __syncthreads();
-    if (threadIdx.x == 0) *active = sh[0] + sh[1] + sh[2] + sh[3];
+    if (host_done) host_done[blockIdx.x] = St.done;
 }
 
 template <typename Real, int Mode, int Kind, bool kLab>
-static void launch_pass(PairDev *pairs, int n_pairs, BlockTask *tasks, int n_tasks, int *active, hipStream_t s,
+static void launch_pass(PairDev *pairs, int n_pairs, BlockTask *tasks, int n_tasks, int *host_done, hipStream_t s,
                         hipEvent_t *&ev) {
     if (ev) {
         // events attached to the dispatch itself: they time the kernel, not the queue
@@ -1040,45 +1034,41 @@ static void launch_pass(PairDev *pairs, int n_pairs, BlockTask *tasks, int n_tas
         hipLaunchKernelGGL((k_iterate<Real, Mode, kLab>), dim3(n_tasks), dim3(kBlock), 0, s, pairs, tasks);
     }
     hipLaunchKernelGGL((k_reduce<Real, Mode>), dim3(kReduceSplit, n_pairs), dim3(kReduceThreads), 0, s, pairs);
-    hipLaunchKernelGGL((k_step<Kind>), dim3(n_pairs), dim3(64), 0, s, pairs, active);
+    hipLaunchKernelGGL((k_step<Kind>), dim3(n_pairs), dim3(64), 0, s, pairs, host_done);
 }
 
 template <typename Real, bool kLab>
 static void launch_iteration(PairDev *pairs, int n_pairs, BlockTask *tasks, int n_tasks, int solver, bool iso,
-                             int *active, hipStream_t s, hipEvent_t *&ev) {
+                             int *host_done, hipStream_t s, hipEvent_t *&ev) {
     if (solver == GCVO_SOLVER_NEWTON) {
-        launch_pass<Real, kModeExact, 1, kLab>(pairs, n_pairs, tasks, n_tasks, active, s, ev);
+        launch_pass<Real, kModeExact, 1, kLab>(pairs, n_pairs, tasks, n_tasks, host_done, s, ev);
     } else if (solver == GCVO_SOLVER_FIRST_ORDER) {
-        launch_pass<Real, kModeGN, 2, kLab>(pairs, n_pairs, tasks, n_tasks, active, s, ev);
-        launch_pass<Real, kModeLine, 3, kLab>(pairs, n_pairs, tasks, n_tasks, active, s, ev);
+        launch_pass<Real, kModeGN, 2, kLab>(pairs, n_pairs, tasks, n_tasks, nullptr, s, ev);
+        launch_pass<Real, kModeLine, 3, kLab>(pairs, n_pairs, tasks, n_tasks, host_done, s, ev);
     } else if (iso) {
-        launch_pass<Real, kModeIso, 0, kLab>(pairs, n_pairs, tasks, n_tasks, active, s, ev);
+        launch_pass<Real, kModeIso, 0, kLab>(pairs, n_pairs, tasks, n_tasks, host_done, s, ev);
     } else {
-        launch_pass<Real, kModeGN, 0, kLab>(pairs, n_pairs, tasks, n_tasks, active, s, ev);
+        launch_pass<Real, kModeGN, 0, kLab>(pairs, n_pairs, tasks, n_tasks, host_done, s, ev);
     }
 }
 
 int passes_per_iteration(int solver) { return solver == GCVO_SOLVER_FIRST_ORDER ? 2 : 1; }
 
 hipError_t launch_iterations(PairDev *pairs, int n_pairs, BlockTask *tasks, int n_tasks, int n_iters,
-                             int precision, int solver, bool labels, bool iso, int *active, hipStream_t s,
+                             int precision, int solver, bool labels, bool iso, int *host_done, hipStream_t s,
                              hipEvent_t *events) {
     if (n_tasks <= 0) return hipSuccess;
     hipEvent_t *ev = events;
     for (int it = 0; it < n_iters; ++it) {
+        int *done = (it == n_iters - 1) ? host_done : nullptr;   // the chunk's last pass reports
         if (precision == GCVO_PRECISION_FP64) {
-            if (labels) launch_iteration<double, true>(pairs, n_pairs, tasks, n_tasks, solver, iso, active, s, ev);
-            else launch_iteration<double, false>(pairs, n_pairs, tasks, n_tasks, solver, iso, active, s, ev);
+            if (labels) launch_iteration<double, true>(pairs, n_pairs, tasks, n_tasks, solver, iso, done, s, ev);
+            else launch_iteration<double, false>(pairs, n_pairs, tasks, n_tasks, solver, iso, done, s, ev);
         } else {
-            if (labels) launch_iteration<float, true>(pairs, n_pairs, tasks, n_tasks, solver, iso, active, s, ev);
-            else launch_iteration<float, false>(pairs, n_pairs, tasks, n_tasks, solver, iso, active, s, ev);
+            if (labels) launch_iteration<float, true>(pairs, n_pairs, tasks, n_tasks, solver, iso, done, s, ev);
+            else launch_iteration<float, false>(pairs, n_pairs, tasks, n_tasks, solver, iso, done, s, ev);
         }
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_count_active(PairDev *pairs, int n_pairs, int *active, hipStream_t s) {
-    hipLaunchKernelGGL(k_count_active, dim3(1), dim3(256), 0, s, pairs, n_pairs, active);
     return hipGetLastError();
 }
 
