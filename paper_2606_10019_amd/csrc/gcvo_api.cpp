@@ -236,6 +236,7 @@ void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &p
         if ((mode == Mode::Register && !iso) || mode == Mode::Shapes) {
             SortJob J = make_job(kJobKnnTarget, nt, P.t_orig, knn_cells_t);
             J.want_shapes = 1;
+            J.pts = A.take<float4>((size_t)J.n);
             J.shape_out = (mode == Mode::Shapes) ? I.shape_out : P.t_shape;
             P.job_knn_t = pl.d_jobs + job;
             if (base) pl.jobs[job] = J;
@@ -244,6 +245,7 @@ void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &p
         if (mode == Mode::Register && !iso) {
             SortJob J = make_job(kJobKnnSource, ns, P.s_orig, knn_cells_s);
             J.want_shapes = 1;
+            J.pts = A.take<float4>((size_t)J.n);
             J.shape_out = P.s_shape;
             P.job_knn_s = pl.d_jobs + job;
             if (base) pl.jobs[job] = J;

@@ -64,6 +64,7 @@ struct SortJob {
     int want_shapes;          // kNN jobs: 1 = compute shapes into shape_out
     int morton;               // 1: key = 30-bit Morton code of the 1024^3 grid cell (no cell table)
     float *shape_out;         // SoA [6][n], original point order
+    float4 *pts;              // kNN jobs: {x, y, z, point index bits} in sorted order
 };
 
 constexpr int kJobKnnTarget = 0;    // grid for the target's kNN shapes

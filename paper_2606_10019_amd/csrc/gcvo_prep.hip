@@ -414,6 +414,18 @@ __device__ void jacobi_cyclic(double a[3][3], double v[3][3]) {
     }
 }
 
+// Sorted point records of a kNN job: {x, y, z, index} at each sorted position,
+// so that a candidate is one 16-byte load instead of an index load followed by
+// three coordinate loads.
+__global__ __launch_bounds__(kBlock) void k_knn_pts(SortJob *jobs, const PairDev *pairs) {
+    const SortJob &J = jobs[blockIdx.y];
+    if (!J.want_shapes || pairs[J.pair].nonfinite) return;
+    const int pos = blockIdx.x * kBlock + threadIdx.x;
+    if (pos >= J.n) return;
+    const uint32_t c = J.idx[pos];
+    J.pts[pos] = make_float4(J.x[c], J.y[c], J.z[c], __uint_as_float(c));
+}
+
 // kNN with kGroupLanes lanes per point: the group lists the x-rows of grid
 // cells meeting a ball of radius r around the point, every lane keeps the K
 // best candidates it sees within r (FP64 squared distances, ties to the smaller
@@ -438,7 +450,7 @@ __global__ __launch_bounds__(kBlock) void k_knn(SortJob *jobs, const PairDev *pa
     // kNN grids are isotropic (inv_hx == inv_h)
     const float gx = (fx - G.lo[0]) * G.inv_h, gy = (fy - G.lo[1]) * G.inv_h, gz = (fz - G.lo[2]) * G.inv_h;
     const int *cs = J.cell_start;
-    const uint32_t *idx = J.idx;
+    const float4 *pts = J.pts;
     __shared__ int sh_rs[kBlock / 64][kGroupsPerWave][kMaxRows], sh_rl[kBlock / 64][kGroupsPerWave][kMaxRows];
     int (*rs_t)[kMaxRows] = sh_rs[wave];
     int (*rl_t)[kMaxRows] = sh_rl[wave];
@@ -490,10 +502,11 @@ __global__ __launch_bounds__(kBlock) void k_knn(SortJob *jobs, const PairDev *pa
                     if (++r < nb) { rs = rs_t[grp][r]; rl = rl_t[grp][r]; }
                 }
                 while (r < nb) {
-                    const uint32_t c = idx[rs + o];
+                    const float4 pc = pts[rs + o];
+                    const uint32_t c = __float_as_uint(pc.w);
                     // Exact differences of float32 values in FP64, products and sums
                     // in written order without contraction: reproducible ranking.
-                    const double dx = (double)J.x[c] - px, dyy = (double)J.y[c] - py, dzz = (double)J.z[c] - pz;
+                    const double dx = (double)pc.x - px, dyy = (double)pc.y - py, dzz = (double)pc.z - pz;
                     const double d = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dyy, dyy)), __dmul_rn(dzz, dzz));
                     if (d <= r2 && nb_less(d, c, bd[K - 1], bq[K - 1])) {
                         bool placed = false;
@@ -671,6 +684,7 @@ hipError_t launch_prepare(PairDev *pairs, int n_pairs, int max_n, SortJob *jobs,
         }
         hipLaunchKernelGGL(k_cells, dim3((max_cells + kBlock) / kBlock, n_jobs), dim3(kBlock), 0, s, jobs);
         if (knn > 0) {
+            hipLaunchKernelGGL(k_knn_pts, dim3(jx, n_jobs), dim3(kBlock), 0, s, jobs, pairs);
             dim3 g((max_job_n + kPointsPerBlock - 1) / kPointsPerBlock, n_jobs);
             switch (knn) {
                 case 2: launch_knn<2>(g, jobs, pairs, s); break;
