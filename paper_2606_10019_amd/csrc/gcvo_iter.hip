@@ -63,12 +63,15 @@ struct Fast<double> {
 // Solve A x = b (6x6) by Gaussian elimination with partial pivoting (rows of A
 // and b swapped in place); false when a pivot is below tiny * max|A|.
 __device__ __forceinline__ bool solve6(double A[6][6], double b[6], double x[6], double tiny) {
-    double amax = 0.0;
+    // max |A| as a tree of fmax (exact, so any order gives the same value)
+    double rmax[6];
 #pragma unroll
     for (int r = 0; r < 6; ++r)
-#pragma unroll
-        for (int c = 0; c < 6; ++c) amax = fmax(amax, fabs(A[r][c]));
+        rmax[r] = fmax(fmax(fmax(fabs(A[r][0]), fabs(A[r][1])), fmax(fabs(A[r][2]), fabs(A[r][3]))),
+                       fmax(fabs(A[r][4]), fabs(A[r][5])));
+    const double amax = fmax(fmax(0.0, fmax(rmax[0], rmax[1])), fmax(fmax(rmax[2], rmax[3]), fmax(rmax[4], rmax[5])));
     if (!(amax > 0.0) || !isfinite(amax)) return false;
+    double invd[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         int p = k;
@@ -84,9 +87,9 @@ __device__ __forceinline__ bool solve6(double A[6][6], double b[6], double x[6],
         if (!(best >= tiny * amax)) return false;
 #pragma unroll
         for (int r = k + 1; r < 6; ++r) {
-            if (r == p) {
+            if (r == p) {   // columns left of k are no longer read
 #pragma unroll
-                for (int c = 0; c < 6; ++c) {
+                for (int c = k; c < 6; ++c) {
                     const double t = A[k][c];
                     A[k][c] = A[r][c];
                     A[r][c] = t;
@@ -97,6 +100,7 @@ __device__ __forceinline__ bool solve6(double A[6][6], double b[6], double x[6],
             }
         }
         const double inv = 1.0 / A[k][k];
+        invd[k] = inv;
 #pragma unroll
         for (int r = k + 1; r < 6; ++r) {
             const double f = A[r][k] * inv;
@@ -110,7 +114,7 @@ __device__ __forceinline__ bool solve6(double A[6][6], double b[6], double x[6],
         double acc = b[r];
 #pragma unroll
         for (int c = r + 1; c < 6; ++c) acc -= A[r][c] * x[c];
-        x[r] = acc / A[r][r];
+        x[r] = acc * invd[r];
     }
     return true;
 }
@@ -129,13 +133,15 @@ __device__ __forceinline__ int damped_step(const double H[6][6], const double Hm
         for (int a = 0; a < 6; ++a) xi[a] = 0.0;
         return 0;
     }
-    double dn = 0.0;
-#pragma unroll
-    for (int a = 0; a < 6; ++a) dn += Hm[a][a] * Hm[a][a];
-    dn = sqrt(dn);
     for (int m = -1; m <= 6; ++m) {
         double A[6][6], b[6], x[6];
-        const double shift = (m < 0) ? 0.0 : 1e-6 * exp10((double)m) * dn;
+        double shift = 0.0;
+        if (m >= 0) {
+            double dn = 0.0;
+#pragma unroll
+            for (int a = 0; a < 6; ++a) dn += Hm[a][a] * Hm[a][a];
+            shift = 1e-6 * exp10((double)m) * sqrt(dn);
+        }
 #pragma unroll
         for (int r = 0; r < 6; ++r) {
 #pragma unroll
@@ -166,15 +172,18 @@ __device__ __forceinline__ void twist_exp(const double xi[6], double E[4][4]) {
     if (th < 1e-5) {
         a = 1.0 - th2 / 6.0;
         b = 0.5 - th2 / 24.0;
-    } else {
-        const double sh = sin(0.5 * th) / (0.5 * th);
-        a = sin(th) / th;
+    }
+    double sn = 0.0, ch = 1.0;
+    if (th >= 1e-5) {
+        sincos(0.5 * th, &sn, &ch);
+        const double sh = sn / (0.5 * th);
+        a = 2.0 * sn * ch / th;
         b = 0.5 * sh * sh;
     }
     if (th < 1e-2)
         c = (1.0 / 6.0) - th2 * (1.0 / 120.0) + th2 * th2 * (1.0 / 5040.0);
     else
-        c = (th - sin(th)) / (th2 * th);
+        c = (th - 2.0 * sn * ch) / (th2 * th);
     // W = w^, W^2 = w w^T - th2 I
     const double W[3][3] = {{0.0, -wz, wy}, {wz, 0.0, -wx}, {-wy, wx, 0.0}};
     const double w[3] = {wx, wy, wz};
