@@ -43,7 +43,10 @@
  * caller-provided DEVICE workspace of at least the size the matching
  * *_workspace_size function returns, aligned to 256 bytes; the library never
  * allocates device memory in these calls and never frees caller memory.
- * Pinned host memory for completion flags is allocated once per process.
+ * Pinned host memory for completion flags (two ints per pair of a call, which
+ * the device writes) is allocated per calling thread on its first call and
+ * again, twice as large, when a batch outgrows it; a thread keeps those
+ * buffers until the process ends.
  *
  * Streams.  `stream` is a hipStream_t (NULL = the default stream).  All device
  * work is enqueued on it.  gcvo_register, gcvo_eval_fgh and the info/T outputs
