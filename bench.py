@@ -296,7 +296,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); a registration runs on a single "
-              "device and this build has no multi-GPU path.", file=sys.stderr)
+              "device and the library has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
     import torch
