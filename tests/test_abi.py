@@ -97,6 +97,11 @@ def test_register_rejects_bad_arguments_without_gpu_work():
     st = L.gcvo_register(ctypes.c_void_p(16), 5, ctypes.c_void_p(16), 100, None, ctypes.byref(p), T,
                          ctypes.byref(info), None, 0, None)
     assert st == gcvo.GCVO_ERR_TOO_FEW_POINTS
+    # a cloud beyond GCVO_MAX_POINTS (2^26) is refused before its memory is touched
+    st = L.gcvo_register(ctypes.c_void_p(16), (1 << 26) + 1, ctypes.c_void_p(16), 100, None, ctypes.byref(p), T,
+                         ctypes.byref(info), None, 0, None)
+    assert st == gcvo.GCVO_ERR_CAPACITY and info.status == st
+    assert gcvo.gcvo_workspace_size((1 << 26) + 1, 100, p) == 0
     assert all(v == 0.0 for v in T)   # pose output untouched
 
 
