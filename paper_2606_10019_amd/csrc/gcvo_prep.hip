@@ -27,14 +27,27 @@ __global__ __launch_bounds__(1024) void k_stats(PairDev *pairs) {
     double s[3] = {0.0, 0.0, 0.0};
     float lo[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, hi[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
     int bad = 0;
-    for (int i = tid; i < n; i += 1024) {
+    // Four points' loads in flight per trip; they are added in the same order
+    // as one at a time.
+    constexpr int kAhead = 4;
+    for (int i0 = tid; i0 < n; i0 += 1024 * kAhead) {
+        float v[kAhead][3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            float v = xyz[3 * (size_t)i + d];
-            if (!isfinite(v)) bad = 1;
-            s[d] += (double)v;
-            lo[d] = fminf(lo[d], v);
-            hi[d] = fmaxf(hi[d], v);
+        for (int u = 0; u < kAhead; ++u) {
+            const int i = i0 + 1024 * u;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) v[u][d] = (i < n) ? xyz[3 * (size_t)i + d] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u) {
+            if (i0 + 1024 * u >= n) break;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                if (!isfinite(v[u][d])) bad = 1;
+                s[d] += (double)v[u][d];
+                lo[d] = fminf(lo[d], v[u][d]);
+                hi[d] = fmaxf(hi[d], v[u][d]);
+            }
         }
     }
     __shared__ double sh_s[3][16];
@@ -91,11 +104,10 @@ __device__ int bits_for(int v) {   // bits needed to represent v (>= 1)
     return b;
 }
 
-// Grid over [lo, hi] with cell edge at least h_min, grown until it has at most
-// max_cells cells (cell counts are evaluated in FP64 so nothing overflows).  A
-// box that is not finite gets a single cell (its pair is flagged invalid).
 // Grid over [lo, hi] with cells of edge h >= h_min (x edge x_ratio * h), grown
-// until there are at most max_cells cells.
+// until it has at most max_cells cells (cell counts are evaluated in FP64 so
+// nothing overflows).  A box that is not finite gets a single cell (its pair
+// is flagged invalid).
 __device__ void make_grid(Grid &G, const float lo[3], const float hi[3], double h_min, int max_cells,
                           double x_ratio = 1.0) {
     double ext[3];
@@ -150,53 +162,63 @@ __device__ double knn_cell(const float lo[3], const float hi[3], int n) {
     return 0.5 * cbrt(vol / (double)(n > 0 ? n : 1));
 }
 
-__global__ void k_setup(PairDev *pairs, int n_pairs) {
-    const int pair = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pair >= n_pairs) return;
-    PairDev &P = pairs[pair];
-    for (int d = 0; d < 3; ++d) P.centre[d] = P.n_t > 0 ? P.sum_t[d] / (double)P.n_t : 0.0;
-    if (P.job_knn_t) make_grid(*P.job_knn_t->grid, P.lo_t, P.hi_t, knn_cell(P.lo_t, P.hi_t, P.n_t),
-                               P.job_knn_t->max_cells);
-    if (P.job_knn_s) make_grid(*P.job_knn_s->grid, P.lo_s, P.hi_s, knn_cell(P.lo_s, P.hi_s, P.n_s),
-                               P.job_knn_s->max_cells);
-    if (P.job_order_s) {   // 1024 cells along the longest axis; keys are Morton codes
-        Grid &M = *P.job_order_s->grid;
-        double emax = 0.0;
-        for (int d = 0; d < 3; ++d) emax = fmax(emax, (double)P.hi_s[d] - (double)P.lo_s[d]);
-        const double h = (isfinite(emax) && emax > 0.0) ? emax / 1023.5 : 1.0;
-        for (int d = 0; d < 3; ++d) {
-            M.lo[d] = isfinite(P.lo_s[d]) ? P.lo_s[d] : 0.0f;
-            M.n[d] = 1024;
+// One 32-thread block per pair, the grids built side by side (each is a short
+// serial FP64 loop): thread 0 the centroid and the solver state, 1 and 2 the
+// kNN grids, 3 the source's Morton grid, 4 + s the pair grid of stage s.
+__global__ __launch_bounds__(32) void k_setup(PairDev *pairs) {
+    PairDev &P = pairs[blockIdx.x];
+    const int t = threadIdx.x;
+    double c[3];
+    for (int d = 0; d < 3; ++d) c[d] = P.n_t > 0 ? P.sum_t[d] / (double)P.n_t : 0.0;
+    if (t == 0) {
+        for (int d = 0; d < 3; ++d) P.centre[d] = c[d];
+        State &S = P.st;
+        for (int a = 0; a < 16; ++a) S.T[a] = P.T_init[a];
+        S.f = 0.0;
+        for (int a = 0; a < 6; ++a) S.g[a] = S.xi[a] = 0.0;
+        for (int a = 0; a < 36; ++a) S.H[a] = 0.0;
+        S.xi_l1 = 0.0;
+        S.pairs_last = 0;
+        S.iter = S.stage = S.stage_iter = S.converged = S.damped = 0;
+        S.phase = 0;
+        S.gnorm = 0.0;
+        for (int a = 0; a < 6; ++a) S.dir[a] = 0.0;
+        for (int s = 0; s < kMaxStages; ++s) S.stage_iters[s] = 0;
+        S.status = P.nonfinite ? GCVO_ERR_INVALID : GCVO_OK;
+        S.done = P.nonfinite ? 1 : 0;
+    } else if (t == 1) {
+        if (P.job_knn_t)
+            make_grid(*P.job_knn_t->grid, P.lo_t, P.hi_t, knn_cell(P.lo_t, P.hi_t, P.n_t), P.job_knn_t->max_cells);
+    } else if (t == 2) {
+        if (P.job_knn_s)
+            make_grid(*P.job_knn_s->grid, P.lo_s, P.hi_s, knn_cell(P.lo_s, P.hi_s, P.n_s), P.job_knn_s->max_cells);
+    } else if (t == 3) {
+        if (P.job_order_s) {   // 1024 cells along the longest axis; keys are Morton codes
+            Grid &M = *P.job_order_s->grid;
+            double emax = 0.0;
+            for (int d = 0; d < 3; ++d) emax = fmax(emax, (double)P.hi_s[d] - (double)P.lo_s[d]);
+            const double h = (isfinite(emax) && emax > 0.0) ? emax / 1023.5 : 1.0;
+            for (int d = 0; d < 3; ++d) {
+                M.lo[d] = isfinite(P.lo_s[d]) ? P.lo_s[d] : 0.0f;
+                M.n[d] = 1024;
+            }
+            M.h = M.hx = (float)h;
+            M.inv_h = M.inv_hx = (float)(1.0 / h);
+            M.ncells = 0;
+            M.key_bits = 30;
         }
-        M.h = M.hx = (float)h;
-        M.inv_h = M.inv_hx = (float)(1.0 / h);
-        M.ncells = 0;
-        M.key_bits = 30;
+    } else if (t - 4 < P.n_stages) {
+        // Stage grids over the recentred target.  float(x - c) is monotone in
+        // x, so the recentred box is the rounded original box.
+        const int s = t - 4;
+        float lo[3], hi[3];
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = (float)((double)P.lo_t[d] - c[d]);
+            hi[d] = (float)((double)P.hi_t[d] - c[d]);
+        }
+        make_grid(P.t_grid[s], lo, hi, P.cell_fraction * P.cutoff_scale * P.ell[s], P.job_stage0[s].max_cells,
+                  P.cell_fraction_x / P.cell_fraction);
     }
-    // Stage grids over the recentred target.  float(x - c) is monotone in x,
-    // so the recentred box is the rounded original box.
-    float lo[3], hi[3];
-    for (int d = 0; d < 3; ++d) {
-        lo[d] = (float)((double)P.lo_t[d] - P.centre[d]);
-        hi[d] = (float)((double)P.hi_t[d] - P.centre[d]);
-    }
-    for (int s = 0; s < P.n_stages; ++s)
-        make_grid(P.t_grid[s], lo, hi, P.cell_fraction * P.cutoff_scale * P.ell[s],
-                  P.job_stage0[s].max_cells, P.cell_fraction_x / P.cell_fraction);
-    State &S = P.st;
-    for (int a = 0; a < 16; ++a) S.T[a] = P.T_init[a];
-    S.f = 0.0;
-    for (int a = 0; a < 6; ++a) S.g[a] = S.xi[a] = 0.0;
-    for (int a = 0; a < 36; ++a) S.H[a] = 0.0;
-    S.xi_l1 = 0.0;
-    S.pairs_last = 0;
-    S.iter = S.stage = S.stage_iter = S.converged = S.damped = 0;
-    S.phase = 0;
-    S.gnorm = 0.0;
-    for (int a = 0; a < 6; ++a) S.dir[a] = 0.0;
-    for (int s = 0; s < kMaxStages; ++s) S.stage_iters[s] = 0;
-    S.status = P.nonfinite ? GCVO_ERR_INVALID : GCVO_OK;
-    S.done = P.nonfinite ? 1 : 0;
 }
 
 // ------------------------------------------------------------------ k_soa
@@ -668,7 +690,8 @@ static void launch_knn(dim3 grid, SortJob *jobs, const PairDev *pairs, hipStream
 hipError_t launch_prepare(PairDev *pairs, int n_pairs, int max_n, SortJob *jobs, int n_jobs, int max_job_n,
                           int max_cells, int knn, hipStream_t s) {
     hipLaunchKernelGGL(k_stats, dim3(2 * n_pairs), dim3(1024), 0, s, pairs);
-    hipLaunchKernelGGL(k_setup, dim3((n_pairs + 63) / 64), dim3(64), 0, s, pairs, n_pairs);
+    static_assert(4 + kMaxStages <= 32, "one setup thread per grid");
+    hipLaunchKernelGGL(k_setup, dim3(n_pairs), dim3(32), 0, s, pairs);
     const int bx = (max_n + kBlock - 1) / kBlock;
     if (bx > 0) hipLaunchKernelGGL(k_soa, dim3(bx, 2 * n_pairs), dim3(kBlock), 0, s, pairs);
     const int jx = (max_job_n + kBlock - 1) / kBlock;
