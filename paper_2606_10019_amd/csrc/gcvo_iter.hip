@@ -811,18 +811,28 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             }
             // Isotropic FP32 passes need only the recentred coordinates (first 16 bytes).
             constexpr bool kXyzOnly = (Mode == kModeIso) && !kExact;
+            // Byte offset of the current record from the stage's (uniform) base:
+            // loads with a scalar base and a 32-bit offset, stepped by the lane
+            // stride within a row and recomputed only at row changes.
+            static_assert(GCVO_MAX_POINTS * 48LL < (1LL << 32), "record offsets fit in 32 bits");
+            typedef const __attribute__((address_space(1))) char *GBytes;
+            unsigned off = (unsigned)(rs + o) * 48u;
             while (r < nb) {
                 vf4 ra = {}, rb = {}, rcc = {}, lx = {};
                 {
-                    const GRec4 rec = trec + 3 * (size_t)(rs + o);
+                    const GRec4 rec = (GRec4)((GBytes)trec + off);
                     ra = rec[0];
                     if constexpr (!kXyzOnly) { rb = rec[1]; rcc = rec[2]; }
                     if constexpr (kLab) lx = tlab[rs + o];
                 }
                 o += kGroupLanes;
-                while (r < nb && o >= rl) {
-                    o -= rl;
-                    if (++r < nb) { rs = rs_t[grp][r]; rl = rl_t[grp][r]; }
+                off += 48u * kGroupLanes;
+                if (o >= rl) {
+                    while (r < nb && o >= rl) {
+                        o -= rl;
+                        if (++r < nb) { rs = rs_t[grp][r]; rl = rl_t[grp][r]; }
+                    }
+                    off = (unsigned)(rs + o) * 48u;
                 }
                 const Real xx = kExact ? (Real)((double)rcc.y - c0) : (Real)ra.x;
                 const Real xy = kExact ? (Real)((double)rcc.z - c1) : (Real)ra.y;
