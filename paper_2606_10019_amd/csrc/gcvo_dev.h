@@ -85,8 +85,7 @@ struct State {
     int pad0;
     double dir[6];                    // first-order solver: unit ascent direction (caller frame)
     double gnorm;                     // its gradient's norm
-    double sub[kReduceSplit][kMaxSums];   // cross-block sums of the current pass, by reduction block
-    unsigned long long sub_pairs[kReduceSplit];
+    double sub[kReduceSplit][kMaxSums];   // cross-block sums of the current pass by reduction block; the pair count follows the sums
 };
 
 // Everything one registration problem needs on the device.

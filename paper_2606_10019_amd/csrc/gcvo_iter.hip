@@ -60,25 +60,27 @@ struct Fast<double> {
 // All 6x6 algebra below is fully unrolled with compile-time indices so that it
 // stays in registers (one lane per pair runs it).
 
-// Solve A x = b (6x6) by Gaussian elimination with partial pivoting (rows of A
-// and b swapped in place); false when a pivot is below tiny * max|A|.
-__device__ __forceinline__ bool solve6(double A[6][6], double b[6], double x[6], double tiny) {
+// Solve A x = b (6x6) by Gaussian elimination with partial pivoting on the
+// augmented matrix M = [A | b] (rows swapped in place; b in column 6, so that
+// the swaps of b stay in registers like those of A); false when a pivot is
+// below tiny * max|A|.
+__device__ __forceinline__ bool solve6(double M[6][7], double x[6], double tiny) {
     // max |A| as a tree of fmax (exact, so any order gives the same value)
     double rmax[6];
 #pragma unroll
     for (int r = 0; r < 6; ++r)
-        rmax[r] = fmax(fmax(fmax(fabs(A[r][0]), fabs(A[r][1])), fmax(fabs(A[r][2]), fabs(A[r][3]))),
-                       fmax(fabs(A[r][4]), fabs(A[r][5])));
+        rmax[r] = fmax(fmax(fmax(fabs(M[r][0]), fabs(M[r][1])), fmax(fabs(M[r][2]), fabs(M[r][3]))),
+                       fmax(fabs(M[r][4]), fabs(M[r][5])));
     const double amax = fmax(fmax(0.0, fmax(rmax[0], rmax[1])), fmax(fmax(rmax[2], rmax[3]), fmax(rmax[4], rmax[5])));
     if (!(amax > 0.0) || !isfinite(amax)) return false;
     double invd[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         int p = k;
-        double best = fabs(A[k][k]);
+        double best = fabs(M[k][k]);
 #pragma unroll
         for (int r = k + 1; r < 6; ++r) {
-            const double v = fabs(A[r][k]);
+            const double v = fabs(M[r][k]);
             if (v > best) {
                 best = v;
                 p = r;
@@ -89,31 +91,27 @@ __device__ __forceinline__ bool solve6(double A[6][6], double b[6], double x[6],
         for (int r = k + 1; r < 6; ++r) {
             if (r == p) {   // columns left of k are no longer read
 #pragma unroll
-                for (int c = k; c < 6; ++c) {
-                    const double t = A[k][c];
-                    A[k][c] = A[r][c];
-                    A[r][c] = t;
+                for (int c = k; c < 7; ++c) {
+                    const double t = M[k][c];
+                    M[k][c] = M[r][c];
+                    M[r][c] = t;
                 }
-                const double t = b[k];
-                b[k] = b[r];
-                b[r] = t;
             }
         }
-        const double inv = 1.0 / A[k][k];
+        const double inv = 1.0 / M[k][k];
         invd[k] = inv;
 #pragma unroll
         for (int r = k + 1; r < 6; ++r) {
-            const double f = A[r][k] * inv;
+            const double f = M[r][k] * inv;
 #pragma unroll
-            for (int c = k + 1; c < 6; ++c) A[r][c] -= f * A[k][c];
-            b[r] -= f * b[k];
+            for (int c = k + 1; c < 7; ++c) M[r][c] -= f * M[k][c];
         }
     }
 #pragma unroll
     for (int r = 5; r >= 0; --r) {
-        double acc = b[r];
+        double acc = M[r][6];
 #pragma unroll
-        for (int c = r + 1; c < 6; ++c) acc -= A[r][c] * x[c];
+        for (int c = r + 1; c < 6; ++c) acc -= M[r][c] * x[c];
         x[r] = acc * invd[r];
     }
     return true;
@@ -134,7 +132,7 @@ __device__ __forceinline__ int damped_step(const double H[6][6], const double Hm
         return 0;
     }
     for (int m = -1; m <= 6; ++m) {
-        double A[6][6], b[6], x[6];
+        double A[6][7], x[6];
         double shift = 0.0;
         if (m >= 0) {
             double dn = 0.0;
@@ -147,9 +145,9 @@ __device__ __forceinline__ int damped_step(const double H[6][6], const double Hm
 #pragma unroll
             for (int c = 0; c < 6; ++c) A[r][c] = (m < 0) ? H[r][c] : Hm[r][c];
             A[r][r] -= shift;
-            b[r] = -g[r];
+            A[r][6] = -g[r];
         }
-        if (solve6(A, b, x, 1e-12)) {
+        if (solve6(A, x, 1e-12)) {
             double gx = 0.0;
 #pragma unroll
             for (int a = 0; a < 6; ++a) gx += g[a] * x[a];
@@ -359,9 +357,91 @@ __device__ __forceinline__ void frame_grad(const double c[3], const double *tot,
     }
 }
 
+// Empty asm statements that hold a loaded value at a point of the program, so
+// that the compiler can neither sink its load past a following branch nor
+// issue it late: they put a kernel's dependent-free loads into one memory
+// round trip ahead of its early-exit test.  pin_s / pin_v are volatile, and
+// the compiler then gives later loads of the kernel their per-lane form (for
+// kernels with none, or with per-lane loads only); tie_s instead makes `key`,
+// a value the early-exit test reads, depend on x without changing either, so
+// that later uniform loads stay scalar.
+template <typename T>
+__device__ __forceinline__ void pin_s(T x) {
+    asm volatile("" ::"s"(x));
+}
+template <typename T>
+__device__ __forceinline__ void pin_v(T x) {
+    asm volatile("" ::"v"(x));
+}
+template <typename T>
+__device__ __forceinline__ void tie_s(int &key, T x) {
+    asm("" : "+s"(key) : "s"(x));
+}
+
+// What the step reads from the descriptor and the state, loaded once at the
+// step kernel's start, in the same memory round trip as the reduction splits;
+// after that the step reads registers only and writes the state back.
+struct StepIn {
+    double T[16];
+    double centre[3];
+    double dir[6];
+    double sigma2, tol, stage_tol, min_step, gnorm;
+    long long *iter_pairs;
+    int iter, stage, stage_iter, damped, n_stages, max_iters, max_per_stage, eval_only;
+};
+
+__device__ __forceinline__ StepIn load_step_in(const PairDev &P) {
+    const State &St = P.st;
+    StepIn R;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) R.T[i] = St.T[i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) R.centre[a] = P.centre[a];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) R.dir[a] = St.dir[a];
+    R.sigma2 = P.sigma2;
+    R.tol = P.tol;
+    R.stage_tol = P.stage_tol;
+    R.min_step = P.min_step;
+    R.gnorm = St.gnorm;
+    R.iter_pairs = P.iter_pairs;
+    R.iter = St.iter;
+    R.stage = St.stage;
+    R.stage_iter = St.stage_iter;
+    R.damped = St.damped;
+    R.n_stages = P.n_stages;
+    R.max_iters = P.max_iters;
+    R.max_per_stage = P.max_per_stage;
+    R.eval_only = P.eval_only;
+    return R;
+}
+
+__device__ __forceinline__ void pin_step_in(const StepIn &R) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) pin_s(R.T[i]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) pin_s(R.centre[a]);
+#pragma unroll
+    for (int a = 0; a < 6; ++a) pin_s(R.dir[a]);
+    pin_s(R.sigma2);
+    pin_s(R.tol);
+    pin_s(R.stage_tol);
+    pin_s(R.min_step);
+    pin_s(R.gnorm);
+    pin_s(R.iter_pairs);
+    pin_s(R.iter);
+    pin_s(R.stage);
+    pin_s(R.stage_iter);
+    pin_s(R.damped);
+    pin_s(R.n_stages);
+    pin_s(R.max_iters);
+    pin_s(R.max_per_stage);
+    pin_s(R.eval_only);
+}
+
 // Record the evaluation (f, g, H) of the current pass.
-__device__ __forceinline__ void record_eval(PairDev &P, State &St, double f, const double g[6], const double H[6][6],
-                                            unsigned long long tot_pairs) {
+__device__ __forceinline__ void record_eval(const StepIn &R, State &St, double f, const double g[6],
+                                            const double H[6][6], unsigned long long tot_pairs) {
     St.f = f;
 #pragma unroll
     for (int a = 0; a < 6; ++a) St.g[a] = g[a];
@@ -370,16 +450,12 @@ __device__ __forceinline__ void record_eval(PairDev &P, State &St, double f, con
 #pragma unroll
         for (int c = 0; c < 6; ++c) St.H[6 * r + c] = H[r][c];
     St.pairs_last = (long long)tot_pairs;
-    if (P.iter_pairs && St.iter < P.max_iters) P.iter_pairs[St.iter] = (long long)tot_pairs;
+    if (R.iter_pairs && R.iter < R.max_iters) R.iter_pairs[R.iter] = (long long)tot_pairs;
 }
 
-// T <- T exp(xi^), then the stage and stop logic.
-__device__ __forceinline__ void apply_step(PairDev &P, State &St, const double xi[6], int stage) {
-    double E[4][4], T[4][4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) T[r][c] = St.T[4 * r + c];
+// T <- T exp(xi^), then the stage and stop logic; returns the done flag.
+__device__ __forceinline__ int apply_step(const StepIn &R, State &St, const double xi[6]) {
+    double E[4][4];
     twist_exp(xi, E);
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -387,7 +463,7 @@ __device__ __forceinline__ void apply_step(PairDev &P, State &St, const double x
         for (int c = 0; c < 4; ++c) {
             double acc = 0.0;
 #pragma unroll
-            for (int b = 0; b < 4; ++b) acc += T[r][b] * E[b][c];
+            for (int b = 0; b < 4; ++b) acc += R.T[4 * r + b] * E[b][c];
             St.T[4 * r + c] = acc;
         }
     double l1 = 0.0;
@@ -397,20 +473,26 @@ __device__ __forceinline__ void apply_step(PairDev &P, State &St, const double x
         l1 += fabs(xi[a]);
     }
     St.xi_l1 = l1;
-    St.iter += 1;
-    St.stage_iter += 1;
-    St.stage_iters[stage] = St.stage_iter;
-    const bool final_stage = (stage + 1 >= P.n_stages);
+    const int stage = R.stage, iter = R.iter + 1, stage_iter = R.stage_iter + 1;
+    St.iter = iter;
+    St.stage_iters[stage] = stage_iter;
+    const bool final_stage = (stage + 1 >= R.n_stages);
+    int done = 0;
     if (final_stage) {
-        if (l1 < P.tol) {
+        if (l1 < R.tol) {
             St.converged = 1;
-            St.done = 1;
+            done = 1;
         }
-    } else if (l1 < P.stage_tol || St.stage_iter >= P.max_per_stage) {
+        St.stage_iter = stage_iter;
+    } else if (l1 < R.stage_tol || stage_iter >= R.max_per_stage) {
         St.stage = stage + 1;
         St.stage_iter = 0;
+    } else {
+        St.stage_iter = stage_iter;
     }
-    if (St.iter >= P.max_iters) St.done = 1;
+    if (iter >= R.max_iters) done = 1;
+    if (done) St.done = 1;
+    return done;
 }
 
 // Symmetric part of H negative definite: Cholesky of -(H + H^T)/2 with every
@@ -454,12 +536,12 @@ __device__ __forceinline__ bool negative_definite(const double H[6][6]) {
 // symmetric part is negative definite, the step is an ascent direction, and it
 // is at most twice as long as the Gauss-Newton step; far from a maximum, pure
 // Newton steps leave the basin.  The damped fallback always uses H_main.
-__device__ __forceinline__ void finish_iteration(PairDev &P, State &St, const double *tot,
-                                                 unsigned long long tot_pairs, int stage, bool exact) {
-    const double sig = P.sigma2;
+__device__ __forceinline__ int finish_iteration(const StepIn &R, State &St, const double *tot,
+                                                 unsigned long long tot_pairs, bool exact) {
+    const double sig = R.sigma2;
     double g[6], Hm[6][6], H[6][6];
-    frame_grad(P.centre, tot, sig, g);
-    frame_sym(P.centre, tot + 7, sig, Hm);
+    frame_grad(R.centre, tot, sig, g);
+    frame_sym(R.centre, tot + 7, sig, Hm);
     // H_GN = H_main + C(g), C(g) = [[-1/2 g_w^, 0], [-g_v^, 0]]
     {
         const double Gw[3][3] = {{0.0, -g[2], g[1]}, {g[2], 0.0, -g[0]}, {-g[1], g[0], 0.0}};
@@ -476,32 +558,32 @@ __device__ __forceinline__ void finish_iteration(PairDev &P, State &St, const do
                 H[3 + r][c] -= Gv[r][c];
             }
     }
-    record_eval(P, St, sig * tot[0], g, H, tot_pairs);
-    if (P.eval_only) {
+    record_eval(R, St, sig * tot[0], g, H, tot_pairs);
+    if (R.eval_only) {
         St.done = 1;
-        return;
+        return 1;
     }
     if (tot_pairs == 0) {
         St.status = GCVO_ERR_NO_PAIRS;
         St.done = 1;
-        return;
+        return 1;
     }
     double xi[6];
     const int dmp = damped_step(H, Hm, g, xi);
     if (dmp < 0) {
         St.status = GCVO_ERR_SINGULAR;
         St.done = 1;
-        return;
+        return 1;
     }
     bool used_exact = false;
     if (exact) {
         double HE[6][6];
         {
             double T1[6][6];
-            frame_sym(P.centre, tot + kNumSums, sig, T1);
+            frame_sym(R.centre, tot + kNumSums, sig, T1);
             const double *M = tot + kNumSums + 21;
             const double tr = M[0] + M[4] + M[8];
-            const double c0 = P.centre[0], c1 = P.centre[1], c2 = P.centre[2];
+            const double c0 = R.centre[0], c1 = R.centre[1], c2 = R.centre[2];
             const double K[3][3] = {{0.0, c2, -c1}, {-c2, 0.0, c0}, {c1, -c0, 0.0}};
             const double Q2[3][3] = {{0.0, -g[5], g[4]}, {g[5], 0.0, -g[3]}, {-g[4], g[3], 0.0}};   // (g_v)^
 #pragma unroll
@@ -518,10 +600,14 @@ __device__ __forceinline__ void finish_iteration(PairDev &P, State &St, const do
                 }
         }
         if (negative_definite(HE)) {
-            double b[6], xn[6];
+            double Me[6][7], xn[6];
 #pragma unroll
-            for (int a = 0; a < 6; ++a) b[a] = -g[a];
-            if (solve6(HE, b, xn, 1e-12)) {
+            for (int r = 0; r < 6; ++r) {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) Me[r][c] = HE[r][c];
+                Me[r][6] = -g[r];
+            }
+            if (solve6(Me, xn, 1e-12)) {
                 double gx = 0.0, nn = 0.0, ng = 0.0;
 #pragma unroll
                 for (int a = 0; a < 6; ++a) {
@@ -537,23 +623,23 @@ __device__ __forceinline__ void finish_iteration(PairDev &P, State &St, const do
             }
         }
     }
-    if (dmp > 0 || (exact && !used_exact)) ++St.damped;
-    apply_step(P, St, xi, stage);
+    if (dmp > 0 || (exact && !used_exact)) St.damped = R.damped + 1;
+    return apply_step(R, St, xi);
 }
 
 // First-order solver, gradient pass done: store the unit ascent direction and
 // hand over to the line pass (a zero gradient is a zero step).
-__device__ __forceinline__ void finish_direction(PairDev &P, State &St, const double *tot,
-                                                 unsigned long long tot_pairs, int stage) {
-    const double sig = P.sigma2;
+__device__ __forceinline__ int finish_direction(const StepIn &R, State &St, const double *tot,
+                                                 unsigned long long tot_pairs) {
+    const double sig = R.sigma2;
     double g[6], Hm[6][6];
-    frame_grad(P.centre, tot, sig, g);
-    frame_sym(P.centre, tot + 7, sig, Hm);
-    record_eval(P, St, sig * tot[0], g, Hm, tot_pairs);
+    frame_grad(R.centre, tot, sig, g);
+    frame_sym(R.centre, tot + 7, sig, Hm);
+    record_eval(R, St, sig * tot[0], g, Hm, tot_pairs);
     if (tot_pairs == 0) {
         St.status = GCVO_ERR_NO_PAIRS;
         St.done = 1;
-        return;
+        return 1;
     }
     double n2 = 0.0;
 #pragma unroll
@@ -561,13 +647,13 @@ __device__ __forceinline__ void finish_direction(PairDev &P, State &St, const do
     const double gn = sqrt(n2);
     if (!(gn > 0.0) || !isfinite(gn)) {
         const double zero[6] = {0, 0, 0, 0, 0, 0};
-        apply_step(P, St, zero, stage);
-        return;
+        return apply_step(R, St, zero);
     }
 #pragma unroll
     for (int a = 0; a < 6; ++a) St.dir[a] = g[a] / gn;
     St.gnorm = gn;
     St.phase = 1;
+    return 0;
 }
 
 // G'(s) = c1 + 2 c2 s + 3 c3 s^2 + 4 c4 s^3.
@@ -643,20 +729,20 @@ __device__ __forceinline__ int line_step(const double c[5], double &s) {
 }
 
 // First-order solver, line pass done: step mu * g with mu = max(min_step, s / |g|).
-__device__ __forceinline__ void finish_line(PairDev &P, State &St, const double *tot, int stage) {
+__device__ __forceinline__ int finish_line(const StepIn &R, State &St, const double *tot) {
     double c[5];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) c[k] = P.sigma2 * tot[k];
+    for (int k = 0; k < 5; ++k) c[k] = R.sigma2 * tot[k];
     double s;
     const int kind = line_step(c, s);
-    if (kind != 1) ++St.damped;
-    const double s_min = P.min_step * St.gnorm;
+    if (kind != 1) St.damped = R.damped + 1;
+    const double s_min = R.min_step * R.gnorm;
     if (!(s > s_min)) s = s_min;
     double xi[6];
 #pragma unroll
-    for (int a = 0; a < 6; ++a) xi[a] = s * St.dir[a];
+    for (int a = 0; a < 6; ++a) xi[a] = s * R.dir[a];
     St.phase = 0;
-    apply_step(P, St, xi, stage);
+    return apply_step(R, St, xi);
 }
 
 // Lane layout of the pair kernel: a wave serves kGroupsPerWave neighbouring
@@ -678,81 +764,134 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     const BlockTask task = tasks[blockIdx.x];
     PairDev &P = pairs[task.pair];
     State &St = P.st;
-    if (St.done || St.phase != (Mode == kModeLine ? 1 : 0)) return;
+    // Everything that does not depend on the stage goes out in one batch ahead
+    // of the done/phase test; the stage's fields and the source point follow
+    // in a second: two memory round trips instead of a chain of dependent ones.
+    int done = St.done;
+    const int phase = St.phase, stage = St.stage;
+    double Tm[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) Tm[i] = St.T[i];
+    const double c0 = P.centre[0], c1 = P.centre[1], c2 = P.centre[2];
+    const int ns = P.n_s;
+    typedef const __attribute__((address_space(1))) float *GFloat;
+    const GFloat src = (GFloat)P.s_sorted;
+    const double cutoff_scale = P.cutoff_scale;
+    void *const partials = P.partials;
+    const float4 *const slab = kLab ? P.s_lab : nullptr;
+    double dir[6] = {};
+    if constexpr (Mode == kModeLine) {
+#pragma unroll
+        for (int a = 0; a < 6; ++a) dir[a] = St.dir[a];
+    }
+    tie_s(done, phase);
+    tie_s(done, stage);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) tie_s(done, Tm[i]);
+    tie_s(done, c0);
+    tie_s(done, c1);
+    tie_s(done, c2);
+    tie_s(done, ns);
+    tie_s(done, src);
+    tie_s(done, cutoff_scale);
+    tie_s(done, partials);
+    if constexpr (kLab) tie_s(done, slab);
+    if constexpr (Mode == kModeLine) {
+#pragma unroll
+        for (int a = 0; a < 6; ++a) tie_s(done, dir[a]);
+    }
+    if ((done != 0) | (phase != (Mode == kModeLine ? 1 : 0))) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int grp = lane / kGroupLanes, q = lane % kGroupLanes;
-    const int stage = St.stage;
     const double ell = P.ell[stage];
     const Grid G = P.t_grid[stage];
-    const int *cells = P.t_cells[stage];
-    const int ns = P.n_s;
+    typedef const __attribute__((address_space(1))) int *GInt;
+    const GInt cells = (GInt)P.t_cells[stage];
     constexpr bool kExact = sizeof(Real) == 8;   // FP64: recentre the original coordinates in FP64
     // Target records through a global-address-space pointer: global (not
     // flat) loads, which do not wait on LDS traffic.
     const GRec4 trec = (GRec4)(P.t_sorted[stage]);
-    const double c0 = P.centre[0], c1 = P.centre[1], c2 = P.centre[2];
+    const double cc[3] = {c0, c1, c2};
 
     // Recentred pose T' = C^{-1} T C: R' = R, t' = R c + t - c.
     double Rd[9], td[3];
     for (int r = 0; r < 3; ++r) {
-        for (int k = 0; k < 3; ++k) Rd[3 * r + k] = St.T[4 * r + k];
-        td[r] = St.T[4 * r + 3] - P.centre[r];
-        for (int k = 0; k < 3; ++k) td[r] += Rd[3 * r + k] * P.centre[k];
+        for (int k = 0; k < 3; ++k) Rd[3 * r + k] = Tm[4 * r + k];
+        td[r] = Tm[4 * r + 3] - cc[r];
+        for (int k = 0; k < 3; ++k) td[r] += Rd[3 * r + k] * cc[k];
     }
 
     const int j = task.block * kPointsPerBlock + wave * kGroupsPerWave + grp;
     const bool valid = j < ns;
-    double y0 = 0.0, y1 = 0.0, y2 = 0.0;
-    Real p00 = 0, p01 = 0, p02 = 0, p11 = 0, p12 = 0, p22 = 0;
-    if (valid) {
-        const float *src = P.s_sorted;
+    // The source point is read on every lane (lanes past the end read point 0:
+    // a launched block's pair has at least one), so that its loads go out
+    // with the stage's fields instead of behind a branch; lanes past the end
+    // then take y = 0 and S' = 0 as before and walk no rows.
+    const int jc = valid ? j : 0;
+    float sv[9];   // coordinates (FP64 path: the original ones), then the 6 shape entries
+#pragma unroll
+    for (int a = 0; a < 3; ++a) sv[a] = src[(kExact ? 9 + a : a) * ns + jc];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) sv[3 + a] = src[(3 + a) * ns + jc];
+    // The stage's fields are read only later (the cell table and records
+    // inside the row loop); tying them and the source point to the lane's
+    // valid flag makes all these loads complete together.
+    int vkey = valid;
+    asm("" : "+v"(vkey)
+        : "v"(sv[0]), "v"(sv[1]), "v"(sv[2]), "v"(sv[3]), "v"(sv[4]), "v"(sv[5]), "v"(sv[6]), "v"(sv[7]),
+          "v"(sv[8]), "s"(cells), "s"(trec), "s"(ell), "s"(G.lo[0]), "s"(G.lo[1]), "s"(G.lo[2]), "s"(G.h),
+          "s"(G.inv_h), "s"(G.n[0]), "s"(G.n[1]), "s"(G.n[2]), "s"(G.inv_hx));
+    const bool lane_valid = vkey != 0;
+    double y0, y1, y2;
+    Real p00, p01, p02, p11, p12, p22;
+    {
         double zx, zy, zz;
         if (kExact) {
-            zx = ((double)src[9 * ns + j] - c0) - td[0];
-            zy = ((double)src[10 * ns + j] - c1) - td[1];
-            zz = ((double)src[11 * ns + j] - c2) - td[2];
+            zx = ((double)sv[0] - c0) - td[0];
+            zy = ((double)sv[1] - c1) - td[1];
+            zz = ((double)sv[2] - c2) - td[2];
         } else {
-            zx = (double)src[j] - td[0];
-            zy = (double)src[ns + j] - td[1];
-            zz = (double)src[2 * ns + j] - td[2];
+            zx = (double)sv[0] - td[0];
+            zy = (double)sv[1] - td[1];
+            zz = (double)sv[2] - td[2];
         }
         // y = R^T (z - t)
         y0 = Rd[0] * zx + Rd[3] * zy + Rd[6] * zz;
         y1 = Rd[1] * zx + Rd[4] * zy + Rd[7] * zz;
         y2 = Rd[2] * zx + Rd[5] * zy + Rd[8] * zz;
         // S' = R^T S R
-        const double S[3][3] = {{src[3 * ns + j], src[4 * ns + j], src[5 * ns + j]},
-                                {src[4 * ns + j], src[6 * ns + j], src[7 * ns + j]},
-                                {src[5 * ns + j], src[7 * ns + j], src[8 * ns + j]}};
+        const double S[3][3] = {{sv[3], sv[4], sv[5]}, {sv[4], sv[6], sv[7]}, {sv[5], sv[7], sv[8]}};
         double SR[3][3], Sp[3][3];
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) SR[a][b] = S[a][0] * Rd[b] + S[a][1] * Rd[3 + b] + S[a][2] * Rd[6 + b];
         for (int a = 0; a < 3; ++a)
             for (int b = a; b < 3; ++b) Sp[a][b] = Rd[a] * SR[0][b] + Rd[3 + a] * SR[1][b] + Rd[6 + a] * SR[2][b];
-        p00 = (Real)Sp[0][0]; p01 = (Real)Sp[0][1]; p02 = (Real)Sp[0][2];
-        p11 = (Real)Sp[1][1]; p12 = (Real)Sp[1][2]; p22 = (Real)Sp[2][2];
+        p00 = lane_valid ? (Real)Sp[0][0] : (Real)0; p01 = lane_valid ? (Real)Sp[0][1] : (Real)0;
+        p02 = lane_valid ? (Real)Sp[0][2] : (Real)0; p11 = lane_valid ? (Real)Sp[1][1] : (Real)0;
+        p12 = lane_valid ? (Real)Sp[1][2] : (Real)0; p22 = lane_valid ? (Real)Sp[2][2] : (Real)0;
+        if (!lane_valid) y0 = y1 = y2 = 0.0;
     }
     const Real yx = (Real)y0, yy = (Real)y1, yz = (Real)y2;
     // label vector of the source point (zero-padded to 4)
     vf4 lz = {0.0f, 0.0f, 0.0f, 0.0f};
     if constexpr (kLab) {
-        if (valid) {
-            const float4 l = P.s_lab[j];
+        if (lane_valid) {
+            const float4 l = slab[j];
             lz = vf4{l.x, l.y, l.z, l.w};
         }
     }
     typedef const vf4 __attribute__((address_space(1))) *GLab;
     const GLab tlab = kLab ? (GLab)(P.t_lab[stage]) : (GLab)nullptr;
-    const double rc = P.cutoff_scale * ell;
+    const double rc = cutoff_scale * ell;
     const Real rc2 = (Real)(rc * rc);
     const Real kexp = (Real)(-1.4426950408889634 / (ell * ell));   // f = exp2(q * inv_det * kexp)
     const Real k2 = (Real)(2.0 / (ell * ell));
     LineDir<Real> ld = {};
     if constexpr (Mode == kModeLine) {
         // Direction in the recentred frame: w' = w, v' = v - c x w.
-        const double w[3] = {St.dir[0], St.dir[1], St.dir[2]};
-        const double v[3] = {St.dir[3] - (c1 * w[2] - c2 * w[1]), St.dir[4] - (c2 * w[0] - c0 * w[2]),
-                             St.dir[5] - (c0 * w[1] - c1 * w[0])};
+        const double w[3] = {dir[0], dir[1], dir[2]};
+        const double v[3] = {dir[3] - (c1 * w[2] - c2 * w[1]), dir[4] - (c2 * w[0] - c0 * w[2]),
+                             dir[5] - (c0 * w[1] - c1 * w[0])};
         double e[3] = {w[1] * y2 - w[2] * y1 + v[0], w[2] * y0 - w[0] * y2 + v[1], w[0] * y1 - w[1] * y0 + v[2]};
         for (int k = 0; k < 4; ++k) {
             for (int a = 0; a < 3; ++a) ld.e[k][a] = (Real)e[a];
@@ -778,7 +917,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         const float xs = G.h * G.inv_hx, padx = 4e-7f * fabsf(gx);   // y-z units -> x units, x rounding
         const int y_lo = max(0, (int)floorf(gy - rh)), y_hi = min(G.n[1] - 1, (int)floorf(gy + rh));
         const int z_lo = max(0, (int)floorf(gz - rh)), z_hi = min(G.n[2] - 1, (int)floorf(gz + rh));
-        const int nyr = (valid && y_lo <= y_hi && z_lo <= z_hi) ? y_hi - y_lo + 1 : 0;
+        const int nyr = (lane_valid && y_lo <= y_hi && z_lo <= z_hi) ? y_hi - y_lo + 1 : 0;
         const int nrows = (nyr > 0) ? nyr * (z_hi - z_lo + 1) : 0;
         int (*rs_t)[kMaxRows] = sh_rs[wave];
         int (*rl_t)[kMaxRows] = sh_rl[wave];
@@ -875,19 +1014,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     if (q == 0) {
         Real v[NS];
         if constexpr (Mode == kModeLine) {
-            v[0] = valid ? s.F : (Real)0;
-            v[1] = valid ? s.L1 : (Real)0;
-            v[2] = valid ? s.L2 : (Real)0;
-            v[3] = valid ? s.L3 : (Real)0;
-            v[4] = valid ? s.L4 : (Real)0;
+            v[0] = lane_valid ? s.F : (Real)0;
+            v[1] = lane_valid ? s.L1 : (Real)0;
+            v[2] = lane_valid ? s.L2 : (Real)0;
+            v[3] = lane_valid ? s.L3 : (Real)0;
+            v[4] = lane_valid ? s.L4 : (Real)0;
         } else {
-            const Real kk = valid ? k2 : (Real)0;
+            const Real kk = lane_valid ? k2 : (Real)0;
             const Real a0 = kk * s.A0, a1 = kk * s.A1, a2 = kk * s.A2;
             const Real b00 = kk * s.B00;
             const Real b01 = (Mode == kModeIso) ? (Real)0 : kk * s.B01, b02 = (Mode == kModeIso) ? (Real)0 : kk * s.B02;
             const Real b11 = (Mode == kModeIso) ? b00 : kk * s.B11, b12 = (Mode == kModeIso) ? (Real)0 : kk * s.B12;
             const Real b22 = (Mode == kModeIso) ? b00 : kk * s.B22;
-            v[0] = valid ? s.F : (Real)0;
+            v[0] = lane_valid ? s.F : (Real)0;
             // g_w = -y x a, g_v = -a
             v[1] = -(yy * a2 - yz * a1);
             v[2] = -(yz * a0 - yx * a2);
@@ -934,7 +1073,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     cnt = wave_sum(cnt);
     if (lane == 0) sh_cnt[wave] = cnt;
     __syncthreads();
-    Real *part = reinterpret_cast<Real *>(P.partials) + (size_t)task.block * kPartialStride;
+    Real *part = reinterpret_cast<Real *>(partials) + (size_t)task.block * kPartialStride;
     if (tid < NS) {
         Real acc = 0;
         for (int pnt = 0; pnt < kPointsPerBlock; ++pnt) acc += sh_pts[pnt][tid];
@@ -953,6 +1092,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 // pair count) over every (1024 / W)-th of those blocks with a Kahan-compensated
 // sum in the pair-term precision, and the slices are added in FP64 in a fixed
 // order.  The step kernel adds the kReduceSplit results, again in fixed order.
+// The descriptor fields go out in one batch ahead of the done/phase test, and
+// each thread requests kAhead of its block partials at a time, so a pair of
+// up to kAhead * 512 pair-kernel blocks costs two memory round trips.
 constexpr int kReduceThreads = 1024;
 
 template <typename Real, int Mode>
@@ -961,28 +1103,54 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(PairDev *pairs) {
     constexpr int W = (NS + 1 <= 32) ? 32 : 64;
     constexpr int kSlices = kReduceThreads / W;
     constexpr int kCountAt = NS + (NS & 1) * (sizeof(Real) == 4);   // 8-byte aligned slot of the pair count
+    constexpr int kAhead = 4;
     PairDev &P = pairs[blockIdx.y];
     State &St = P.st;
-    if (St.done || St.phase != (Mode == kModeLine ? 1 : 0)) return;
+    typedef const __attribute__((address_space(1))) Real *GReal;
+    const GReal parts = (GReal)P.partials;
+    const int nb = P.n_blocks;
+    const int done = St.done, phase = St.phase;
+    pin_s(parts);
+    pin_s(nb);
+    if ((done != 0) | (phase != (Mode == kModeLine ? 1 : 0))) return;
     const int split = blockIdx.x;
     const int tid = threadIdx.x, ck = tid % W, slice = tid / W;
-    const Real *parts = reinterpret_cast<const Real *>(P.partials);
     __shared__ double sh[kSlices][W + 1];
     __shared__ unsigned long long sh_c[kSlices];
-    const int nb = P.n_blocks, step = kSlices * kReduceSplit;
+    const int step = kSlices * kReduceSplit;
     if (ck < NS) {
         Real sm = 0, cp = 0;
-        for (int b = split + kReduceSplit * slice; b < nb; b += step) {
-            const Real y = parts[(size_t)b * kPartialStride + ck] - cp;
-            const Real t = sm + y;
-            cp = (t - sm) - y;
-            sm = t;
+        for (int b0 = split + kReduceSplit * slice; b0 < nb; b0 += kAhead * step) {
+            Real y[kAhead];
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) {
+                const int b = b0 + u * step;
+                y[u] = b < nb ? parts[(size_t)b * kPartialStride + ck] : (Real)0;
+            }
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) {
+                if (b0 + u * step < nb) {
+                    const Real yy = y[u] - cp;
+                    const Real t = sm + yy;
+                    cp = (t - sm) - yy;
+                    sm = t;
+                }
+            }
         }
         sh[slice][ck] = (double)sm - (double)cp;
     } else if (ck == NS) {
         unsigned long long c = 0;
-        for (int b = split + kReduceSplit * slice; b < nb; b += step)
-            c += *reinterpret_cast<const unsigned long long *>(parts + (size_t)b * kPartialStride + kCountAt);
+        for (int b0 = split + kReduceSplit * slice; b0 < nb; b0 += kAhead * step) {
+            unsigned long long y[kAhead];
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) {
+                const int b = b0 + u * step;
+                typedef const __attribute__((address_space(1))) unsigned long long *GU64;
+                y[u] = b < nb ? *(GU64)(parts + (size_t)b * kPartialStride + kCountAt) : 0ull;
+            }
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) c += y[u];
+        }
         sh_c[slice] = c;
     }
     __syncthreads();
@@ -993,52 +1161,56 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(PairDev *pairs) {
     } else if (tid == NS) {
         unsigned long long c = 0;
         for (int sl = 0; sl < kSlices; ++sl) c += sh_c[sl];
-        St.sub_pairs[split] = c;
+        St.sub[split][NS] = (double)c;   // exact: counts stay below 2^53
     }
 }
 
 // The FP64 step of one pair, on one lane (its registers are not shared with
-// any wide kernel).  The wave first adds the reduction splits, one sum per
-// lane with all its loads in flight at once (same order as a single lane), so
-// the step starts after one memory round trip.  Step kinds: 0 Gauss-Newton,
-// 1 Newton, 2 first-order direction (after a gradient pass), 3 first-order line
-// step.  At the last pass of a chunk of iterations the host passes host_done
-// (pinned host memory, one int per pair), and every pair stores its done flag
-// there for the host to poll.
+// any wide kernel).  Every lane first requests its column of the reduction
+// splits (the sums, then the pair count in column NS), and the step's reads of
+// the descriptor and state go out with them, ahead of the done/phase test:
+// one memory round trip, after which the step reads only registers and LDS.
+// The splits are added in a fixed order, one column per lane.  Step kinds:
+// 0 Gauss-Newton, 1 Newton, 2 first-order direction (after a gradient pass),
+// 3 first-order line step.  At the last pass of a chunk of iterations the host
+// passes host_done (pinned host memory, one int per pair), and every pair
+// stores its done flag there for the host to poll.
 template <int Kind>
 __global__ __launch_bounds__(64) void k_step(PairDev *pairs, int *host_done) {
     constexpr int Mode = Kind == 1 ? kModeExact : Kind == 3 ? kModeLine : kModeGN;
     constexpr int NS = ModeInfo<Mode>::sums;
-    static_assert(NS < 64, "one sum per lane");
+    static_assert(NS < 64 && NS < kMaxSums, "one column per lane, the pair count after the sums");
     PairDev &P = pairs[blockIdx.x];
     State &St = P.st;
-    if (St.done || St.phase != (Mode == kModeLine ? 1 : 0)) {
-        if (host_done && threadIdx.x == 0) host_done[blockIdx.x] = St.done;
+    const int lane = threadIdx.x;
+    const int col = lane < NS ? lane : NS;
+    double v[kReduceSplit];
+#pragma unroll
+    for (int sp = 0; sp < kReduceSplit; ++sp) v[sp] = St.sub[sp][col];
+    const StepIn R = load_step_in(P);
+    const int done = St.done, phase = St.phase;
+    double acc = 0.0;
+#pragma unroll
+    for (int sp = 0; sp < kReduceSplit; ++sp) acc += v[sp];
+    pin_v(acc);
+    pin_step_in(R);
+    if ((done != 0) | (phase != (Mode == kModeLine ? 1 : 0))) {
+        if (host_done && lane == 0) host_done[blockIdx.x] = done;
         return;
     }
     __shared__ double sh_tot[NS + 1];
-    const int lane = threadIdx.x;
-    if (lane < NS) {
-        double acc = 0.0;
-#pragma unroll
-        for (int sp = 0; sp < kReduceSplit; ++sp) acc += St.sub[sp][lane];
-        sh_tot[lane] = acc;
-    } else if (lane == NS) {
-        unsigned long long c = 0;
-#pragma unroll
-        for (int sp = 0; sp < kReduceSplit; ++sp) c += St.sub_pairs[sp];
-        sh_tot[NS] = (double)c;
-    }
+    if (lane <= NS) sh_tot[lane] = acc;
     __syncthreads();
     if (lane != 0) return;
     double tot[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) tot[k] = sh_tot[k];
     const unsigned long long c = (unsigned long long)sh_tot[NS];
-    if constexpr (Kind == 0 || Kind == 1) finish_iteration(P, St, tot, c, St.stage, Kind == 1);
-    else if constexpr (Kind == 2) finish_direction(P, St, tot, c, St.stage);
-    else finish_line(P, St, tot, St.stage);
-    if (host_done) host_done[blockIdx.x] = St.done;
+    int now_done;
+    if constexpr (Kind == 0 || Kind == 1) now_done = finish_iteration(R, St, tot, c, Kind == 1);
+    else if constexpr (Kind == 2) now_done = finish_direction(R, St, tot, c);
+    else now_done = finish_line(R, St, tot);
+    if (host_done) host_done[blockIdx.x] = now_done;
 }
 
 template <typename Real, int Mode, int Kind, bool kLab>
