@@ -300,15 +300,19 @@ __global__ __launch_bounds__(256) void k_sort_up(SortJob *jobs, int shift, int p
 }
 
 __global__ __launch_bounds__(256) void k_sort_scan(SortJob *jobs) {
+    constexpr int kChunk = 16;   // tile counts in flight per thread
     const SortJob &J = jobs[blockIdx.x];
     const int ntile = (J.n + kSortTile - 1) / kSortTile;
     const int d = threadIdx.x, lane = d & 63, wave = d >> 6;
     unsigned *row = J.tile_counts + (size_t)d * ntile;
+    // total of digit d over the tiles (kChunk independent loads at a time)
     unsigned run = 0;
-    for (int t = 0; t < ntile; ++t) {   // exclusive prefix over tiles for digit d
-        const unsigned v = row[t];
-        row[t] = run;
-        run += v;
+    for (int t0 = 0; t0 < ntile; t0 += kChunk) {
+        unsigned v[kChunk];
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) v[u] = (t0 + u < ntile) ? row[t0 + u] : 0u;
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) run += v[u];
     }
     // exclusive scan of the 256 digit totals
     unsigned inc = run;
@@ -322,8 +326,18 @@ __global__ __launch_bounds__(256) void k_sort_scan(SortJob *jobs) {
     __syncthreads();
     unsigned before = 0;
     for (int w = 0; w < wave; ++w) before += wsum[w];
-    const unsigned digit_base = before + inc - run;
-    for (int t = 0; t < ntile; ++t) row[t] += digit_base;
+    // tile t of digit d starts at the digit's base plus the counts of tiles < t
+    unsigned acc = before + inc - run;
+    for (int t0 = 0; t0 < ntile; t0 += kChunk) {
+        unsigned v[kChunk];
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) v[u] = (t0 + u < ntile) ? row[t0 + u] : 0u;
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+            if (t0 + u < ntile) row[t0 + u] = acc;
+            acc += v[u];
+        }
+    }
 }
 
 __global__ __launch_bounds__(256) void k_sort_down(SortJob *jobs, int shift, int pass) {
