@@ -27,9 +27,9 @@ __global__ __launch_bounds__(1024) void k_stats(PairDev *pairs) {
     double s[3] = {0.0, 0.0, 0.0};
     float lo[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, hi[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
     int bad = 0;
-    // Four points' loads in flight per trip; they are added in the same order
+    // Eight points' loads in flight per trip; they are added in the same order
     // as one at a time.
-    constexpr int kAhead = 4;
+    constexpr int kAhead = 8;
     for (int i0 = tid; i0 < n; i0 += 1024 * kAhead) {
         float v[kAhead][3];
 #pragma unroll
@@ -468,8 +468,11 @@ __global__ __launch_bounds__(kBlock) void k_knn_pts(SortJob *jobs, const PairDev
 // index), and the 16 lists are merged by K rounds of a group minimum.  If fewer
 // than K points lie within r, r doubles and the point is scanned again; the
 // K-th merged distance never exceeds r, so no closer point was skipped.
+// Register budget of five waves per SIMD (96 VGPRs, no spills; 112 VGPRs and
+// four waves otherwise): 11 % shorter on a LiDAR cloud pair; six waves spill.
 template <int K>
-__global__ __launch_bounds__(kBlock) void k_knn(SortJob *jobs, const PairDev *pairs) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_knn(SortJob *jobs,
+                                                                                     const PairDev *pairs) {
     const SortJob &J = jobs[blockIdx.y];
     if (!J.want_shapes || pairs[J.pair].nonfinite) return;
     const int n = J.n;
