@@ -131,19 +131,36 @@ __device__ __forceinline__ int damped_step(const double H[6][6], const double Hm
         for (int a = 0; a < 6; ++a) xi[a] = 0.0;
         return 0;
     }
-    for (int m = -1; m <= 6; ++m) {
+    {   // plain H (its own copy of the solve, so that H's registers serve as
+        // the working matrix without a select between H and H_main)
         double A[6][7], x[6];
-        double shift = 0.0;
-        if (m >= 0) {
-            double dn = 0.0;
-#pragma unroll
-            for (int a = 0; a < 6; ++a) dn += Hm[a][a] * Hm[a][a];
-            shift = 1e-6 * exp10((double)m) * sqrt(dn);
-        }
 #pragma unroll
         for (int r = 0; r < 6; ++r) {
 #pragma unroll
-            for (int c = 0; c < 6; ++c) A[r][c] = (m < 0) ? H[r][c] : Hm[r][c];
+            for (int c = 0; c < 6; ++c) A[r][c] = H[r][c];
+            A[r][6] = -g[r];
+        }
+        if (solve6(A, x, 1e-12)) {
+            double gx = 0.0;
+#pragma unroll
+            for (int a = 0; a < 6; ++a) gx += g[a] * x[a];
+            if (gx > 0.0) {
+#pragma unroll
+                for (int a = 0; a < 6; ++a) xi[a] = x[a];
+                return 0;
+            }
+        }
+    }
+    double dn = 0.0;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) dn += Hm[a][a] * Hm[a][a];
+    for (int m = 0; m <= 6; ++m) {
+        double A[6][7], x[6];
+        const double shift = 1e-6 * exp10((double)m) * sqrt(dn);
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) A[r][c] = Hm[r][c];
             A[r][r] -= shift;
             A[r][6] = -g[r];
         }
