@@ -38,6 +38,8 @@
 #include <hip/hip_ext.h>
 #include <math.h>
 
+#include <type_traits>
+
 #include "gcvo_dev.h"
 
 namespace gcvo {
@@ -1121,55 +1123,55 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(PairDev *pairs) {
     constexpr int kSlices = kReduceThreads / W;
     constexpr int kCountAt = NS + (NS & 1) * (sizeof(Real) == 4);   // 8-byte aligned slot of the pair count
     constexpr int kAhead = 4;
+    // Rows are read as raw words of the pair-term width, so that the sums'
+    // lanes and the count's lanes (two 4-byte words in FP32 rows, one 8-byte
+    // word in FP64 rows) share one load sequence: one memory round trip per
+    // kAhead rows for every wave.
+    typedef typename std::conditional<sizeof(Real) == 8, unsigned long long, unsigned>::type Word;
+    constexpr int kCountWords = sizeof(Real) == 4 ? 2 : 1;
+    static_assert(kCountAt + kCountWords <= W, "the count's words have lanes of their own");
     PairDev &P = pairs[blockIdx.y];
     State &St = P.st;
-    typedef const __attribute__((address_space(1))) Real *GReal;
-    const GReal parts = (GReal)P.partials;
+    typedef const __attribute__((address_space(1))) Word *GWord;
+    const GWord words = (GWord)P.partials;
     const int nb = P.n_blocks;
     const int done = St.done, phase = St.phase;
-    pin_s(parts);
+    pin_s(words);
     pin_s(nb);
     if ((done != 0) | (phase != (Mode == kModeLine ? 1 : 0))) return;
     const int split = blockIdx.x;
     const int tid = threadIdx.x, ck = tid % W, slice = tid / W;
     __shared__ double sh[kSlices][W + 1];
-    __shared__ unsigned long long sh_c[kSlices];
+    __shared__ unsigned long long sh_c[kCountWords][kSlices];
     const int step = kSlices * kReduceSplit;
-    if (ck < NS) {
-        Real sm = 0, cp = 0;
+    const bool is_sum = ck < NS, is_cnt = ck >= kCountAt && ck < kCountAt + kCountWords;
+    Real sm = 0, cp = 0;
+    unsigned long long cacc = 0;
+    if (is_sum || is_cnt) {
         for (int b0 = split + kReduceSplit * slice; b0 < nb; b0 += kAhead * step) {
-            Real y[kAhead];
+            Word y[kAhead];
 #pragma unroll
             for (int u = 0; u < kAhead; ++u) {
                 const int b = b0 + u * step;
-                y[u] = b < nb ? parts[(size_t)b * kPartialStride + ck] : (Real)0;
+                y[u] = b < nb ? words[(size_t)b * kPartialStride + ck] : (Word)0;
             }
 #pragma unroll
             for (int u = 0; u < kAhead; ++u) {
                 if (b0 + u * step < nb) {
-                    const Real yy = y[u] - cp;
-                    const Real t = sm + yy;
-                    cp = (t - sm) - yy;
-                    sm = t;
+                    if (is_sum) {
+                        const Real yy = __builtin_bit_cast(Real, y[u]) - cp;
+                        const Real t = sm + yy;
+                        cp = (t - sm) - yy;
+                        sm = t;
+                    } else {
+                        cacc += y[u];
+                    }
                 }
             }
         }
-        sh[slice][ck] = (double)sm - (double)cp;
-    } else if (ck == NS) {
-        unsigned long long c = 0;
-        for (int b0 = split + kReduceSplit * slice; b0 < nb; b0 += kAhead * step) {
-            unsigned long long y[kAhead];
-#pragma unroll
-            for (int u = 0; u < kAhead; ++u) {
-                const int b = b0 + u * step;
-                typedef const __attribute__((address_space(1))) unsigned long long *GU64;
-                y[u] = b < nb ? *(GU64)(parts + (size_t)b * kPartialStride + kCountAt) : 0ull;
-            }
-#pragma unroll
-            for (int u = 0; u < kAhead; ++u) c += y[u];
-        }
-        sh_c[slice] = c;
     }
+    if (is_sum) sh[slice][ck] = (double)sm - (double)cp;
+    else if (is_cnt) sh_c[ck - kCountAt][slice] = cacc;
     __syncthreads();
     if (tid < NS) {
         double acc = 0.0;
@@ -1177,7 +1179,10 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(PairDev *pairs) {
         St.sub[split][tid] = acc;
     } else if (tid == NS) {
         unsigned long long c = 0;
-        for (int sl = 0; sl < kSlices; ++sl) c += sh_c[sl];
+        for (int sl = 0; sl < kSlices; ++sl) {
+            c += sh_c[0][sl];
+            if constexpr (kCountWords == 2) c += sh_c[1][sl] << 32;   // high words of the FP32 rows' counts
+        }
         St.sub[split][NS] = (double)c;   // exact: counts stay below 2^53
     }
 }
