@@ -261,6 +261,161 @@ int orc_point_shapes(const double *P, long n, int k, double rho, double *S6) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Pair search: which target points are within the cutoff of a source point. */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * The sums below visit, for each transformed source point y, every target
+ * point i with ||x_i - y||^2 <= cutoff^2, in increasing i.  Two ways of finding
+ * them give the same index lists:
+ *   - brute force: test every i (the definition);
+ *   - grid: a uniform grid over X with cells of edge >= cutoff, so every point
+ *     within the cutoff of y lies in one of the 27 cells around y's cell; the
+ *     same distance test is applied to their points and the accepted indices
+ *     are sorted ascending.
+ * The grid is used when nx * nz reaches orc_set_grid_threshold's value
+ * (default 25e6, i.e. above two 5000-point clouds) and there is a cutoff.
+ */
+static long long g_grid_min_pairs = 25000000LL;
+
+void orc_set_grid_threshold(long long min_pairs) { g_grid_min_pairs = min_pairs; }
+
+typedef struct {
+    int on;
+    double lo[3], inv_h;
+    long n[3];
+    long *start; /* [ncells + 1]: cell c holds idx[start[c] .. start[c + 1]) */
+    long *idx;   /* point indices grouped by cell, ascending within a cell     */
+} pair_search;
+
+static long clampl(long v, long lo, long hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+static long grid_cell(const pair_search *S, const double p[3], int d) {
+    return (long)floor((p[d] - S->lo[d]) * S->inv_h);
+}
+
+static void search_free(pair_search *S);
+
+/* Sets up the grid when it is to be used; without memory for it the search
+ * stays brute force (the same index lists). */
+static void search_init(pair_search *S, const double *X, long nx, long nz, double cutoff) {
+    memset(S, 0, sizeof *S);
+    if (!(cutoff > 0.0) || nx == 0 || (long long)nx * (long long)nz < g_grid_min_pairs) return;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (long i = 0; i < nx; ++i)
+        for (int d = 0; d < 3; ++d) {
+            if (X[3 * i + d] < lo[d]) lo[d] = X[3 * i + d];
+            if (X[3 * i + d] > hi[d]) hi[d] = X[3 * i + d];
+        }
+    /* Edge slightly above the cutoff (so rounding of the cell coordinates
+     * cannot put a point within the cutoff two cells away), doubled until the
+     * grid has at most 8 cells per point. */
+    double h = cutoff * (1.0 + 1e-9);
+    long n[3];
+    for (;;) {
+        double cells = 1.0;
+        for (int d = 0; d < 3; ++d) {
+            n[d] = (long)floor((hi[d] - lo[d]) / h) + 1;
+            cells *= (double)n[d];
+        }
+        if (cells <= 8.0 * (double)nx + 1024.0) break;
+        h *= 2.0;
+    }
+    S->on = 1;
+    for (int d = 0; d < 3; ++d) {
+        S->lo[d] = lo[d];
+        S->n[d] = n[d];
+    }
+    S->inv_h = 1.0 / h;
+    const long ncells = n[0] * n[1] * n[2];
+    S->start = (long *)calloc((size_t)ncells + 1, sizeof(long));
+    S->idx = (long *)malloc(sizeof(long) * (size_t)nx);
+    long *cell = (long *)malloc(sizeof(long) * (size_t)nx);
+    if (!S->start || !S->idx || !cell) {
+        free(cell);
+        search_free(S);
+        return;
+    }
+    for (long i = 0; i < nx; ++i) {
+        long c[3];
+        for (int d = 0; d < 3; ++d) c[d] = clampl(grid_cell(S, X + 3 * i, d), 0, n[d] - 1);
+        cell[i] = c[0] + n[0] * (c[1] + n[1] * c[2]);
+        S->start[cell[i] + 1] += 1;
+    }
+    for (long c = 0; c < ncells; ++c) S->start[c + 1] += S->start[c];
+    long *fill = (long *)malloc(sizeof(long) * (size_t)ncells);
+    if (!fill) {
+        free(cell);
+        search_free(S);
+        return;
+    }
+    memcpy(fill, S->start, sizeof(long) * (size_t)ncells);
+    for (long i = 0; i < nx; ++i) S->idx[fill[cell[i]]++] = i;   /* ascending i within each cell */
+    free(fill);
+    free(cell);
+}
+
+static void search_free(pair_search *S) {
+    free(S->start);
+    free(S->idx);
+    memset(S, 0, sizeof *S);
+}
+
+static int cmp_long(const void *a, const void *b) {
+    const long x = *(const long *)a, y = *(const long *)b;
+    return (x > y) - (x < y);
+}
+
+/* Indices i with ||x_i - y||^2 <= rc2, ascending, into *buf (grown as needed;
+ * the caller frees it).  Returns the count, or -1 on allocation failure. */
+static long pairs_of(const pair_search *S, const double *X, long nx, const double y[3], double rc2, long **buf,
+                     long *cap) {
+    long m = 0;
+#define ORC_PUSH(ii)                                                              \
+    do {                                                                          \
+        if (m == *cap) {                                                          \
+            long nc = *cap ? 2 * *cap : 256;                                      \
+            long *nb = (long *)realloc(*buf, sizeof(long) * (size_t)nc);          \
+            if (!nb) return -1;                                                   \
+            *buf = nb;                                                            \
+            *cap = nc;                                                            \
+        }                                                                         \
+        (*buf)[m++] = (ii);                                                       \
+    } while (0)
+    if (!S->on) {
+        for (long i = 0; i < nx; ++i) {
+            double r3[3] = {X[3 * i] - y[0], X[3 * i + 1] - y[1], X[3 * i + 2] - y[2]};
+            double d2 = r3[0] * r3[0] + r3[1] * r3[1] + r3[2] * r3[2];
+            if (d2 <= rc2) ORC_PUSH(i);
+        }
+        return m;
+    }
+    long c[3], lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+        const double u = (y[d] - S->lo[d]) * S->inv_h;
+        if (!(u > -2.0 && u < (double)S->n[d] + 1.0)) return 0;   /* no cell within reach (or NaN) */
+        c[d] = (long)floor(u);
+        lo[d] = clampl(c[d] - 1, 0, S->n[d] - 1);
+        hi[d] = clampl(c[d] + 1, 0, S->n[d] - 1);
+        if (c[d] + 1 < 0 || c[d] - 1 > S->n[d] - 1) return 0;
+    }
+    for (long cz = lo[2]; cz <= hi[2]; ++cz)
+        for (long cy = lo[1]; cy <= hi[1]; ++cy)
+            for (long cx = lo[0]; cx <= hi[0]; ++cx) {
+                const long cell = cx + S->n[0] * (cy + S->n[1] * cz);
+                for (long a = S->start[cell]; a < S->start[cell + 1]; ++a) {
+                    const long i = S->idx[a];
+                    double r3[3] = {X[3 * i] - y[0], X[3 * i + 1] - y[1], X[3 * i + 2] - y[2]};
+                    double d2 = r3[0] * r3[0] + r3[1] * r3[1] + r3[2] * r3[2];
+                    if (d2 <= rc2) ORC_PUSH(i);
+                }
+            }
+#undef ORC_PUSH
+    if (m > 1) qsort(*buf, (size_t)m, sizeof(long), cmp_long);
+    return m;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Objective, gradient and Hessians at a pose (literal double sum).         */
 /* ------------------------------------------------------------------------ */
 
@@ -331,8 +486,14 @@ int orc_eval_l(const double *X, const double *SX, const double *LX, long nx, con
     transpose(Rs, Rst, 3, 3);
     const double half_l2 = 0.5 * ell * ell;
     const double rc2 = (cutoff > 0.0) ? cutoff * cutoff : INFINITY;
+    pair_search search;
+    search_init(&search, X, nx, nz, cutoff);
+    int failed = 0;
 
-#pragma omp parallel for schedule(dynamic, 16)
+#pragma omp parallel
+    {
+    long *pairs = NULL, cap = 0;
+#pragma omp for schedule(dynamic, 16)
     for (long j = 0; j < nz; ++j) {
         double *acc = slot + (size_t)j * stride;
         double zt[3] = {Z[3 * j] - t[0], Z[3 * j + 1] - t[1], Z[3 * j + 2] - t[2]};
@@ -350,10 +511,15 @@ int orc_eval_l(const double *X, const double *SX, const double *LX, long nx, con
                 J[r * 6 + 3 + c] = (r == c) ? 1.0 : 0.0;
             }
         transpose(J, Jt, 3, 6);
-        for (long i = 0; i < nx; ++i) {
+        const long m = pairs_of(&search, X, nx, y, rc2, &pairs, &cap);
+        if (m < 0) {
+#pragma omp atomic write
+            failed = 1;
+            continue;
+        }
+        for (long a = 0; a < m; ++a) {
+            const long i = pairs[a];
             double r3[3] = {X[3 * i] - y[0], X[3 * i + 1] - y[1], X[3 * i + 2] - y[2]};
-            double d2 = r3[0] * r3[0] + r3[1] * r3[1] + r3[2] * r3[2];
-            if (!(d2 <= rc2)) continue;
             double Si[9], Sig[9], Sinv[9];
             shape6_to_mat(SX + 6 * i, Si);
             for (int a = 0; a < 9; ++a) Sig[a] = half_l2 * (Si[a] + SjR[a]);
@@ -381,6 +547,10 @@ int orc_eval_l(const double *X, const double *SX, const double *LX, long nx, con
             pcount[j] += 1;
         }
     }
+    free(pairs);
+    }
+    search_free(&search);
+    if (failed) { free(slot); free(pcount); return ORC_ERR_INVALID; }
 
     double f = 0.0, g[6] = {0}, H[36] = {0}, T1[36] = {0}, T2[36] = {0};
     long long np = 0;
@@ -507,8 +677,14 @@ int orc_line_coeffs_l(const double *X, const double *SX, const double *LX, long 
     const double rc2 = (cutoff > 0.0) ? cutoff * cutoff : INFINITY;
     double W[9];
     hat3(xi, W);
+    pair_search search;
+    search_init(&search, X, nx, nz, cutoff);
+    int failed = 0;
 
-#pragma omp parallel for schedule(dynamic, 16)
+#pragma omp parallel
+    {
+    long *pairs = NULL, cap = 0;
+#pragma omp for schedule(dynamic, 16)
     for (long j = 0; j < nz; ++j) {
         double *acc = slot + (size_t)j * 5;
         double zt[3] = {Z[3 * j] - t[0], Z[3 * j + 1] - t[1], Z[3 * j + 2] - t[2]};
@@ -522,10 +698,15 @@ int orc_line_coeffs_l(const double *X, const double *SX, const double *LX, long 
         matmul(W, y, e[1], 3, 3, 1);
         for (int a = 0; a < 3; ++a) e[1][a] += xi[3 + a];
         for (int k = 2; k <= 4; ++k) matmul(W, e[k - 1], e[k], 3, 3, 1);
-        for (long i = 0; i < nx; ++i) {
+        const long m = pairs_of(&search, X, nx, y, rc2, &pairs, &cap);
+        if (m < 0) {
+#pragma omp atomic write
+            failed = 1;
+            continue;
+        }
+        for (long a = 0; a < m; ++a) {
+            const long i = pairs[a];
             double r3[3] = {X[3 * i] - y[0], X[3 * i + 1] - y[1], X[3 * i + 2] - y[2]};
-            double d2 = r3[0] * r3[0] + r3[1] * r3[1] + r3[2] * r3[2];
-            if (!(d2 <= rc2)) continue;
             double Si[9], Sig[9], P[9];
             shape6_to_mat(SX + 6 * i, Si);
             for (int a = 0; a < 9; ++a) Sig[a] = half_l2 * (Si[a] + SjR[a]);
@@ -564,6 +745,10 @@ int orc_line_coeffs_l(const double *X, const double *SX, const double *LX, long 
             pcount[j] += 1;
         }
     }
+    free(pairs);
+    }
+    search_free(&search);
+    if (failed) { free(slot); free(pcount); return ORC_ERR_INVALID; }
     double c[5] = {0};
     long long np = 0;
     for (long j = 0; j < nz; ++j) {

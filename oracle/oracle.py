@@ -27,13 +27,21 @@ _llp = ctypes.POINTER(ctypes.c_longlong)
 _ip = ctypes.POINTER(ctypes.c_int)
 
 
+CFLAGS = ["-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+
+
+def compile_to(src: str, out: str, extra=()) -> str:
+    """gcc build of an oracle source file into the shared library ``out``."""
+    tmp = out + ".tmp"
+    subprocess.check_call(["gcc", *CFLAGS, *extra, "-o", tmp, src, "-lm"])
+    os.replace(tmp, out)
+    return out
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (FP contraction off, OpenMP on)."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
-                               "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
-        os.replace(tmp, LIB)
+        compile_to(SRC, LIB)
     return LIB
 
 
@@ -45,35 +53,43 @@ def lib() -> ctypes.CDLL:
     if _lib is None:
         if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
             build(force=True)
-        L = ctypes.CDLL(LIB)
-        L.orc_knn.argtypes = [_dp, ctypes.c_long, ctypes.c_int, _lp]
-        L.orc_point_shapes.argtypes = [_dp, ctypes.c_long, ctypes.c_int, ctypes.c_double, _dp]
-        L.orc_eval.argtypes = [_dp, _dp, ctypes.c_long, _dp, _dp, ctypes.c_long, _dp, _dp,
-                               ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                               _dp, _dp, _dp, _dp, _dp, _llp]
-        L.orc_connection.argtypes = [_dp, _dp]
-        L.orc_connection.restype = None
-        L.orc_se3_exp.argtypes = [_dp, _dp]
-        L.orc_se3_exp.restype = None
-        L.orc_solve_step.argtypes = [_dp, _dp, _dp, _dp, _ip]
-        L.orc_register.argtypes = [_dp, _dp, ctypes.c_long, _dp, _dp, ctypes.c_long, _dp,
-                                   ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                   ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
-                                   ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
-                                   ctypes.c_double, _dp, _dp]
-        L.orc_line_coeffs.argtypes = [_dp, _dp, ctypes.c_long, _dp, _dp, ctypes.c_long, _dp, ctypes.c_double,
-                                      ctypes.c_double, ctypes.c_double, _dp, _dp, _llp]
-        L.orc_first_order_step.argtypes = [_dp, ctypes.c_double, _dp]
-        L.orc_eval_l.argtypes = [_dp, _dp, _dp, ctypes.c_long, _dp, _dp, _dp, ctypes.c_long, ctypes.c_int, _dp, _dp,
-                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, _dp, _dp, _dp, _dp, _llp]
-        L.orc_register_l.argtypes = [_dp, _dp, _dp, ctypes.c_long, _dp, _dp, _dp, ctypes.c_long, ctypes.c_int, _dp,
-                                     ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                     ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
-                                     ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
-                                     ctypes.c_double, _dp, _dp]
-        L.orc_num_threads.argtypes = []
-        _lib = L
+        _lib = load(LIB)
     return _lib
+
+
+def load(path: str) -> ctypes.CDLL:
+    """Open an oracle build at ``path`` with the argument types declared (the
+    tests also open builds of deliberately altered copies of the source)."""
+    L = ctypes.CDLL(path)
+    L.orc_knn.argtypes = [_dp, ctypes.c_long, ctypes.c_int, _lp]
+    L.orc_point_shapes.argtypes = [_dp, ctypes.c_long, ctypes.c_int, ctypes.c_double, _dp]
+    L.orc_eval.argtypes = [_dp, _dp, ctypes.c_long, _dp, _dp, ctypes.c_long, _dp, _dp,
+                           ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                           _dp, _dp, _dp, _dp, _dp, _llp]
+    L.orc_connection.argtypes = [_dp, _dp]
+    L.orc_connection.restype = None
+    L.orc_se3_exp.argtypes = [_dp, _dp]
+    L.orc_se3_exp.restype = None
+    L.orc_solve_step.argtypes = [_dp, _dp, _dp, _dp, _ip]
+    L.orc_register.argtypes = [_dp, _dp, ctypes.c_long, _dp, _dp, ctypes.c_long, _dp,
+                               ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                               ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                               ctypes.c_double, _dp, _dp]
+    L.orc_line_coeffs.argtypes = [_dp, _dp, ctypes.c_long, _dp, _dp, ctypes.c_long, _dp, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_double, _dp, _dp, _llp]
+    L.orc_first_order_step.argtypes = [_dp, ctypes.c_double, _dp]
+    L.orc_eval_l.argtypes = [_dp, _dp, _dp, ctypes.c_long, _dp, _dp, _dp, ctypes.c_long, ctypes.c_int, _dp, _dp,
+                             ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, _dp, _dp, _dp, _dp, _llp]
+    L.orc_register_l.argtypes = [_dp, _dp, _dp, ctypes.c_long, _dp, _dp, _dp, ctypes.c_long, ctypes.c_int, _dp,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                 ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                 ctypes.c_double, _dp, _dp]
+    L.orc_num_threads.argtypes = []
+    L.orc_set_grid_threshold.argtypes = [ctypes.c_longlong]
+    L.orc_set_grid_threshold.restype = None
+    return L
 
 
 def _d(a) -> np.ndarray:
@@ -94,6 +110,16 @@ class OracleError(RuntimeError):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+GRID_DEFAULT_MIN_PAIRS = 25_000_000
+
+
+def set_grid_threshold(min_pairs: int) -> None:
+    """Pair search of the sums: a uniform grid when nx * nz >= min_pairs (and
+    there is a cutoff), else brute force.  Both give the same index lists, so
+    the same results bit for bit; 0 forces the grid, a huge value brute force."""
+    lib().orc_set_grid_threshold(int(min_pairs))
 
 
 def knn(P, k: int) -> np.ndarray:

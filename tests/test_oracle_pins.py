@@ -396,3 +396,148 @@ def test_config1_registers_close_to_truth():
     r = O.register_spec(spec)
     assert r.converged and r.iters <= 30
     assert rot_err_deg(r.T, spec.T_true) < 0.2 and trans_err_m(r.T, spec.T_true) < 0.01
+
+
+# --------------------------------------------------------------------------- annealing schedule
+#
+# The schedule is a reading of the scale-decay passage after Remark 1 (the
+# covariance scale is decayed whenever the objective converges at the current
+# scale) around Algorithm 1's loop: ell_0 = length_scale, ell_{s+1} =
+# max(alpha ell_s, ell_min); a non-final stage ends at ||xi||_1 < stage_tol or
+# after max_iters_per_stage iterations, the final stage at ||xi||_1 < tol, and
+# max_iters caps the total.  The pins compare an annealed run with a chain of
+# fixed-scale runs over a hand-written scale list, each started where the
+# previous one stopped; the stage rules then fix the result bit for bit.
+
+def _schedule_problem():
+    rng = np.random.default_rng(21)
+    Z = small_surface(rng, 160, 0.01)
+    G0 = random_pose(rng, 0.2, 0.2)
+    X = synth.transform_points(G0, small_surface(rng, 170, 0.01))
+    return X, Z, O.point_shapes(X, 10, 0.05), O.point_shapes(Z, 10, 0.05)
+
+
+def _fixed_chain(X, Z, SX, SZ, ells, per_stage, stage_tol, tol, max_total):
+    """Stages as separate fixed-scale runs: a non-final stage is a run with
+    tol = stage_tol and at most per_stage iterations, the final one a run to
+    tol; together at most max_total iterations."""
+    T, used, stage_iters, r = np.eye(4), 0, [], None
+    for s, ell in enumerate(ells):
+        final = s == len(ells) - 1
+        cap = max_total - used if final else min(per_stage, max_total - used)
+        r = O.register(X, Z, T, SX=SX, SZ=SZ, length_scale=ell, eig_ratio_min=0.05, max_iters=cap,
+                       tol=tol if final else stage_tol)
+        T, used = r.T, used + r.iters
+        stage_iters.append(r.iters)
+        if used >= max_total:
+            break
+    return T, stage_iters, r
+
+
+def _pin_schedule_matches_fixed_chain():
+    X, Z, SX, SZ = _schedule_problem()
+    # 0.8 -> 0.4 -> 0.2 -> 0.1 would undershoot ell_min = 0.15: the last stage is clamped to it
+    ells = [0.8, 0.4, 0.2, 0.15]
+    kw = dict(per_stage=6, stage_tol=3e-3, tol=1e-9, max_total=200)
+    a = O.register(X, Z, SX=SX, SZ=SZ, length_scale=0.8, length_scale_min=0.15, anneal_factor=0.5,
+                   eig_ratio_min=0.05, max_iters=kw["max_total"], max_iters_per_stage=kw["per_stage"],
+                   tol=kw["tol"], stage_tol=kw["stage_tol"])
+    T, stage_iters, last = _fixed_chain(X, Z, SX, SZ, ells, **kw)
+    # the problem exercises both ways a stage can end
+    assert kw["per_stage"] in stage_iters[:-1], stage_iters
+    assert any(s < kw["per_stage"] for s in stage_iters[:-1]), stage_iters
+    assert a.converged and last.converged
+    assert a.stages == len(ells) and a.stage_iters == stage_iters, (a.stage_iters, stage_iters)
+    assert a.iters == sum(stage_iters)
+    assert np.array_equal(a.T, T)
+    assert a.f == last.f and np.array_equal(a.g, last.g)
+
+
+def _pin_schedule_one_iteration_stages():
+    """A stage tolerance no step can reach ends every non-final stage after one
+    iteration (1, 0.5, 0.25, 0.125 then the clamped final 0.1)."""
+    X, Z, SX, SZ = _schedule_problem()
+    a = O.register(X, Z, SX=SX, SZ=SZ, length_scale=1.0, length_scale_min=0.1, anneal_factor=0.5,
+                   eig_ratio_min=0.05, max_iters=200, max_iters_per_stage=30, tol=1e-9, stage_tol=1e300)
+    assert a.converged and a.stages == 5
+    assert a.stage_iters[:4] == [1, 1, 1, 1] and a.stage_iters[4] == a.iters - 4
+    T, stage_iters, _ = _fixed_chain(X, Z, SX, SZ, [1.0, 0.5, 0.25, 0.125, 0.1], per_stage=1,
+                                     stage_tol=1e300, tol=1e-9, max_total=200)
+    assert stage_iters == a.stage_iters and np.array_equal(a.T, T)
+
+
+def _pin_schedule_total_cap():
+    """max_iters counts every stage: 4 + 2 iterations, stopped in stage 2."""
+    X, Z, SX, SZ = _schedule_problem()
+    a = O.register(X, Z, SX=SX, SZ=SZ, length_scale=0.8, length_scale_min=0.15, anneal_factor=0.5,
+                   eig_ratio_min=0.05, max_iters=6, max_iters_per_stage=4, tol=1e-9, stage_tol=1e-12)
+    assert not a.converged and a.iters == 6 and a.stages == 2 and a.stage_iters == [4, 2]
+    T, stage_iters, _ = _fixed_chain(X, Z, SX, SZ, [0.8, 0.4, 0.2, 0.15], per_stage=4, stage_tol=1e-12,
+                                     tol=1e-9, max_total=6)
+    assert stage_iters == [4, 2] and np.array_equal(a.T, T)
+
+
+SCHEDULE_PINS = [_pin_schedule_matches_fixed_chain, _pin_schedule_one_iteration_stages, _pin_schedule_total_cap]
+
+
+@pytest.mark.parametrize("pin", SCHEDULE_PINS, ids=lambda f: f.__name__[5:])
+def test_annealing_schedule(pin):
+    pin()
+
+
+# Plausible slips in the oracle's stage logic; each must fail at least one pin.
+SCHEDULE_MUTATIONS = {
+    "non_final_stage_ends_on_tol": ("xi_l1 < stage_tol", "xi_l1 < tol"),
+    "no_clamp_to_ell_min": ("if (cur_ell < ell_min) cur_ell = ell_min;", ""),
+    "stage_cap_off_by_one": ("stage_it >= max_iters_per_stage", "stage_it > max_iters_per_stage"),
+    "final_stage_test_inclusive": ("const int final_stage = !(cur_ell > ell_min);",
+                                   "const int final_stage = !(cur_ell >= ell_min);"),
+    "stage_counter_not_reset": ("            ++stage;\n            stage_it = 0;", "            ++stage;"),
+    "decay_squared": ("cur_ell = alpha * cur_ell;", "cur_ell = alpha * alpha * cur_ell;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SCHEDULE_MUTATIONS))
+def test_annealing_pins_catch_mutated_oracle(name, tmp_path, monkeypatch):
+    old, new = SCHEDULE_MUTATIONS[name]
+    src = open(O.SRC).read()
+    assert src.count(old) == 1, "the mutation no longer applies to the oracle source"
+    mutant = tmp_path / "mutant.c"
+    mutant.write_text(src.replace(old, new))
+    monkeypatch.setattr(O, "_lib", O.load(O.compile_to(str(mutant), str(tmp_path / "mutant.so"))))
+    failed = []
+    for pin in SCHEDULE_PINS:
+        try:
+            pin()
+        except AssertionError:
+            failed.append(pin.__name__)
+    assert failed, f"mutation {name} passes every schedule pin"
+
+
+# --------------------------------------------------------------------------- pair search
+
+@pytest.mark.parametrize("where", ["overlapping", "source_outside_target_box"])
+def test_grid_search_equals_brute_force(where):
+    """The grid pair search returns the brute-force index lists, so every sum
+    is the same number (bitwise), pair count included."""
+    spec = synth.make_config1(1)
+    X, Z = spec.target.astype(np.float64), spec.source.astype(np.float64)
+    SX, SZ = O.point_shapes(X, 10, 0.01), O.point_shapes(Z, 10, 0.01)
+    T = np.eye(4)
+    T[:3, 3] = [0.05, -0.02, 0.03] if where == "overlapping" else [3.5, 0.0, 0.0]
+    xi = np.array([0.01, 0.02, -0.01, 0.03, 0.0, 0.01])
+    out = {}
+    try:
+        for mode, thr in (("brute", 1 << 62), ("grid", 0)):
+            O.set_grid_threshold(thr)
+            e = O.evaluate(X, SX, Z, SZ, T, 0.3, 0.9, with_t=True)
+            c, n = O.line_coeffs(X, SX, Z, SZ, T, xi, 0.3, 0.9)
+            r = O.register(X, Z, T, SX=SX, SZ=SZ, length_scale=0.3, eig_ratio_min=0.01, max_iters=5)
+            out[mode] = (e, c, n, r)
+    finally:
+        O.set_grid_threshold(O.GRID_DEFAULT_MIN_PAIRS)
+    (a, ca, na, ra), (b, cb, nb, rb) = out["brute"], out["grid"]
+    assert a.npairs == b.npairs == na == nb and a.npairs > 1000
+    assert a.f == b.f and np.array_equal(a.g, b.g) and np.array_equal(a.Hmain, b.Hmain)
+    assert np.array_equal(a.T1, b.T1) and np.array_equal(a.T2, b.T2) and np.array_equal(ca, cb)
+    assert np.array_equal(ra.T, rb.T) and ra.iters == rb.iters
