@@ -2,9 +2,10 @@
 
 A step is one complete registration of a synthetic LiDAR frame pair (64-ring x
 1024-azimuth scan of a ground plane with 40 boxes and 30 cylinders, voxelised
-at 0.3 m, second scan after 1 m forward and 2 deg yaw; length scale annealed
-1.0 -> 0.1 m): per-point covariance shapes of both clouds, cell lists for every
-stage, and all Gauss-Newton iterations to convergence.  Inputs are resident in
+at 0.3 m to about 30k points per cloud, second scan after 1 m forward and 2
+deg yaw; length scale annealed 1.0 -> 0.1 m): per-point covariance shapes of
+both clouds, cell lists for every stage, and all Gauss-Newton iterations to
+convergence.  Inputs are resident in
 device memory before the timed region; poses are on the host when it ends.
 
 value = registrations/s counting only registrations whose pose lies within
@@ -12,8 +13,10 @@ value = registrations/s counting only registrations whose pose lies within
 
 roofline: the pair kernel k_iterate (transform, pair terms, per-point finish,
 block partial sums), FP32 VALU bound.  A second pass over the same steps
-brackets every launch of that kernel with HIP events on the stream it runs on;
-algorithmic FLOP = 76 per pair within the cutoff + 230 per source point.
+brackets every launch of that kernel with HIP events on the stream it runs on
+(a gcvo_profile given with the calls); algorithmic FLOP = 76 per pair within
+the cutoff + 230 per source point.  The first stage alone is reported beside
+it (config.first_stage_roofline).
 traffic: HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE
 counter summary in profiles/ (null once the kernel sources or the cell shape
 differ from the ones it was taken with).
@@ -23,12 +26,14 @@ Before the timed steps, the pair-grid cell shape is autotuned on the same pairs
 fastest is used.  Further legs (reported under config): the same pairs registered together by one
 batch call; the RGB-D precision pair with FP32 and FP64 kernels; the
 exact-Hessian solver; the LiDAR pairs with an intensity label per point and
-with the isotropic kernel; the learned warm start on held-out large-motion pairs
-against the plain single-pair path; optionally (--objects) the 256 object
-pairs in one batch call.
+with the isotropic kernel; the learned warm start on 128 held-out large-motion
+pairs against the plain single-pair path, gated against the oracle's fixed
+points; the 256 object pairs in one batch call, with its own roofline.
 
-cpu_baseline: the FP64 oracle, as it stands, registering one of the same pairs
-on the host's cores.
+cpu_baseline: the FP64 oracle, as it stands, on the host's cores: one
+evaluation per length-scale stage of one of the same pairs, median of five
+runs with all cores and one single-threaded, scaled to a registration by the
+oracle's own iteration counts.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -101,9 +106,22 @@ def precision_leg(gcvo, synth, golden, dev, rot_err_deg, trans_err_m, reps=2):
     return out
 
 
+def roofline(prof):
+    """Algorithmic FP32 rate of the pair kernel from a gcvo_profile dict."""
+    kernel_s = prof["pair_kernel_ms"] / 1e3
+    flop = FLOP_PER_PAIR * prof["pairs"] + FLOP_PER_SOURCE_POINT * prof["source_points"]
+    achieved = flop / kernel_s / 1e12 if kernel_s > 0 else 0.0
+    return {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP32_VALU_PEAK_TFLOPS, "kernel": "k_iterate<float>",
+            "avg_launch_us": 1e6 * kernel_s / max(prof["launches"], 1), "launches": prof["launches"],
+            "pairs_per_launch": prof["pairs"] / max(prof["launches"], 1),
+            "kernel_pairs_per_s": prof["pairs"] / kernel_s if kernel_s > 0 else 0.0}
+
+
 def objects_leg(gcvo, synth, golden, dev, rot_err_deg, trans_err_m, n_pairs=256):
-    """The 256 object pairs (1k-50k points each) registered by one batch call;
-    pairs of the oracle-checked sample are gated, the rest reported as converged."""
+    """The 256 object pairs (1k-50k points each) registered by one batch call:
+    pairs with a stored oracle fixed point are gated, the rest reported as
+    converged; the batch is then repeated with the pair kernel measured."""
     import torch
     t0 = time.perf_counter()
     specs = [synth.make_config4(i) for i in range(n_pairs)]
@@ -121,21 +139,91 @@ def objects_leg(gcvo, synth, golden, dev, rot_err_deg, trans_err_m, n_pairs=256)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     converged = sum(1 for i in infos if i["converged"])
-    sample, in_gate = 0, 0
+    sample, in_gate, sizes = 0, 0, []
     for k, s in enumerate(specs):
         g = golden.get(s.name)
-        if g is None or not (g["prod_converged"] and g["ref_converged"]):
+        if g is None or g.get("digest") != s.digest() or not (g["prod_converged"] and g["ref_converged"]):
             continue
         sample += 1
+        sizes.append(len(s.source))
         Tref = np.array(g["T_ref"]).reshape(4, 4)
         if infos[k]["converged"] and rot_err_deg(T[k], Tref) <= 1e-3 and trans_err_m(T[k], Tref) <= 1e-5:
             in_gate += 1
-    out = {"pairs": n_pairs, "seconds_per_batch": dt, "converged": converged,
-           "registrations_per_s_converged": converged / dt, "oracle_sample": sample, "oracle_sample_in_gate": in_gate,
-           "mean_iterations": float(np.mean([i["iters"] for i in infos]))}
+    prof = gcvo.gcvo_profile()
+    gcvo.gcvo_register_batch(tgt, to, src, so, None, gcvo.profiled(params, prof), ws=ws)
+    rl = roofline(prof.to_dict())
+    out = {"workload": f"object_pairs_{n_pairs}_1k_to_50k_points", "pairs": n_pairs,
+           "source_points": int(so[-1]), "seconds_per_batch": dt, "converged": converged,
+           "registrations_per_s_converged": converged / dt, "oracle_sample": sample,
+           "oracle_sample_in_gate": in_gate, "oracle_sample_sizes": sizes,
+           "mean_iterations": float(np.mean([i["iters"] for i in infos])),
+           "iterations_at_cap": sum(1 for i in infos if not i["converged"]), "roofline": rl}
     print(f"[bench] objects: {dt:.2f} s for {n_pairs} pairs, {converged} converged, oracle sample "
-          f"{in_gate}/{sample} in gate", file=sys.stderr, flush=True)
+          f"{in_gate}/{sample} in gate; pair kernel {rl['avg_launch_us']:.1f} us/launch, frac {rl['frac']:.4f}",
+          file=sys.stderr, flush=True)
     return out
+
+
+def cpu_baseline(spec, golden_entry, n_runs=5):
+    """The FP64 oracle as it stands, on the host: one evaluation of f, g and H
+    per length-scale stage of a LiDAR pair at its fixed point, each timed as the
+    median of n_runs with all cores and once with one thread (a subprocess with
+    OMP_NUM_THREADS=1).  A registration's time is estimated as the sum over its
+    stages of (the oracle's own iteration count in that stage) x (that stage's
+    evaluation time); the step and exponential cost microseconds."""
+    import subprocess
+    from oracle import oracle as O
+    X, Z = spec.target.astype(np.float64), spec.source.astype(np.float64)
+    T = np.array(golden_entry["T_ref"]).reshape(4, 4)
+    stage_iters = golden_entry["prod_stage_iters"]
+    ells, ell = [], spec.length_scale
+    while True:
+        ells.append(ell)
+        if not ell > spec.length_scale_min:
+            break
+        ell = max(spec.anneal_factor * ell, spec.length_scale_min)
+    SX = O.point_shapes(X, spec.knn, spec.eig_ratio_min)
+    SZ = O.point_shapes(Z, spec.knn, spec.eig_ratio_min)
+    med, pairs = [], []
+    for ell in ells:
+        ts = []
+        for _ in range(n_runs):
+            t0 = time.perf_counter()
+            e = O.evaluate(X, SX, Z, SZ, T, ell, spec.cutoff_scale * ell)
+            ts.append(time.perf_counter() - t0)
+        med.append(float(np.median(ts)))
+        pairs.append(e.npairs)
+    reg_s = sum(n * t for n, t in zip(stage_iters, med))
+    pairs_total = sum(n * p for n, p in zip(stage_iters, pairs))
+    code = ("import sys, time, json, numpy as np; sys.path.insert(0, %r)\n"
+            "from oracle import oracle as O\nfrom paper_2606_10019_amd import synth\n"
+            "s = synth.make_config2(%d); X, Z = s.target.astype(np.float64), s.source.astype(np.float64)\n"
+            "T = np.array(%r).reshape(4, 4); SX = O.point_shapes(X, s.knn, s.eig_ratio_min); "
+            "SZ = O.point_shapes(Z, s.knn, s.eig_ratio_min)\nout = []\n"
+            "for ell in %r:\n    t0 = time.perf_counter(); O.evaluate(X, SX, Z, SZ, T, ell, 3 * ell); "
+            "out.append(time.perf_counter() - t0)\nprint(json.dumps([O.num_threads(), out]))\n"
+            % (ROOT, golden_entry["instance"], golden_entry["T_ref"], ells))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    one = json.loads(subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                                    check=True).stdout.strip().splitlines()[-1])
+    reg_1 = sum(n * t for n, t in zip(stage_iters, one[1]))
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": 1.0 / reg_s, "unit": "registrations/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": (f"FP64 oracle evaluation of f, g, H at each of the {len(ells)} length-scale stages of LiDAR "
+                       f"pair {spec.name} ({len(X)}/{len(Z)} points) at its fixed point, median of {n_runs} runs "
+                       f"on all cores; registration time = sum over stages of the oracle's iterations there "
+                       f"({stage_iters}) x the stage's evaluation time"),
+            "stage_eval_s_median": med, "stage_pairs": pairs, "pairs_per_s": pairs_total / reg_s,
+            "single_thread": {"registrations_per_s": 1.0 / reg_1, "stage_eval_s": one[1], "cores": one[0]},
+            "nproc": len(os.sched_getaffinity(0)), "cpu_model": model,
+            "note": "correctness reference timed as it stands, not a tuned CPU implementation"}
 
 
 def _make_c5_eval(i):
@@ -143,12 +231,12 @@ def _make_c5_eval(i):
     return synth.make_config5(i, "eval")
 
 
-def warmstart_leg(gcvo, synth, dev, rot_err_deg, trans_err_m, n_pairs=64, workers=16):
-    """Held-out large-motion LiDAR pairs (yaw up to 15 deg, up to 3 m): the plain
-    single-pair path from identity, the plain batch from identity, and the
-    batched warm start (network prediction, refine, objective fallback), each
-    counted at 1e-3 deg / 1e-5 m of plain G-CVO's fixed point from the true
-    motion."""
+def warmstart_leg(gcvo, synth, golden, dev, rot_err_deg, trans_err_m, n_pairs=128, workers=16):
+    """Held-out large-motion LiDAR pairs (yaw up to 15 deg, up to 3 m, about
+    30k points per cloud), one batch of n_pairs: the plain single-pair path
+    from identity, the plain batch from identity, and the batched warm start
+    (network prediction, refine, objective fallback), each counted at 1e-3 deg
+    / 1e-5 m of the FP64 oracle's fixed point reached from the true motion."""
     import multiprocessing as mp
     from concurrent.futures import ProcessPoolExecutor
 
@@ -159,16 +247,19 @@ def warmstart_leg(gcvo, synth, dev, rot_err_deg, trans_err_m, n_pairs=64, worker
         specs = list(ex.map(_make_c5_eval, range(n_pairs), chunksize=2))
     print(f"[bench] warm start: generated {n_pairs} pairs in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
           flush=True)
+    refs = []
+    for s in specs:
+        g = golden.get(s.name)
+        assert g is not None and g["digest"] == s.digest(), f"no oracle reference for {s.name}"
+        refs.append((np.array(g["T_ref"]).reshape(4, 4), bool(g["ref_converged"])))
+    keep = [k for k in range(n_pairs) if refs[k][1]]
     ps = warmstart.PairSet.from_specs(specs, dev)
     params = [gcvo.params_from_spec(s) for s in specs]
-    refs, rinfo = gcvo.gcvo_register_batch(ps.targets, ps.tgt_off, ps.sources, ps.src_off,
-                                           np.array([s.T_true for s in specs]), params)
-    keep = [k for k in range(n_pairs) if rinfo[k]["converged"]]
     net = warmstart.Network.load(device=dev)
 
     def in_gate(T, infos):
-        return sum(1 for k in keep if infos[k]["converged"] and rot_err_deg(T[k], refs[k]) <= 1e-3
-                   and trans_err_m(T[k], refs[k]) <= 1e-5)
+        return sum(1 for k in keep if infos[k]["converged"] and rot_err_deg(T[k], refs[k][0]) <= 1e-3
+                   and trans_err_m(T[k], refs[k][0]) <= 1e-5)
 
     clouds = [(ps.targets[ps.tgt_off[k]:ps.tgt_off[k + 1]], ps.sources[ps.src_off[k]:ps.src_off[k + 1]])
               for k in range(n_pairs)]
@@ -189,10 +280,12 @@ def warmstart_leg(gcvo, synth, dev, rot_err_deg, trans_err_m, n_pairs=64, worker
     n_batch = in_gate(Tb, ib)
     t0 = time.perf_counter()
     Tw, iw, rec = warmstart.register_warm(net, ps, params)
-    torch.cuda.synchronize()
+    Tw = Tw.cpu().numpy()
     t_warm = time.perf_counter() - t0
     n_warm = in_gate(Tw, iw)
-    out = {"workload": f"lidar_pair_large_motion_15deg_3m_{n_pairs}pairs", "pairs_with_reference": len(keep),
+    out = {"workload": f"lidar_pair_large_motion_15deg_3m_{n_pairs}pairs",
+           "points_per_cloud": int(np.mean([len(s.target) for s in specs])),
+           "pairs_with_oracle_reference": len(keep), "reference": "FP64 oracle fixed point from the true motion",
            "plain_single": {"in_gate": n_single, "seconds": t_single, "registrations_per_s": n_single / t_single},
            "plain_batched": {"in_gate": n_batch, "seconds": t_batch, "registrations_per_s": n_batch / t_batch},
            "warm_batched": {"in_gate": n_warm, "seconds": t_warm, "registrations_per_s": n_warm / t_warm,
@@ -289,8 +382,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="use the default pair-grid cell shape (no autotuning)")
     ap.add_argument("--cell-fraction", type=float, nargs=2, metavar=("YZ", "X"), default=None,
                     help="use this pair-grid cell shape (fractions of the cutoff) instead of autotuning")
-    ap.add_argument("--objects", action="store_true",
-                    help="add the 256 object-pair batch leg (one gcvo_register_batch call)")
+    ap.add_argument("--no-objects", action="store_true",
+                    help="skip the 256 object-pair batch leg (one gcvo_register_batch call)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -408,36 +501,34 @@ def main():
                                                       trans_err_m)
     variants = None if args.no_variants else variants_leg(gcvo, synth, golden, specs, clouds, rot_err_deg,
                                                           trans_err_m, dev, cell_fraction)
-    warm = None if args.no_warmstart else warmstart_leg(gcvo, synth, dev, rot_err_deg, trans_err_m)
-    objects = objects_leg(gcvo, synth, golden, dev, rot_err_deg, trans_err_m) if args.objects else None
+    warm = None if args.no_warmstart else warmstart_leg(gcvo, synth, golden, dev, rot_err_deg, trans_err_m)
+    objects = None if args.no_objects else objects_leg(gcvo, synth, golden, dev, rot_err_deg, trans_err_m)
 
-    # Roofline pass: the same steps with every pair-kernel launch bracketed by events.
-    gcvo.gcvo_profile_reset()
-    gcvo.gcvo_profile_enable(True)
+    # Roofline pass: the same steps with every pair-kernel launch bracketed by
+    # HIP events on the stream it runs on (a per-call measurement).
+    prof = gcvo.gcvo_profile()
+    pparams = gcvo.profiled(params, prof)
     for k in range(args.steps):
-        step(k)
+        i = k % N_INSTANCES
+        gcvo.gcvo_register(clouds[i][0], clouds[i][1], None, pparams[i], ws=ws)
     torch.cuda.synchronize()
-    gcvo.gcvo_profile_enable(False)
-    prof = gcvo.gcvo_profile_read()
-    kernel_s = prof["pair_kernel_ms"] / 1e3
-    flop = FLOP_PER_PAIR * prof["pairs"] + FLOP_PER_SOURCE_POINT * prof["source_points"]
-    achieved = flop / kernel_s / 1e12 if kernel_s > 0 else 0.0
-    avg_launch_us = 1e6 * kernel_s / max(prof["launches"], 1)
-    pairs_per_s = prof["pairs"] / kernel_s if kernel_s > 0 else 0.0
-    print(f"[bench] pair kernel: {prof['launches']} launches, avg {avg_launch_us:.1f} us, "
-          f"{prof['pairs'] / max(prof['launches'], 1):.3g} pairs/launch, {pairs_per_s:.3g} pairs/s",
-          file=sys.stderr, flush=True)
+    rl = roofline(prof.to_dict())
+    # The first stage alone (ell = 1 m, the most pairs per point): ten iterations
+    # of each pair at that fixed length scale.
+    prof1 = gcvo.gcvo_profile()
+    for i in range(N_INSTANCES):
+        p1 = gcvo.params_from_spec(specs[i], length_scale_min=specs[i].length_scale, max_iters=10,
+                                   cell_fraction=cell_fraction[0], cell_fraction_x=cell_fraction[1])
+        gcvo.gcvo_register(clouds[i][0], clouds[i][1], None, gcvo.profiled(p1, prof1), ws=ws)
+    rl1 = roofline(prof1.to_dict())
+    print(f"[bench] pair kernel: {rl['launches']} launches, avg {rl['avg_launch_us']:.1f} us, "
+          f"{rl['pairs_per_launch']:.3g} pairs/launch, {rl['kernel_pairs_per_s']:.3g} pairs/s, frac {rl['frac']:.4f};"
+          f" first stage {rl1['avg_launch_us']:.1f} us, frac {rl1['frac']:.4f}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
-        from oracle import oracle as O
-        s = specs[0]
-        tc = time.perf_counter()
-        r = O.register_spec(s)
-        dtc = time.perf_counter() - tc
-        cpu = {"value": 1.0 / dtc, "unit": "registrations/s", "cores": O.num_threads(), "kind": "oracle",
-               "sample": f"one full FP64 oracle registration of LiDAR pair {s.name} "
-                         f"({len(s.target)}/{len(s.source)} points, {r.iters} iterations, {dtc:.1f} s)"}
+        cpu = cpu_baseline(specs[0], golden[specs[0].name])
+        print(f"[bench] cpu baseline: {json.dumps(cpu)}", file=sys.stderr, flush=True)
 
     ms_per_step = 1e3 * elapsed / args.steps
     out = {
@@ -453,20 +544,18 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "lidar_pair_64x1024_voxel0.3_anneal1.0to0.1",
+        "config": {"workload": "lidar_pair_64x1024_voxel0.3_30k_anneal1.0to0.1",
                    "points_per_cloud": int(np.mean([len(s.target) for s in specs])),
                    "instances": N_INSTANCES, "registrations_total": args.steps,
                    "cell_fraction": cell_fraction, "cell_fraction_tuning_ms": tune or None,
                    "registrations_in_gate": passed, "mean_iterations": float(np.mean(iters)),
-                   "kernel_pairs_per_s": pairs_per_s,
-                   "pct_fp32_valu_peak": 100.0 * achieved / FP32_VALU_PEAK_TFLOPS,
+                   "kernel_pairs_per_s": rl["kernel_pairs_per_s"],
+                   "pct_fp32_valu_peak": 100.0 * rl["frac"],
+                   "first_stage_roofline": rl1,
                    "batched": batch, "precision": precision, "solvers": solvers, "variants": variants,
                    "warmstart": warm,
                    "objects": objects},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": measured_traffic(cell_fraction),
-                     "kernel": "k_iterate<float>", "avg_launch_us": avg_launch_us,
-                     "launches": prof["launches"]},
+        "roofline": {**rl, "traffic": measured_traffic(cell_fraction)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

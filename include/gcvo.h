@@ -43,15 +43,17 @@
  * caller-provided DEVICE workspace of at least the size the matching
  * *_workspace_size function returns, aligned to 256 bytes; the library never
  * allocates device memory in these calls and never frees caller memory.
- * Pinned host memory for completion flags (two ints per pair of a call, which
- * the device writes) is allocated per calling thread on its first call and
- * again, twice as large, when a batch outgrows it; a thread keeps those
- * buffers until the process ends.
+ * The one piece of state the library keeps across calls is a per-device pool
+ * of small pinned host buffers (two ints per pair of a call) in which the
+ * device reports completion to the polling host; a buffer returns to the pool
+ * when the stream has passed the last work that writes it, and the pool is
+ * guarded by a mutex, so calls from several threads are safe.
  *
  * Streams.  `stream` is a hipStream_t (NULL = the default stream).  All device
- * work is enqueued on it.  gcvo_register, gcvo_eval_fgh and the info/T outputs
- * of gcvo_register_batch are complete when the call returns (the call waits on
- * the stream); gcvo_point_shapes returns without waiting.
+ * work is enqueued on it.  gcvo_register and gcvo_eval_fgh are complete when
+ * the call returns (the call waits on the stream); gcvo_register_batch writes
+ * its device outputs on the stream after it returns, and gcvo_point_shapes
+ * returns without waiting.
  *
  * Errors.  Every function returns 0 (GCVO_OK) or a negative GCVO_ERR_* code;
  * no exception or abort crosses the ABI.  On error, pose outputs are left
@@ -112,6 +114,19 @@ extern "C" {
 #define GCVO_MAX_POINTS (1LL << 26) /* per cloud */
 #define GCVO_MAX_LABEL_DIM 4        /* entries of a label vector (the *_labeled calls) */
 
+/* Pair-kernel measurement of one call (caller-owned, zero it first; calls
+ * that are given one add to it): over the launches of the per-iteration pair
+ * kernel in which at least one pair was still iterating, their summed duration
+ * (HIP events attached to each dispatch, on the caller's stream), their
+ * number, the (target, source) pairs evaluated within the cutoff and the
+ * source points processed.  A measured call waits on its stream. */
+typedef struct gcvo_profile {
+    double pair_kernel_ms;
+    long long launches;
+    long long pairs;
+    long long source_points;
+} gcvo_profile;
+
 typedef struct gcvo_params {
     double length_scale;      /* ell of the first stage, metres (> 0)                                   */
     double length_scale_min;  /* ell of the final stage (0 < min <= length_scale); == length_scale: fixed */
@@ -137,6 +152,8 @@ typedef struct gcvo_params {
                                  additions; smaller x cells clip each row closer to the cutoff ball
                                  without adding rows, smaller y-z cells add rows (see the autotuner
                                  of the Python binding).                                                */
+    gcvo_profile *profile;    /* optional measurement of the call (NULL: none); a batch call uses the
+                                 first parameter set's                                                   */
 } gcvo_params;
 
 typedef struct gcvo_info {
@@ -149,11 +166,14 @@ typedef struct gcvo_info {
     double g[6];             /* gradient (omega, v) at the last evaluated pose              */
     double xi_l1;            /* ||xi||_1 of the last step                                   */
     int stage_iters[GCVO_MAX_STAGES]; /* iterations spent in each stage                     */
+    int damped;              /* steps not taken with the plain system: damped Gauss-Newton steps
+                                (Newton: also the steps taken with the Gauss-Newton system;
+                                first order: steps not at a root of the line-search quartic) */
 } gcvo_info;
 
 /* Fills p with the defaults named above (ell = 0.3 fixed, cutoff 3, knn 10,
  * rho 0.01, sigma2 1, 30 iterations, tol 1e-6, stage_tol 1e-4, FP32, Gauss-Newton,
- * cell fractions 0.5 across and 0.125 along the rows). */
+ * cell fractions 0.5 across and 0.125 along the rows, no profile). */
 void gcvo_default_params(gcvo_params *p);
 
 /* Bytes of device workspace gcvo_register needs for clouds of these sizes and
@@ -178,16 +198,31 @@ size_t gcvo_batch_workspace_size(int n_pairs, const long long *tgt_off, const lo
                                  const gcvo_params *p, int shared_params);
 
 /*
- * Registers n_pairs independent pairs in one pass over the device.  Pair k's
- * target is tgt_xyz[tgt_off[k] .. tgt_off[k+1]) and its source
- * src_xyz[src_off[k] .. src_off[k+1]) (device float32 [*][3]); the offsets are
- * HOST int64 arrays of n_pairs + 1 entries.  T_init: host [n_pairs][16] or NULL
- * (identity).  p: host array of n_pairs parameter sets, or one set shared by all
- * pairs when shared_params != 0; all pairs must use the same knn, precision and solver.
- * T_out: host [n_pairs][16]; info: host [n_pairs] or NULL.  A pair that fails (for example with no pairs in reach)
- * reports its own status in info[k].status and keeps T_out[k] = T_init[k]; the
- * call returns the first failing pair's code only for argument errors, HIP
- * errors and workspace errors.  Waits on `stream`.
+ * Registers n_pairs independent pairs in one pass over the device (Algorithm 1
+ * for every pair, as gcvo_register does for one).  Pair k's target is
+ * tgt_xyz[tgt_off[k] .. tgt_off[k+1]) and its source src_xyz[src_off[k] ..
+ * src_off[k+1]) (device float32 [*][3]).
+ *   tgt_off, src_off  HOST int64 [n_pairs + 1]: the host lays the workspace out
+ *                     from the pair sizes, which the caller knows (taking them
+ *                     from device memory would stall the stream on every call).
+ *   T_init            DEVICE double [n_pairs][16] row-major start poses, or NULL
+ *                     (identity).  A start pose that is not a rigid motion within
+ *                     1e-6 fails its pair with GCVO_ERR_INVALID.
+ *   p                 HOST: n_pairs parameter sets, or one set shared by all pairs
+ *                     when shared_params != 0; all pairs must use the same knn,
+ *                     precision and solver.
+ *   T_out             DEVICE double [n_pairs][16]: the poses.
+ *   info              DEVICE gcvo_info [n_pairs] or NULL: the run summaries.
+ * A pair that fails (too few points, no pair in reach, a bad start pose, ...)
+ * reports its status in info[k].status and gets T_out[k] = its start pose; the
+ * call itself returns an error only for argument, workspace and HIP errors.
+ * Asynchronous outputs: the call returns once every pair has stopped iterating
+ * (the device reports completion through pinned host flags that the host
+ * polls, so no iteration beyond the last useful chunk is enqueued); T_out and
+ * info are then written by a kernel enqueued on `stream`, so they are ready
+ * once the stream has reached it (synchronise the stream, or order later work
+ * on it).  Until then the workspace, T_init, T_out and info must stay valid.
+ * Two calls that share a workspace must not overlap on the device.
  */
 int gcvo_register_batch(int n_pairs, const float *tgt_xyz, const long long *tgt_off, const float *src_xyz,
                         const long long *src_off, const double *T_init, const gcvo_params *p,
@@ -260,23 +295,41 @@ int gcvo_point_shapes(const float *xyz, long long n, int knn, double rho, float 
                       void *workspace, size_t workspace_bytes, void *stream);
 
 /*
- * Measurement of the per-iteration pair kernel (process-wide counters, meant
- * for benchmarks; calls that run while profiling is enabled must not overlap).
- * When enabled, gcvo_register and gcvo_register_batch bracket every launch of
- * the pair kernel with HIP events on the caller's stream and accumulate, over
- * the launches in which at least one pair was still iterating: the summed
- * kernel time (ms), the number of such launches, the number of (target,
- * source) pairs evaluated within the cutoff, and the number of source points
- * processed.  gcvo_profile_read copies the counters out (any pointer may be NULL).
+ * Shapes of n_clouds clouds in one pass (gcvo_point_shapes for each): cloud k
+ * is xyz[off[k] .. off[k+1]) (device float32 [*][3]; off HOST int64
+ * [n_clouds + 1]), and its shapes go to shape6_out + 6 * off[k] as device
+ * float32 [6][n_k] (the single-cloud layout, cloud after cloud).  Every cloud
+ * needs at least knn points.  Does not wait on `stream`.
  */
-void gcvo_profile_enable(int on);
-void gcvo_profile_reset(void);
-void gcvo_profile_read(double *pair_kernel_ms, long long *launches, long long *pairs, long long *source_points);
+size_t gcvo_shapes_batch_workspace_size(int n_clouds, const long long *off);
+int gcvo_point_shapes_batch(int n_clouds, const float *xyz, const long long *off, int knn, double rho,
+                            float *shape6_out, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * n_pairs evaluations (gcvo_eval_fgh for each) in one pass.  Pair k's clouds
+ * are rows tgt_off[k] .. tgt_off[k+1] and src_off[k] .. src_off[k+1] of
+ * tgt_xyz / src_xyz (device float32 [*][3]; offsets HOST int64 [n_pairs + 1]),
+ * their shapes at tgt_shape6 + 6 * tgt_off[k] and src_shape6 + 6 * src_off[k]
+ * (device float32 [6][n_k] each, the layout of gcvo_point_shapes_batch).
+ * T: DEVICE double [n_pairs][16] poses, or NULL (identity); length_scale: HOST
+ * double [n_pairs]; the cutoff of pair k is cutoff_scale * length_scale[k].
+ * Outputs, DEVICE, each may be NULL: f [n_pairs], g [n_pairs][6], H [n_pairs][36]
+ * (H_GN incl. the connection term, as gcvo_eval_fgh), n_pairs_out [n_pairs],
+ * status [n_pairs] (GCVO_ERR_INVALID for a pose that is not a rigid motion,
+ * whose sums are then 0).  A pair with an empty cloud has zero sums.  Written
+ * on `stream` after the call returns.
+ */
+size_t gcvo_eval_batch_workspace_size(int n_pairs, const long long *tgt_off, const long long *src_off);
+int gcvo_eval_fgh_batch(int n_pairs, const float *tgt_xyz, const float *tgt_shape6, const long long *tgt_off,
+                        const float *src_xyz, const float *src_shape6, const long long *src_off, const double *T,
+                        const double *length_scale, double cutoff_scale, double sigma2, int precision, double *f,
+                        double *g, double *H, long long *n_pairs_out, int *status, void *workspace,
+                        size_t workspace_bytes, void *stream);
 
 /* Static text for a status code. */
 const char *gcvo_strerror(int status);
 
-/* ABI version of this header (major * 100 + minor). */
+/* ABI version of this header (major * 100 + minor): 200. */
 int gcvo_abi_version(void);
 
 #ifdef __cplusplus

@@ -43,8 +43,8 @@
  * the index list) attaining the maximum; relu'(0) = 0.
  *
  * Memory, streams, errors and determinism follow gcvo.h: device work is
- * enqueued on `stream`; gcvo_mlp_forward waits for the stream only when it
- * returns poses to the host; the other calls return without waiting.  An index
+ * enqueued on `stream`; the calls return without waiting, except for the index
+ * check below.  An index
  * outside its cloud makes the call return GCVO_ERR_INVALID (the kernels read row
  * 0 of that cloud instead, so nothing is read out of bounds); that check waits
  * for the stream.  Sums over points, pairs and clouds run in a fixed order
@@ -92,8 +92,9 @@ long long gcvo_mlp_param_count(void);
 size_t gcvo_mlp_workspace_size(int n_pairs, int n_points);
 
 /* Forward pass.  out6: device float32 [B][6] (the normalised twists), required.
- * T_out: host double [B][16], or NULL; when given, the predicted poses
- * exp(xi^) (FP64) are written there and the call waits for the stream. */
+ * T_out: device double [B][16], or NULL; when given, the predicted poses
+ * exp(xi^) (FP64, row-major) are written there on the stream, ready to be the
+ * start poses of gcvo_register_batch. */
 int gcvo_mlp_forward(const gcvo_mlp_batch *batch, const uint16_t *w_bf16, float *out6, double *T_out,
                      void *ws, size_t ws_bytes, void *stream);
 

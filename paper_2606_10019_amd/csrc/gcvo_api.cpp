@@ -13,6 +13,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
+#include <mutex>
 #include <vector>
 
 #include "gcvo_dev.h"
@@ -99,6 +101,7 @@ struct PairInput {
     double eval_ell = 0.0, eval_cutoff = 0.0;                 // Eval
     const float *tgt_label = nullptr, *src_label = nullptr;   // [n][label_dim] or null
     int label_dim = 0;
+    const double *T0_dev = nullptr;                           // device start pose (batch calls) or null: T0
 };
 
 // Register mode with eig_ratio_min = 1: every shape is the identity (Remark 3),
@@ -118,6 +121,10 @@ struct Plan {
     int max_n = 0, max_job_n = 0, max_cells = 0;
     bool labels = false;   // the pairs carry label vectors
     bool iso = false;      // every pair is isotropic
+    // batch calls: one output slot per caller pair (set before build_plan)
+    std::vector<OutSlot> out;
+    OutSlot *d_out = nullptr;
+    gcvo_profile *profile = nullptr;   // measurement of the call, or null
 };
 
 // Lays out (base == nullptr: sizes) every device array of a batch.
@@ -147,6 +154,7 @@ void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &p
     size_t desc_start = A.off - sizeof(PairDev) * np;
     pl.d_jobs = A.take<SortJob>(std::max(n_jobs, 1));
     pl.d_tasks = A.take<BlockTask>(std::max(n_tasks, 1));
+    pl.d_out = A.take<OutSlot>(std::max<size_t>(pl.out.size(), 1));
     pl.desc_bytes = A.off - desc_start;
     pl.labels = np > 0 && in[0].label_dim > 0;
     pl.iso = np > 0;
@@ -187,6 +195,7 @@ void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &p
         P.cell_fraction = I.p.cell_fraction;
         P.cell_fraction_x = I.p.cell_fraction_x;
         std::memcpy(P.T_init, I.T0, sizeof P.T_init);
+        P.T_init_dev = I.T0_dev;
         P.t_orig = A.take<float>(3 * (size_t)nt);
         P.s_orig = A.take<float>(3 * (size_t)ns);
         P.t_rec = A.take<float>(3 * (size_t)nt);
@@ -277,44 +286,56 @@ void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &p
     pl.bytes = A.off + 256;
 }
 
-// Process-wide pair-kernel measurement (see gcvo_profile_enable).
-struct Profile {
-    bool on = false;
-    double ms = 0.0;
-    long long launches = 0, pairs = 0, points = 0;
-    std::vector<hipEvent_t> ev;   // grown on demand, kept for the process
-};
-Profile g_prof;
-
-hipEvent_t prof_event(size_t k) {
-    while (g_prof.ev.size() <= k) {
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
-        g_prof.ev.push_back(e);
-    }
-    return g_prof.ev[k];
-}
-
-struct Pinned {
-    int *flags = nullptr;
-    int cap = 0;           // ints held
-    ~Pinned() = default;   // lives for the thread; released by the runtime at exit
+// Pinned host buffers for the completion flags the device writes (two slots
+// of one int per pair), pooled per device.  Each buffer carries an event
+// recorded after the last work of the call that used it: it is handed out
+// again only once that event has completed, so the tail of one call's no-op
+// launches can never write into the next call's flags.  Buffers stay in the
+// pool until the process ends (the device may have written them).
+struct FlagBuf {
+    int *p = nullptr;
+    int cap = 0;                 // ints
+    hipEvent_t last = nullptr;   // recorded after the last work that writes p
+    bool busy = false;
 };
 
-// Two slots of n done flags in pinned host memory, written by the device.  A
-// larger batch gets a new buffer of twice the size; the old one is kept until
-// the process ends (the device wrote it), so a thread holds a few small buffers.
-int *pinned_flags(int n) {
-    static thread_local Pinned p;
-    if (p.cap < 2 * n) {
-        const int cap = std::max(2 * n, 2 * p.cap);
+class FlagPool {
+   public:
+    FlagBuf *acquire(int n_flags) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || dev < 0) return nullptr;
+        std::lock_guard<std::mutex> lock(m_);
+        if ((int)per_dev_.size() <= dev) per_dev_.resize(dev + 1);
+        auto &bufs = per_dev_[dev];
+        for (auto &b : bufs)
+            if (!b->busy && b->cap >= n_flags && hipEventQuery(b->last) == hipSuccess) {
+                b->busy = true;
+                return b.get();
+            }
+        auto b = std::make_unique<FlagBuf>();
+        b->cap = std::max(n_flags, 256);
         void *q = nullptr;
-        if (hipHostMalloc(&q, sizeof(int) * (size_t)cap, hipHostMallocDefault) != hipSuccess) return nullptr;
-        p.flags = static_cast<int *>(q);
-        p.cap = cap;
+        if (hipHostMalloc(&q, sizeof(int) * (size_t)b->cap, hipHostMallocDefault) != hipSuccess) return nullptr;
+        b->p = static_cast<int *>(q);
+        if (hipEventCreateWithFlags(&b->last, hipEventDisableTiming) != hipSuccess) return nullptr;
+        b->busy = true;
+        bufs.push_back(std::move(b));
+        return bufs.back().get();
     }
-    return p.flags;
-}
+    // Marks b free once the stream passes the work enqueued so far.
+    hipError_t release(FlagBuf *b, hipStream_t s) {
+        const hipError_t e = hipEventRecord(b->last, s);
+        std::lock_guard<std::mutex> lock(m_);
+        b->busy = false;
+        return e;
+    }
+
+   private:
+    std::mutex m_;
+    std::vector<std::vector<std::unique_ptr<FlagBuf>>> per_dev_;
+};
+
+FlagPool g_flag_pool;
 
 #define HIP_OK(expr)                                        \
     do {                                                    \
@@ -322,7 +343,7 @@ int *pinned_flags(int n) {
     } while (0)
 
 int upload_and_prepare(Plan &pl, int knn, hipStream_t s) {
-    // descriptors are contiguous from d_pairs; copy the three host vectors into place
+    // descriptors are contiguous from d_pairs; copy the host vectors into place
     std::vector<char> blob(pl.desc_bytes, 0);
     char *d0 = reinterpret_cast<char *>(pl.d_pairs);
     std::memcpy(blob.data(), pl.pairs.data(), pl.pairs.size() * sizeof(PairDev));
@@ -330,17 +351,21 @@ int upload_and_prepare(Plan &pl, int knn, hipStream_t s) {
                 pl.jobs.size() * sizeof(SortJob));
     std::memcpy(blob.data() + (reinterpret_cast<char *>(pl.d_tasks) - d0), pl.tasks.data(),
                 pl.tasks.size() * sizeof(BlockTask));
+    std::memcpy(blob.data() + (reinterpret_cast<char *>(pl.d_out) - d0), pl.out.data(),
+                pl.out.size() * sizeof(OutSlot));
     HIP_OK(hipMemcpyAsync(d0, blob.data(), pl.desc_bytes, hipMemcpyHostToDevice, s));
+    if (pl.pairs.empty()) return GCVO_OK;
     const int n_jobs = (int)pl.jobs.size();
     HIP_OK(launch_prepare(pl.d_pairs, (int)pl.pairs.size(), pl.max_n, pl.d_jobs, n_jobs, pl.max_job_n, pl.max_cells,
                           knn, s));
     return GCVO_OK;
 }
 
-// After a profiled run: launches in which some pair iterated are the first
-// max_k(iterations of pair k) ones; their event-bracketed durations and the
-// pairs logged by the device are added to the counters.
-int profile_collect(Plan &pl, int launched, int solver, hipStream_t s) {
+// After a measured run (the stream synchronised): launches in which some pair
+// iterated are the first max_k(iterations of pair k) ones; their
+// event-bracketed durations and the pairs logged by the device are added to
+// the caller's profile.
+int profile_collect(Plan &pl, int launched, int solver, const std::vector<hipEvent_t> &ev) {
     const int passes = passes_per_iteration(solver);
     const int np = (int)pl.pairs.size();
     int active = 0;
@@ -363,43 +388,54 @@ int profile_collect(Plan &pl, int launched, int solver, hipStream_t s) {
     pairs *= passes;
     points *= passes;
     double ms = 0.0;
-    for (int i = 0; i < active; ++i) {
+    for (int i = 0; i < active && 2 * i + 1 < (int)ev.size(); ++i) {
         float e = 0.0f;
-        if (hipEventElapsedTime(&e, g_prof.ev[2 * i], g_prof.ev[2 * i + 1]) != hipSuccess) return GCVO_ERR_HIP;
+        if (hipEventElapsedTime(&e, ev[2 * i], ev[2 * i + 1]) != hipSuccess) return GCVO_ERR_HIP;
         ms += e;
     }
-    (void)s;
-    g_prof.ms += ms;
-    g_prof.launches += active;
-    g_prof.pairs += pairs;
-    g_prof.points += points;
+    pl.profile->pair_kernel_ms += ms;
+    pl.profile->launches += active;
+    pl.profile->pairs += pairs;
+    pl.profile->source_points += points;
     return GCVO_OK;
 }
 
-int run_iterations(Plan &pl, int max_iters, int precision, int solver, hipStream_t s) {
+// Enqueues the iterations chunk by chunk until every pair is done (or
+// max_iters).  With wait, or when the call is measured, it returns after the
+// stream has finished them; otherwise the last chunk may still be queued.
+int run_iterations(Plan &pl, int max_iters, int precision, int solver, hipStream_t s, bool wait) {
     const int np = (int)pl.pairs.size();
-    int *flags = pinned_flags(std::max(np, 1));
-    if (!flags) return GCVO_ERR_HIP;
+    if (np == 0) return GCVO_OK;
+    FlagBuf *fb = g_flag_pool.acquire(2 * np);
+    if (!fb) return GCVO_ERR_HIP;
+    int *flags = fb->p;
     hipEvent_t ev[2];
-    HIP_OK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-    if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
-        hipEventDestroy(ev[0]);
+    if (hipEventCreateWithFlags(&ev[0], hipEventDisableTiming) != hipSuccess) {
+        g_flag_pool.release(fb, s);
         return GCVO_ERR_HIP;
     }
+    if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
+        hipEventDestroy(ev[0]);
+        g_flag_pool.release(fb, s);
+        return GCVO_ERR_HIP;
+    }
+    std::vector<hipEvent_t> pev;   // measured calls: two events per pair-kernel launch
     const int n_tasks = (int)pl.tasks.size();
     int launched = 0, slot = 0, rc = GCVO_OK;
     bool pending[2] = {false, false};
     auto enqueue = [&](int c) -> hipError_t {
         int *done = flags + (size_t)slot * np;
-        if (!g_prof.on)
+        if (!pl.profile)
             return launch_iterations(pl.d_pairs, np, pl.d_tasks, n_tasks, c, precision, solver, pl.labels, pl.iso,
                                      done, s);
-        const int per = 2 * passes_per_iteration(solver);
-        std::vector<hipEvent_t> ev((size_t)per * c);
-        for (size_t i = 0; i < ev.size(); ++i)
-            if (!(ev[i] = prof_event((size_t)per * launched + i))) return hipErrorOutOfMemory;
+        const size_t first = pev.size(), per = 2 * (size_t)passes_per_iteration(solver) * c;
+        for (size_t i = 0; i < per; ++i) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return hipErrorOutOfMemory;
+            pev.push_back(e);
+        }
         return launch_iterations(pl.d_pairs, np, pl.d_tasks, n_tasks, c, precision, solver, pl.labels, pl.iso,
-                                 done, s, ev.data());
+                                 done, s, pev.data() + first);
     };
     while (rc == GCVO_OK && launched < max_iters) {
         const int c = std::min(kChunk, max_iters - launched);
@@ -422,10 +458,12 @@ int run_iterations(Plan &pl, int max_iters, int precision, int solver, hipStream
         }
         slot = other;
     }
-    if (hipStreamSynchronize(s) != hipSuccess) rc = GCVO_ERR_HIP;
+    if ((wait || pl.profile) && hipStreamSynchronize(s) != hipSuccess) rc = GCVO_ERR_HIP;
+    if (g_flag_pool.release(fb, s) != hipSuccess) rc = GCVO_ERR_HIP;
     hipEventDestroy(ev[0]);
     hipEventDestroy(ev[1]);
-    if (rc == GCVO_OK && g_prof.on) rc = profile_collect(pl, launched, solver, s);
+    if (rc == GCVO_OK && pl.profile) rc = profile_collect(pl, launched, solver, pev);
+    for (hipEvent_t e : pev) hipEventDestroy(e);
     return rc;
 }
 
@@ -441,6 +479,7 @@ void fill_info(const State &S, gcvo_info *info) {
     std::memcpy(info->g, S.g, sizeof info->g);
     info->xi_l1 = S.xi_l1;
     for (int s = 0; s < kMaxStages; ++s) info->stage_iters[s] = S.stage_iters[s];
+    info->damped = S.damped;
 }
 
 bool ws_ok(void *ws, size_t ws_bytes, size_t need) {
@@ -448,15 +487,17 @@ bool ws_ok(void *ws, size_t ws_bytes, size_t need) {
 }
 
 int register_many(Mode mode, std::vector<PairInput> &in, double *T_out, gcvo_info *info, void *ws,
-                  size_t ws_bytes, hipStream_t s, int shared_knn, int precision, int solver, int max_iters) {
+                  size_t ws_bytes, hipStream_t s, int shared_knn, int precision, int solver, int max_iters,
+                  gcvo_profile *profile) {
     Plan sizing;
     build_plan(nullptr, mode, in, sizing);
     if (!ws_ok(ws, ws_bytes, sizing.bytes)) return GCVO_ERR_WORKSPACE;
     Plan pl;
+    pl.profile = profile;
     build_plan(ws, mode, in, pl);
     int rc = upload_and_prepare(pl, shared_knn, s);
     if (rc) return rc;
-    rc = run_iterations(pl, max_iters, precision, solver, s);
+    rc = run_iterations(pl, max_iters, precision, solver, s, true);
     if (rc) return rc;
     const int np = (int)in.size();
     std::vector<State> st(np);
@@ -496,23 +537,10 @@ void gcvo_default_params(gcvo_params *p) {
     p->min_step = 1e-10;
     p->cell_fraction = 0.5;
     p->cell_fraction_x = 0.125;
+    p->profile = nullptr;
 }
 
-int gcvo_abi_version(void) { return 104; }
-
-void gcvo_profile_enable(int on) { g_prof.on = on != 0; }
-
-void gcvo_profile_reset(void) {
-    g_prof.ms = 0.0;
-    g_prof.launches = g_prof.pairs = g_prof.points = 0;
-}
-
-void gcvo_profile_read(double *ms, long long *launches, long long *pairs, long long *points) {
-    if (ms) *ms = g_prof.ms;
-    if (launches) *launches = g_prof.launches;
-    if (pairs) *pairs = g_prof.pairs;
-    if (points) *points = g_prof.points;
-}
+int gcvo_abi_version(void) { return 200; }
 
 const char *gcvo_strerror(int status) {
     switch (status) {
@@ -556,7 +584,7 @@ int gcvo_register(const float *tgt_xyz, long long n_tgt, const float *src_xyz, l
     std::memcpy(in[0].T0, T_init ? T_init : kIdentity, sizeof in[0].T0);
     double T[16];
     int rc = register_many(Mode::Register, in, T, info, workspace, workspace_bytes, (hipStream_t)stream, p->knn,
-                           p->precision, p->solver, p->max_iters);
+                           p->precision, p->solver, p->max_iters, p->profile);
     if (rc == GCVO_ERR_HIP || rc == GCVO_ERR_WORKSPACE) return fail(rc);   // info not filled by the run
     if (rc != GCVO_OK) return rc;                                           // info holds the run's summary
     std::memcpy(T_out, T, sizeof T);
@@ -567,22 +595,57 @@ int gcvo_register(const float *tgt_xyz, long long n_tgt, const float *src_xyz, l
 
 namespace {
 
-size_t batch_workspace(int n_pairs, const long long *tgt_off, const long long *src_off, const gcvo_params *p,
-                       int shared_params, int label_dim) {
-    if (n_pairs < 1 || !tgt_off || !src_off || !p) return 0;
-    if (label_dim < 0 || label_dim > GCVO_MAX_LABEL_DIM) return 0;
-    std::vector<PairInput> in;
+// The pairs of a batch that run on the device (the others fail before any
+// device work: too few points for the neighbourhoods) and every caller pair's
+// output slot.
+struct BatchSplit {
+    std::vector<PairInput> run;
+    std::vector<OutSlot> out;
+};
+
+// Host validation and the split.  Returns GCVO_OK, or the call's error.
+int split_batch(int n_pairs, const float *tgt_xyz, const float *tgt_label, const long long *tgt_off,
+                const float *src_xyz, const float *src_label, const long long *src_off, int label_dim,
+                const double *T_init_dev, const gcvo_params *p, int shared_params, BatchSplit &B) {
+    if (n_pairs < 1 || !tgt_off || !src_off || !p) return GCVO_ERR_INVALID;
+    if (label_dim < 0 || label_dim > GCVO_MAX_LABEL_DIM) return GCVO_ERR_INVALID;
+    const int knn = p[0].knn, prec = p[0].precision, solver = p[0].solver;
+    B.run.clear();
+    B.out.assign(n_pairs, OutSlot{-1, GCVO_OK});
     for (int k = 0; k < n_pairs; ++k) {
         const gcvo_params &pk = shared_params ? p[0] : p[k];
+        if (!params_ok(&pk) || pk.knn != knn || pk.precision != prec || pk.solver != solver) return GCVO_ERR_INVALID;
         const long long nt = tgt_off[k + 1] - tgt_off[k], ns = src_off[k + 1] - src_off[k];
-        if (!params_ok(&pk) || nt < 0 || ns < 0 || nt > GCVO_MAX_POINTS || ns > GCVO_MAX_POINTS) return 0;
-        if (nt < pk.knn || ns < pk.knn) continue;   // such pairs are reported, not run
-        in.push_back(PairInput{nullptr, nullptr, nt, ns, pk, {}});
-        in.back().label_dim = label_dim;
+        if (nt < 0 || ns < 0 || tgt_off[k] < 0 || src_off[k] < 0) return GCVO_ERR_INVALID;
+        if (nt > GCVO_MAX_POINTS || ns > GCVO_MAX_POINTS) return GCVO_ERR_CAPACITY;
+        if (nt < knn || ns < knn) {
+            B.out[k].status = GCVO_ERR_TOO_FEW_POINTS;
+            continue;
+        }
+        PairInput I{tgt_xyz ? tgt_xyz + 3 * tgt_off[k] : nullptr, src_xyz ? src_xyz + 3 * src_off[k] : nullptr,
+                    nt, ns, pk, {}};
+        std::memcpy(I.T0, kIdentity, sizeof I.T0);
+        I.T0_dev = T_init_dev ? T_init_dev + 16 * (size_t)k : nullptr;
+        if (label_dim > 0) {
+            I.tgt_label = tgt_label ? tgt_label + (size_t)label_dim * tgt_off[k] : nullptr;
+            I.src_label = src_label ? src_label + (size_t)label_dim * src_off[k] : nullptr;
+            I.label_dim = label_dim;
+        }
+        B.out[k].run = (int)B.run.size();
+        B.run.push_back(I);
     }
-    if (in.empty()) return 256;
+    return GCVO_OK;
+}
+
+size_t batch_workspace(int n_pairs, const long long *tgt_off, const long long *src_off, const gcvo_params *p,
+                       int shared_params, int label_dim) {
+    BatchSplit B;
+    if (split_batch(n_pairs, nullptr, nullptr, tgt_off, nullptr, nullptr, src_off, label_dim, nullptr, p,
+                    shared_params, B) != GCVO_OK)
+        return 0;
     Plan pl;
-    build_plan(nullptr, Mode::Register, in, pl);
+    pl.out = B.out;
+    build_plan(nullptr, Mode::Register, B.run, pl);
     return pl.bytes;
 }
 
@@ -593,52 +656,26 @@ int register_batch(int n_pairs, const float *tgt_xyz, const float *tgt_label, co
     if (n_pairs < 1 || !tgt_xyz || !tgt_off || !src_xyz || !src_off || !p || !T_out) return GCVO_ERR_INVALID;
     if (label_dim < 0 || label_dim > GCVO_MAX_LABEL_DIM || (label_dim > 0 && (!tgt_label || !src_label)))
         return GCVO_ERR_INVALID;
-    std::vector<PairInput> in(n_pairs);
-    int knn = p[0].knn, prec = p[0].precision, solver = p[0].solver, max_it = 0;
-    for (int k = 0; k < n_pairs; ++k) {
-        const gcvo_params &pk = shared_params ? p[0] : p[k];
-        if (!params_ok(&pk) || pk.knn != knn || pk.precision != prec || pk.solver != solver) return GCVO_ERR_INVALID;
-        const long long nt = tgt_off[k + 1] - tgt_off[k], ns = src_off[k + 1] - src_off[k];
-        if (nt < 0 || ns < 0 || tgt_off[k] < 0 || src_off[k] < 0) return GCVO_ERR_INVALID;
-        if (nt > GCVO_MAX_POINTS || ns > GCVO_MAX_POINTS) return GCVO_ERR_CAPACITY;
-        const double *T0 = T_init ? T_init + 16 * (size_t)k : kIdentity;
-        if (!pose_ok(T0)) return GCVO_ERR_INVALID;
-        in[k] = PairInput{tgt_xyz + 3 * tgt_off[k], src_xyz + 3 * src_off[k], nt, ns, pk, {}};
-        std::memcpy(in[k].T0, T0, sizeof in[k].T0);
-        if (label_dim > 0) {
-            in[k].tgt_label = tgt_label + (size_t)label_dim * tgt_off[k];
-            in[k].src_label = src_label + (size_t)label_dim * src_off[k];
-            in[k].label_dim = label_dim;
-        }
-        max_it = std::max(max_it, pk.max_iters);
-    }
-    // Pairs too small to register fail individually; the rest run.
-    std::vector<int> keep;
-    for (int k = 0; k < n_pairs; ++k) {
-        std::memcpy(T_out + 16 * (size_t)k, in[k].T0, 16 * sizeof(double));
-        if (in[k].n_t < knn || in[k].n_s < knn) {
-            if (info) {
-                std::memset(info + k, 0, sizeof(gcvo_info));
-                info[k].status = GCVO_ERR_TOO_FEW_POINTS;
-            }
-        } else {
-            keep.push_back(k);
-        }
-    }
-    if (keep.empty()) return GCVO_OK;
-    std::vector<PairInput> run;
-    for (int k : keep) run.push_back(in[k]);
-    std::vector<double> T(16 * run.size());
-    std::vector<gcvo_info> inf(run.size());
-    for (size_t r = 0; r < run.size(); ++r) std::memcpy(&T[16 * r], run[r].T0, 16 * sizeof(double));
-    int rc = register_many(Mode::Register, run, T.data(), inf.data(), workspace, workspace_bytes,
-                           (hipStream_t)stream, knn, prec, solver, max_it);
-    if (rc == GCVO_ERR_HIP || rc == GCVO_ERR_WORKSPACE) return rc;
-    for (size_t r = 0; r < run.size(); ++r) {
-        const int k = keep[r];
-        if (inf[r].status == GCVO_OK) std::memcpy(T_out + 16 * (size_t)k, &T[16 * r], 16 * sizeof(double));
-        if (info) info[k] = inf[r];
-    }
+    BatchSplit B;
+    int rc = split_batch(n_pairs, tgt_xyz, tgt_label, tgt_off, src_xyz, src_label, src_off, label_dim, T_init, p,
+                         shared_params, B);
+    if (rc) return rc;
+    int max_it = 0;
+    for (const PairInput &I : B.run) max_it = std::max(max_it, I.p.max_iters);
+    hipStream_t s = (hipStream_t)stream;
+    Plan sizing;
+    sizing.out = B.out;
+    build_plan(nullptr, Mode::Register, B.run, sizing);
+    if (!ws_ok(workspace, workspace_bytes, sizing.bytes)) return GCVO_ERR_WORKSPACE;
+    Plan pl;
+    pl.out = B.out;
+    pl.profile = p[0].profile;
+    build_plan(workspace, Mode::Register, B.run, pl);
+    rc = upload_and_prepare(pl, p[0].knn, s);
+    if (rc) return rc;
+    rc = run_iterations(pl, max_it, p[0].precision, p[0].solver, s, false);
+    if (rc) return rc;
+    HIP_OK(launch_outputs(pl.d_pairs, pl.d_out, n_pairs, T_init, T_out, info, s));
     return GCVO_OK;
 }
 
@@ -746,6 +783,7 @@ int gcvo_register_batch_labeled(int n_pairs, const float *tgt_xyz, const float *
 
 size_t gcvo_eval_workspace_size(long long n_tgt, long long n_src) { return eval_workspace(n_tgt, n_src, 0); }
 
+
 int gcvo_eval_fgh(const float *tgt_xyz, const float *tgt_shape6, long long n_tgt, const float *src_xyz,
                   const float *src_shape6, long long n_src, const double *T, double length_scale, double cutoff,
                   double sigma2, int precision, double *f, double *g, double *H, long long *n_pairs,
@@ -767,6 +805,135 @@ int gcvo_eval_fgh_labeled(const float *tgt_xyz, const float *tgt_shape6, const f
     if (label_dim < 1) return GCVO_ERR_INVALID;
     return eval_fgh(tgt_xyz, tgt_shape6, tgt_label, n_tgt, src_xyz, src_shape6, src_label, n_src, label_dim, T,
                     length_scale, cutoff, sigma2, precision, f, g, H, n_pairs, workspace, workspace_bytes, stream);
+}
+
+// ---------------------------------------------------------------- batched shapes and evaluations
+
+namespace {
+
+// Clouds of a shapes batch, or the error of the call.
+int shapes_inputs(int n_clouds, const float *xyz, const long long *off, int knn, double rho, float *out,
+                  std::vector<PairInput> &in) {
+    if (n_clouds < 1 || !off || knn < 2 || knn > kMaxKnn || !(rho > 0.0 && rho <= 1.0)) return GCVO_ERR_INVALID;
+    gcvo_params p;
+    gcvo_default_params(&p);
+    p.knn = knn;
+    p.eig_ratio_min = rho;
+    in.clear();
+    for (int k = 0; k < n_clouds; ++k) {
+        const long long n = off[k + 1] - off[k];
+        if (off[k] < 0 || n < 0) return GCVO_ERR_INVALID;
+        if (n > GCVO_MAX_POINTS) return GCVO_ERR_CAPACITY;
+        if (n < knn) return GCVO_ERR_TOO_FEW_POINTS;
+        PairInput I{xyz ? xyz + 3 * off[k] : nullptr, xyz ? xyz + 3 * off[k] : nullptr, n, 0, p, {}};
+        std::memcpy(I.T0, kIdentity, sizeof I.T0);
+        I.shape_out = out ? out + 6 * off[k] : nullptr;
+        in.push_back(I);
+    }
+    return GCVO_OK;
+}
+
+// Pairs of an evaluation batch: pairs with an empty cloud never run (their
+// sums are zero); the rest evaluate at their pose.
+int eval_inputs(int n_pairs, const float *tgt_xyz, const float *tgt_shape6, const long long *tgt_off,
+                const float *src_xyz, const float *src_shape6, const long long *src_off, const double *T_dev,
+                const double *ell, double cutoff_scale, double sigma2, int precision, std::vector<PairInput> &in,
+                std::vector<OutSlot> &out) {
+    if (n_pairs < 1 || !tgt_off || !src_off || !ell) return GCVO_ERR_INVALID;
+    if (!(std::isfinite(cutoff_scale) && cutoff_scale > 0.0) || !(std::isfinite(sigma2) && sigma2 > 0.0))
+        return GCVO_ERR_INVALID;
+    if (precision != GCVO_PRECISION_FP32 && precision != GCVO_PRECISION_FP64) return GCVO_ERR_INVALID;
+    gcvo_params p;
+    gcvo_default_params(&p);
+    p.sigma2 = sigma2;
+    p.precision = precision;
+    in.clear();
+    out.assign(n_pairs, OutSlot{-1, GCVO_OK});
+    for (int k = 0; k < n_pairs; ++k) {
+        const long long nt = tgt_off[k + 1] - tgt_off[k], ns = src_off[k + 1] - src_off[k];
+        if (tgt_off[k] < 0 || src_off[k] < 0 || nt < 0 || ns < 0) return GCVO_ERR_INVALID;
+        if (nt > GCVO_MAX_POINTS || ns > GCVO_MAX_POINTS) return GCVO_ERR_CAPACITY;
+        if (!(std::isfinite(ell[k]) && ell[k] > 0.0)) return GCVO_ERR_INVALID;
+        if (nt == 0 || ns == 0) continue;
+        PairInput I{tgt_xyz ? tgt_xyz + 3 * tgt_off[k] : nullptr, src_xyz ? src_xyz + 3 * src_off[k] : nullptr,
+                    nt, ns, p, {}};
+        std::memcpy(I.T0, kIdentity, sizeof I.T0);
+        I.T0_dev = T_dev ? T_dev + 16 * (size_t)k : nullptr;
+        I.tgt_shape = tgt_shape6 ? tgt_shape6 + 6 * tgt_off[k] : nullptr;
+        I.src_shape = src_shape6 ? src_shape6 + 6 * src_off[k] : nullptr;
+        I.eval_ell = ell[k];
+        I.eval_cutoff = cutoff_scale * ell[k];
+        out[k].run = (int)in.size();
+        in.push_back(I);
+    }
+    return GCVO_OK;
+}
+
+}  // namespace
+
+size_t gcvo_shapes_batch_workspace_size(int n_clouds, const long long *off) {
+    std::vector<PairInput> in;
+    if (shapes_inputs(n_clouds, nullptr, off, 2, 0.5, nullptr, in) != GCVO_OK) return 0;
+    Plan pl;
+    build_plan(nullptr, Mode::Shapes, in, pl);
+    return pl.bytes;
+}
+
+int gcvo_point_shapes_batch(int n_clouds, const float *xyz, const long long *off, int knn, double rho,
+                            float *shape6_out, void *workspace, size_t workspace_bytes, void *stream) {
+    if (!xyz || !shape6_out) return GCVO_ERR_INVALID;
+    std::vector<PairInput> in;
+    int rc = shapes_inputs(n_clouds, xyz, off, knn, rho, shape6_out, in);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    Plan sizing;
+    build_plan(nullptr, Mode::Shapes, in, sizing);
+    if (!ws_ok(workspace, workspace_bytes, sizing.bytes)) return GCVO_ERR_WORKSPACE;
+    Plan pl;
+    build_plan(workspace, Mode::Shapes, in, pl);
+    return upload_and_prepare(pl, knn, s);
+}
+
+size_t gcvo_eval_batch_workspace_size(int n_pairs, const long long *tgt_off, const long long *src_off) {
+    std::vector<PairInput> in;
+    std::vector<OutSlot> out;
+    if (n_pairs < 1 || !tgt_off || !src_off) return 0;
+    std::vector<double> ell(n_pairs, 1.0);
+    if (eval_inputs(n_pairs, nullptr, nullptr, tgt_off, nullptr, nullptr, src_off, nullptr, ell.data(), 3.0, 1.0,
+                    GCVO_PRECISION_FP32, in, out) != GCVO_OK)
+        return 0;
+    Plan pl;
+    pl.out = out;
+    build_plan(nullptr, Mode::Eval, in, pl);
+    return pl.bytes;
+}
+
+int gcvo_eval_fgh_batch(int n_pairs, const float *tgt_xyz, const float *tgt_shape6, const long long *tgt_off,
+                        const float *src_xyz, const float *src_shape6, const long long *src_off, const double *T,
+                        const double *length_scale, double cutoff_scale, double sigma2, int precision, double *f,
+                        double *g, double *H, long long *n_pairs_out, int *status, void *workspace,
+                        size_t workspace_bytes, void *stream) {
+    if (!tgt_xyz || !tgt_shape6 || !src_xyz || !src_shape6) return GCVO_ERR_INVALID;
+    std::vector<PairInput> in;
+    std::vector<OutSlot> out;
+    int rc = eval_inputs(n_pairs, tgt_xyz, tgt_shape6, tgt_off, src_xyz, src_shape6, src_off, T, length_scale,
+                         cutoff_scale, sigma2, precision, in, out);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    Plan sizing;
+    sizing.out = out;
+    build_plan(nullptr, Mode::Eval, in, sizing);
+    if (!ws_ok(workspace, workspace_bytes, sizing.bytes)) return GCVO_ERR_WORKSPACE;
+    Plan pl;
+    pl.out = out;
+    build_plan(workspace, Mode::Eval, in, pl);
+    rc = upload_and_prepare(pl, 0, s);
+    if (rc) return rc;
+    if (!in.empty())
+        HIP_OK(launch_iterations(pl.d_pairs, (int)in.size(), pl.d_tasks, (int)pl.tasks.size(), 1, precision,
+                                 GCVO_SOLVER_GN, false, false, nullptr, s));
+    HIP_OK(launch_eval_outputs(pl.d_pairs, pl.d_out, n_pairs, f, g, H, n_pairs_out, status, s));
+    return GCVO_OK;
 }
 
 size_t gcvo_shapes_workspace_size(long long n) {

@@ -74,7 +74,7 @@ constexpr int kJobStage = 3;        // kJobStage + s: pair grid of stage s over 
 
 // Per-pair solver state, FP64, owned by the device for the whole solve.
 struct State {
-    double T[16];          // current pose in the recentred frame (row-major 4x4)
+    double T[16];          // current pose in the caller's frame (row-major 4x4; the pair kernel recentres it)
     double f, g[6], H[36]; // last evaluation (H = H_GN incl. connection term)
     double xi[6];
     double xi_l1;
@@ -107,6 +107,7 @@ struct PairDev {
     double cell_fraction;             // pair-grid cell edge (y, z) as a fraction of the cutoff
     double cell_fraction_x;           // pair-grid cell edge along x (the row direction), same unit
     double T_init[16];                // caller frame
+    const double *T_init_dev;         // device [16] start pose (batch calls), checked to be in SE(3); or null: T_init
     // derived on device
     double centre[3];                 // target centroid, subtracted before the FP32 cast
     double sum_t[3];                  // FP64 coordinate sums of the target
@@ -138,6 +139,14 @@ struct PairDev {
     // Solver state, held in the descriptor so that a kernel reaches it with the
     // descriptor's own loads (no pointer to follow).
     State st;
+};
+
+// Where a caller's pair k of a batch call finds its result: run >= 0 is the
+// index of the pair in the device batch; run < 0 means it never ran and
+// `status` is its error.
+struct OutSlot {
+    int run;
+    int status;
 };
 
 struct BlockTask {   // one block of the pair kernel: a pair and a 256-point slice of its source
@@ -189,5 +198,16 @@ hipError_t launch_iterations(PairDev *pairs_dev, int n_pairs, BlockTask *tasks_d
                              hipEvent_t *events = nullptr);
 // Pair-kernel passes per solver iteration (2 for the first-order solver).
 int passes_per_iteration(int solver);
+// Enqueue the outputs of a batch call: for caller pair k, T_out[k] (device
+// [16]) = the solved pose, or the start pose (T_init_dev + 16 k, identity when
+// null) when the pair failed or never ran; info[k] (device, may be null) = the
+// run summary or {status, 0...}.
+hipError_t launch_outputs(const PairDev *pairs, const OutSlot *slots, int n_out, const double *T_init_dev,
+                          double *T_out, gcvo_info *info, hipStream_t s);
+// Enqueue the outputs of a batch of evaluations: for caller pair k, f[k],
+// g[k][6], H[k][36], n_pairs[k] and status[k] (each device, may be null) from
+// the evaluation, or zeros (an empty double sum) when the pair never ran.
+hipError_t launch_eval_outputs(const PairDev *pairs, const OutSlot *slots, int n_out, double *f, double *g,
+                               double *H, long long *n_pairs, int *status, hipStream_t s);
 
 }  // namespace gcvo

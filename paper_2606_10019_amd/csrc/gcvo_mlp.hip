@@ -445,15 +445,8 @@ int gcvo_mlp_forward(const gcvo_mlp_batch *batch, const uint16_t *w_bf16, float 
     launch_forward(a, s);
     if (hipGetLastError() != hipSuccess) return GCVO_ERR_HIP;
     if (T_out) {
-        double *dT = reinterpret_cast<double *>(static_cast<char *>(ws) + L.T);
-        hipLaunchKernelGGL(k_poses, dim3((a.B + 63) / 64), dim3(64), 0, s, out6, a.B, dT);
+        hipLaunchKernelGGL(k_poses, dim3((a.B + 63) / 64), dim3(64), 0, s, out6, a.B, T_out);
         if (hipGetLastError() != hipSuccess) return GCVO_ERR_HIP;
-        rc = check_bad(a, s);
-        if (rc != GCVO_OK) return rc;
-        if (hipMemcpyAsync(T_out, dT, sizeof(double) * 16 * a.B, hipMemcpyDeviceToHost, s) != hipSuccess)
-            return GCVO_ERR_HIP;
-        if (hipStreamSynchronize(s) != hipSuccess) return GCVO_ERR_HIP;
-        return GCVO_OK;
     }
     return check_bad(a, s);
 }

@@ -162,6 +162,23 @@ __device__ double knn_cell(const float lo[3], const float hi[3], int n) {
     return 0.5 * cbrt(vol / (double)(n > 0 ? n : 1));
 }
 
+// A start pose given in device memory must be a rigid motion: finite, last
+// row (0, 0, 0, 1), R^T R = I and det R = 1, each within 1e-6.
+__device__ bool in_se3(const double T[16]) {
+    for (int a = 0; a < 16; ++a)
+        if (!isfinite(T[a])) return false;
+    if (fabs(T[12]) > 1e-6 || fabs(T[13]) > 1e-6 || fabs(T[14]) > 1e-6 || fabs(T[15] - 1.0) > 1e-6) return false;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) s += T[4 * k + a] * T[4 * k + b];
+            if (fabs(s - (a == b ? 1.0 : 0.0)) > 1e-6) return false;
+        }
+    const double det = T[0] * (T[5] * T[10] - T[6] * T[9]) - T[1] * (T[4] * T[10] - T[6] * T[8]) +
+                       T[2] * (T[4] * T[9] - T[5] * T[8]);
+    return fabs(det - 1.0) <= 1e-6;
+}
+
 // One 32-thread block per pair, the grids built side by side (each is a short
 // serial FP64 loop): thread 0 the centroid and the solver state, 1 and 2 the
 // kNN grids, 3 the source's Morton grid, 4 + s the pair grid of stage s.
@@ -173,7 +190,13 @@ __global__ __launch_bounds__(32) void k_setup(PairDev *pairs) {
     if (t == 0) {
         for (int d = 0; d < 3; ++d) P.centre[d] = c[d];
         State &S = P.st;
-        for (int a = 0; a < 16; ++a) S.T[a] = P.T_init[a];
+        bool pose_ok = true;
+        if (P.T_init_dev) {
+            for (int a = 0; a < 16; ++a) S.T[a] = P.T_init_dev[a];
+            pose_ok = in_se3(S.T);
+        } else {
+            for (int a = 0; a < 16; ++a) S.T[a] = P.T_init[a];
+        }
         S.f = 0.0;
         for (int a = 0; a < 6; ++a) S.g[a] = S.xi[a] = 0.0;
         for (int a = 0; a < 36; ++a) S.H[a] = 0.0;
@@ -184,8 +207,9 @@ __global__ __launch_bounds__(32) void k_setup(PairDev *pairs) {
         S.gnorm = 0.0;
         for (int a = 0; a < 6; ++a) S.dir[a] = 0.0;
         for (int s = 0; s < kMaxStages; ++s) S.stage_iters[s] = 0;
-        S.status = P.nonfinite ? GCVO_ERR_INVALID : GCVO_OK;
-        S.done = P.nonfinite ? 1 : 0;
+        const bool bad = P.nonfinite || !pose_ok;
+        S.status = bad ? GCVO_ERR_INVALID : GCVO_OK;
+        S.done = bad ? 1 : 0;
     } else if (t == 1) {
         if (P.job_knn_t)
             make_grid(*P.job_knn_t->grid, P.lo_t, P.hi_t, knn_cell(P.lo_t, P.hi_t, P.n_t), P.job_knn_t->max_cells);
@@ -695,6 +719,71 @@ __global__ __launch_bounds__(kBlock) void k_gather(SortJob *jobs, const PairDev 
         out[2] = make_float4(sh[5], org[p], org[(size_t)n + p], org[2 * (size_t)n + p]);
         if (P.label_dim > 0) P.t_lab[stage][pos] = lab;
     }
+}
+
+// ------------------------------------------------------------------ batch outputs
+
+// One thread per caller pair: the pose (or the start pose when the pair failed
+// or never ran) and the run summary.
+__global__ __launch_bounds__(64) void k_output(const PairDev *pairs, const OutSlot *slots, int n_out,
+                                               const double *T_init_dev, double *T_out, gcvo_info *info) {
+    const int k = blockIdx.x * 64 + threadIdx.x;
+    if (k >= n_out) return;
+    const OutSlot o = slots[k];
+    const State *S = o.run >= 0 ? &pairs[o.run].st : nullptr;
+    const int status = S ? S->status : o.status;
+    double *T = T_out + 16 * (size_t)k;
+    for (int a = 0; a < 16; ++a) {
+        const double start = T_init_dev ? T_init_dev[16 * (size_t)k + a] : ((a % 5 == 0) ? 1.0 : 0.0);
+        T[a] = (S && status == GCVO_OK) ? S->T[a] : start;
+    }
+    if (!info) return;
+    gcvo_info r = {};
+    r.status = status;
+    if (S) {
+        r.converged = S->converged;
+        r.iters = S->iter;
+        r.stages = S->stage + 1;
+        r.pairs_last = S->pairs_last;
+        r.f = S->f;
+        for (int a = 0; a < 6; ++a) r.g[a] = S->g[a];
+        r.xi_l1 = S->xi_l1;
+        for (int s = 0; s < kMaxStages; ++s) r.stage_iters[s] = S->stage_iters[s];
+        r.damped = S->damped;
+    }
+    info[k] = r;
+}
+
+hipError_t launch_outputs(const PairDev *pairs, const OutSlot *slots, int n_out, const double *T_init_dev,
+                          double *T_out, gcvo_info *info, hipStream_t s) {
+    if (n_out <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_output, dim3((n_out + 63) / 64), dim3(64), 0, s, pairs, slots, n_out, T_init_dev, T_out,
+                       info);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(64) void k_eval_output(const PairDev *pairs, const OutSlot *slots, int n_out, double *f,
+                                                    double *g, double *H, long long *n_pairs, int *status) {
+    const int k = blockIdx.x * 64 + threadIdx.x;
+    if (k >= n_out) return;
+    const OutSlot o = slots[k];
+    const State *S = o.run >= 0 ? &pairs[o.run].st : nullptr;
+    const bool ok = S && S->status == GCVO_OK;
+    if (status) status[k] = S ? S->status : o.status;
+    if (f) f[k] = ok ? S->f : 0.0;
+    if (g)
+        for (int a = 0; a < 6; ++a) g[6 * (size_t)k + a] = ok ? S->g[a] : 0.0;
+    if (H)
+        for (int a = 0; a < 36; ++a) H[36 * (size_t)k + a] = ok ? S->H[a] : 0.0;
+    if (n_pairs) n_pairs[k] = ok ? S->pairs_last : 0;
+}
+
+hipError_t launch_eval_outputs(const PairDev *pairs, const OutSlot *slots, int n_out, double *f, double *g,
+                               double *H, long long *n_pairs, int *status, hipStream_t s) {
+    if (n_out <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_eval_output, dim3((n_out + 63) / 64), dim3(64), 0, s, pairs, slots, n_out, f, g, H,
+                       n_pairs, status);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ launcher

@@ -6,8 +6,10 @@ every step of the computation runs in the library's kernels.  There is no CPU
 fallback: if the library is missing or fails to load, every call raises.
 
 Device tensors are torch CUDA (HIP) tensors: clouds float32 ``[n, 3]``
-contiguous, shapes float32 ``[6, n]`` (xx, xy, xz, yy, yz, zz).  Poses are
-float64 numpy ``4x4`` arrays on the host.
+contiguous, shapes float32 ``[6, n]`` (xx, xy, xz, yy, yz, zz).  Single-pair
+poses are float64 numpy ``4x4`` arrays on the host; the batch calls take and
+give device poses (``[n, 4, 4]`` float64 tensors), with host numpy copies as
+the default return for convenience.
 """
 from __future__ import annotations
 
@@ -38,15 +40,24 @@ GCVO_MAX_LABEL_DIM = 4
 
 EXPORTED = ["gcvo_default_params", "gcvo_workspace_size", "gcvo_register", "gcvo_batch_workspace_size",
             "gcvo_register_batch", "gcvo_eval_workspace_size", "gcvo_eval_fgh", "gcvo_shapes_workspace_size",
-            "gcvo_point_shapes", "gcvo_strerror", "gcvo_abi_version", "gcvo_profile_enable",
-            "gcvo_profile_reset", "gcvo_profile_read",
+            "gcvo_point_shapes", "gcvo_strerror", "gcvo_abi_version",
             "gcvo_mlp_param_count", "gcvo_mlp_workspace_size", "gcvo_mlp_forward", "gcvo_mlp_loss_grad",
             "gcvo_mlp_adam", "gcvo_batch_workspace_size_labeled", "gcvo_register_batch_labeled",
-            "gcvo_eval_workspace_size_labeled", "gcvo_eval_fgh_labeled"]
+            "gcvo_eval_workspace_size_labeled", "gcvo_eval_fgh_labeled", "gcvo_shapes_batch_workspace_size",
+            "gcvo_point_shapes_batch", "gcvo_eval_batch_workspace_size", "gcvo_eval_fgh_batch"]
 
 GCVO_MLP_N_PARAMS = 42246
 GCVO_MLP_ROT_SCALE = 0.3
 GCVO_MLP_TRANS_SCALE = 3.0
+
+
+class gcvo_profile(ctypes.Structure):
+    _fields_ = [("pair_kernel_ms", ctypes.c_double), ("launches", ctypes.c_longlong),
+                ("pairs", ctypes.c_longlong), ("source_points", ctypes.c_longlong)]
+
+    def to_dict(self) -> dict:
+        return dict(pair_kernel_ms=self.pair_kernel_ms, launches=self.launches, pairs=self.pairs,
+                    source_points=self.source_points)
 
 
 class gcvo_params(ctypes.Structure):
@@ -56,19 +67,19 @@ class gcvo_params(ctypes.Structure):
                 ("max_iters", ctypes.c_int), ("max_iters_per_stage", ctypes.c_int),
                 ("tol", ctypes.c_double), ("stage_tol", ctypes.c_double), ("precision", ctypes.c_int),
                 ("solver", ctypes.c_int), ("min_step", ctypes.c_double), ("cell_fraction", ctypes.c_double),
-                ("cell_fraction_x", ctypes.c_double)]
+                ("cell_fraction_x", ctypes.c_double), ("profile", ctypes.POINTER(gcvo_profile))]
 
 
 class gcvo_info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("converged", ctypes.c_int), ("iters", ctypes.c_int),
                 ("stages", ctypes.c_int), ("pairs_last", ctypes.c_longlong), ("f", ctypes.c_double),
                 ("g", ctypes.c_double * 6), ("xi_l1", ctypes.c_double),
-                ("stage_iters", ctypes.c_int * GCVO_MAX_STAGES)]
+                ("stage_iters", ctypes.c_int * GCVO_MAX_STAGES), ("damped", ctypes.c_int)]
 
     def to_dict(self) -> dict:
         return dict(status=self.status, converged=bool(self.converged), iters=self.iters, stages=self.stages,
                     pairs_last=self.pairs_last, f=self.f, g=list(self.g), xi_l1=self.xi_l1,
-                    stage_iters=list(self.stage_iters)[:max(self.stages, 0)])
+                    stage_iters=list(self.stage_iters)[:max(self.stages, 0)], damped=self.damped)
 
 
 class gcvo_mlp_batch(ctypes.Structure):
@@ -109,8 +120,8 @@ def load_library() -> ctypes.CDLL:
                                 ctypes.POINTER(gcvo_info), _P, ctypes.c_size_t, _P]
     L.gcvo_batch_workspace_size.argtypes = [ctypes.c_int, _P, _P, pp, ctypes.c_int]
     L.gcvo_batch_workspace_size.restype = ctypes.c_size_t
-    L.gcvo_register_batch.argtypes = [ctypes.c_int, _P, _P, _P, _P, _P, pp, ctypes.c_int, _P,
-                                      ctypes.POINTER(gcvo_info), _P, ctypes.c_size_t, _P]
+    L.gcvo_register_batch.argtypes = [ctypes.c_int, _P, _P, _P, _P, _P, pp, ctypes.c_int, _P, _P, _P,
+                                      ctypes.c_size_t, _P]
     L.gcvo_eval_workspace_size.argtypes = [ctypes.c_longlong, ctypes.c_longlong]
     L.gcvo_eval_workspace_size.restype = ctypes.c_size_t
     L.gcvo_eval_fgh.argtypes = [_P, _P, ctypes.c_longlong, _P, _P, ctypes.c_longlong, _P, ctypes.c_double,
@@ -119,7 +130,7 @@ def load_library() -> ctypes.CDLL:
     L.gcvo_batch_workspace_size_labeled.argtypes = [ctypes.c_int, _P, _P, pp, ctypes.c_int, ctypes.c_int]
     L.gcvo_batch_workspace_size_labeled.restype = ctypes.c_size_t
     L.gcvo_register_batch_labeled.argtypes = [ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.c_int, _P, pp,
-                                              ctypes.c_int, _P, ctypes.POINTER(gcvo_info), _P, ctypes.c_size_t, _P]
+                                              ctypes.c_int, _P, _P, _P, ctypes.c_size_t, _P]
     L.gcvo_eval_workspace_size_labeled.argtypes = [ctypes.c_longlong, ctypes.c_longlong, ctypes.c_int]
     L.gcvo_eval_workspace_size_labeled.restype = ctypes.c_size_t
     L.gcvo_eval_fgh_labeled.argtypes = [_P, _P, _P, ctypes.c_longlong, _P, _P, _P, ctypes.c_longlong, ctypes.c_int,
@@ -129,15 +140,17 @@ def load_library() -> ctypes.CDLL:
     L.gcvo_shapes_workspace_size.restype = ctypes.c_size_t
     L.gcvo_point_shapes.argtypes = [_P, ctypes.c_longlong, ctypes.c_int, ctypes.c_double, _P, _P,
                                     ctypes.c_size_t, _P]
+    L.gcvo_shapes_batch_workspace_size.argtypes = [ctypes.c_int, _P]
+    L.gcvo_shapes_batch_workspace_size.restype = ctypes.c_size_t
+    L.gcvo_point_shapes_batch.argtypes = [ctypes.c_int, _P, _P, ctypes.c_int, ctypes.c_double, _P, _P,
+                                          ctypes.c_size_t, _P]
+    L.gcvo_eval_batch_workspace_size.argtypes = [ctypes.c_int, _P, _P]
+    L.gcvo_eval_batch_workspace_size.restype = ctypes.c_size_t
+    L.gcvo_eval_fgh_batch.argtypes = [ctypes.c_int, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
     L.gcvo_strerror.argtypes = [ctypes.c_int]
     L.gcvo_strerror.restype = ctypes.c_char_p
     L.gcvo_abi_version.argtypes = []
-    L.gcvo_profile_enable.argtypes = [ctypes.c_int]
-    L.gcvo_profile_enable.restype = None
-    L.gcvo_profile_reset.argtypes = []
-    L.gcvo_profile_reset.restype = None
-    L.gcvo_profile_read.argtypes = [_P, _P, _P, _P]
-    L.gcvo_profile_read.restype = None
     L.gcvo_mlp_param_count.argtypes = []
     L.gcvo_mlp_param_count.restype = ctypes.c_longlong
     L.gcvo_mlp_workspace_size.argtypes = [ctypes.c_int, ctypes.c_int]
@@ -272,8 +285,33 @@ def _param_array(params, n_pairs):
     return 0, ctypes.cast(arr, ctypes.POINTER(gcvo_params))
 
 
-def _register_batch(targets, tgt_labels, tgt_off, sources, src_labels, src_off, T_init, params, ws, stream):
+def _device_poses(T, n_pairs: int, device):
+    """Start poses as a float64 CUDA tensor [n_pairs, 16] (None stays None):
+    a CUDA tensor is used in place, host values are copied over."""
+    if T is None:
+        return None
+    torch = _torch()
+    if isinstance(T, torch.Tensor) and T.is_cuda:
+        if T.dtype != torch.float64 or T.numel() != 16 * n_pairs:
+            raise TypeError(f"T_init must be float64 with {n_pairs} x 16 entries")
+        return T.reshape(n_pairs, 16).contiguous()
+    a = np.ascontiguousarray(np.asarray(T, np.float64).reshape(n_pairs, 16))
+    return torch.from_numpy(a).to(device)
+
+
+INFO_BYTES = ctypes.sizeof(gcvo_info)
+
+
+def infos_from_device(buf) -> list:
+    """Info dicts from a device gcvo_info array (uint8 CUDA tensor [n, INFO_BYTES])."""
+    raw = buf.cpu().numpy().tobytes()
+    return [gcvo_info.from_buffer_copy(raw, k * INFO_BYTES).to_dict() for k in range(len(raw) // INFO_BYTES)]
+
+
+def _register_batch(targets, tgt_labels, tgt_off, sources, src_labels, src_off, T_init, params, ws, stream,
+                    device):
     L = load_library()
+    torch = _torch()
     targets = _cloud(targets, "targets")
     sources = _cloud(sources, "sources")
     to = np.ascontiguousarray(tgt_off, dtype=np.int64)
@@ -281,10 +319,9 @@ def _register_batch(targets, tgt_labels, tgt_off, sources, src_labels, src_off, 
     n_pairs = len(to) - 1
     p = params if params is not None else default_params()
     shared, parr = _param_array(p, n_pairs)
-    T0 = None if T_init is None else np.ascontiguousarray(np.asarray(T_init, np.float64).reshape(n_pairs, 16))
-    T0p = T0.ctypes.data_as(_P) if T0 is not None else None
-    T_out = np.zeros((n_pairs, 4, 4))
-    infos = (gcvo_info * n_pairs)()
+    T0 = _device_poses(T_init, n_pairs, targets.device)
+    T_out = torch.empty((n_pairs, 4, 4), dtype=torch.float64, device=targets.device)
+    infos = torch.empty((n_pairs, INFO_BYTES), dtype=torch.uint8, device=targets.device)
     if tgt_labels is None:
         name = "gcvo_register_batch"
         need = L.gcvo_batch_workspace_size(n_pairs, to.ctypes.data_as(_P), so.ctypes.data_as(_P), parr, shared)
@@ -303,33 +340,48 @@ def _register_batch(targets, tgt_labels, tgt_off, sources, src_labels, src_off, 
         holder, wptr, wbytes = ws
     if tgt_labels is None:
         st = L.gcvo_register_batch(n_pairs, _ptr(targets), to.ctypes.data_as(_P), _ptr(sources),
-                                   so.ctypes.data_as(_P), T0p, parr, shared, T_out.ctypes.data_as(_P), infos,
+                                   so.ctypes.data_as(_P), _ptr(T0), parr, shared, _ptr(T_out), _ptr(infos),
                                    ctypes.c_void_p(wptr), wbytes, _stream_handle(stream))
     else:
         st = L.gcvo_register_batch_labeled(n_pairs, _ptr(targets), _ptr(tl), to.ctypes.data_as(_P), _ptr(sources),
-                                           _ptr(sl), so.ctypes.data_as(_P), dim, T0p, parr, shared,
-                                           T_out.ctypes.data_as(_P), infos, ctypes.c_void_p(wptr), wbytes,
+                                           _ptr(sl), so.ctypes.data_as(_P), dim, _ptr(T0), parr, shared,
+                                           _ptr(T_out), _ptr(infos), ctypes.c_void_p(wptr), wbytes,
                                            _stream_handle(stream))
-    del holder
     if st != GCVO_OK:
         raise GcvoError(st, name)
-    return T_out, [i.to_dict() for i in infos]
+    # the outputs are written on the stream after the call returns: keep the
+    # workspace and the start poses alive until the stream has reached them
+    s = torch.cuda.current_stream() if stream is None else stream
+    if holder is not None:
+        holder.record_stream(s)
+    if T0 is not None:
+        T0.record_stream(s)
+    del holder
+    if device:
+        return T_out, infos
+    return T_out.cpu().numpy(), infos_from_device(infos)
 
 
-def gcvo_register_batch(targets, tgt_off, sources, src_off, T_init=None, params=None, ws=None, stream=None):
+def gcvo_register_batch(targets, tgt_off, sources, src_off, T_init=None, params=None, ws=None, stream=None,
+                        device: bool = False):
     """Register len(tgt_off) - 1 pairs held in two concatenated clouds.
 
     targets / sources: float32 CUDA [sum, 3]; tgt_off / src_off: int64 host
-    offsets.  Returns (T [n_pairs, 4, 4], list of info dicts).
+    offsets; T_init: None (identity), a float64 CUDA tensor [n_pairs, 4, 4]
+    (used in place) or host values (copied to the device).  Returns (T, infos):
+    with device=True a float64 CUDA tensor [n_pairs, 4, 4] and a uint8 CUDA
+    tensor of gcvo_info records (see infos_from_device), both written on the
+    stream; otherwise numpy [n_pairs, 4, 4] and a list of info dicts.
     """
-    return _register_batch(targets, None, tgt_off, sources, None, src_off, T_init, params, ws, stream)
+    return _register_batch(targets, None, tgt_off, sources, None, src_off, T_init, params, ws, stream, device)
 
 
 def gcvo_register_batch_labeled(targets, tgt_labels, tgt_off, sources, src_labels, src_off, T_init=None,
-                                params=None, ws=None, stream=None):
+                                params=None, ws=None, stream=None, device: bool = False):
     """gcvo_register_batch with per-point label vectors (float32 CUDA [sum, d],
     d <= 4) weighting each pair by <l^X_i, l^Z_j>."""
-    return _register_batch(targets, tgt_labels, tgt_off, sources, src_labels, src_off, T_init, params, ws, stream)
+    return _register_batch(targets, tgt_labels, tgt_off, sources, src_labels, src_off, T_init, params, ws, stream,
+                           device)
 
 
 def gcvo_batch_workspace_size_labeled(tgt_off, src_off, params, label_dim: int) -> int:
@@ -432,20 +484,87 @@ def gcvo_point_shapes(xyz, knn: int = 10, rho: float = 0.01, ws=None, stream=Non
     return out
 
 
-def gcvo_profile_enable(on: bool = True) -> None:
-    load_library().gcvo_profile_enable(int(bool(on)))
+def gcvo_point_shapes_batch(xyz, off, knn: int = 10, rho: float = 0.01, stream=None):
+    """Shapes of the clouds xyz[off[k]:off[k+1]] (float32 CUDA [sum, 3], host
+    offsets): float32 CUDA [6 * sum], cloud k's [6, n_k] block at 6 * off[k]."""
+    torch = _torch()
+    L = load_library()
+    xyz = _cloud(xyz, "xyz")
+    o = np.ascontiguousarray(off, dtype=np.int64)
+    out = torch.empty(6 * xyz.shape[0], dtype=torch.float32, device=xyz.device)
+    need = L.gcvo_shapes_batch_workspace_size(len(o) - 1, o.ctypes.data_as(_P))
+    holder, wptr, wbytes = workspace(max(need, 256), xyz.device)
+    st = L.gcvo_point_shapes_batch(len(o) - 1, _ptr(xyz), o.ctypes.data_as(_P), int(knn), float(rho), _ptr(out),
+                                   ctypes.c_void_p(wptr), wbytes, _stream_handle(stream))
+    if st != GCVO_OK:
+        raise GcvoError(st, "gcvo_point_shapes_batch")
+    holder.record_stream(torch.cuda.current_stream() if stream is None else stream)
+    return out
 
 
-def gcvo_profile_reset() -> None:
-    load_library().gcvo_profile_reset()
+def shape_block(shapes, off, k: int):
+    """Cloud k's [6, n_k] view of a gcvo_point_shapes_batch output."""
+    a, b = int(off[k]), int(off[k + 1])
+    return shapes[6 * a:6 * b].view(6, b - a)
 
 
-def gcvo_profile_read() -> dict:
-    ms = ctypes.c_double()
-    launches, pairs, points = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_longlong()
-    load_library().gcvo_profile_read(ctypes.byref(ms), ctypes.byref(launches), ctypes.byref(pairs),
-                                     ctypes.byref(points))
-    return dict(pair_kernel_ms=ms.value, launches=launches.value, pairs=pairs.value, source_points=points.value)
+@dataclass
+class EvalBatch:
+    f: object        # float64 CUDA [n]
+    g: object        # float64 CUDA [n, 6]
+    H: object        # float64 CUDA [n, 6, 6]
+    npairs: object   # int64 CUDA [n]
+    status: object   # int32 CUDA [n]
+
+
+def gcvo_eval_fgh_batch(targets, tgt_shapes, tgt_off, sources, src_shapes, src_off, T, length_scales,
+                        cutoff_scale: float = 3.0, sigma2: float = 1.0, precision: int = GCVO_PRECISION_FP32,
+                        stream=None) -> EvalBatch:
+    """Evaluations of several pairs in one pass: shapes in the layout of
+    gcvo_point_shapes_batch, T None (identity) or float64 CUDA [n, 4, 4] (or
+    host values, copied over), length_scales host [n].  Outputs stay on the
+    device."""
+    torch = _torch()
+    L = load_library()
+    targets = _cloud(targets, "targets")
+    sources = _cloud(sources, "sources")
+    to = np.ascontiguousarray(tgt_off, dtype=np.int64)
+    so = np.ascontiguousarray(src_off, dtype=np.int64)
+    n = len(to) - 1
+    for name, sh, rows in (("tgt_shapes", tgt_shapes, targets.shape[0]), ("src_shapes", src_shapes, sources.shape[0])):
+        if not sh.is_cuda or sh.dtype != torch.float32 or sh.numel() != 6 * rows:
+            raise TypeError(f"{name} must be a float32 CUDA tensor of 6 x {rows} values")
+    ells = np.ascontiguousarray(np.broadcast_to(np.asarray(length_scales, np.float64), (n,)))
+    T0 = _device_poses(T, n, targets.device)
+    dev = targets.device
+    out = EvalBatch(torch.empty(n, dtype=torch.float64, device=dev), torch.empty((n, 6), dtype=torch.float64, device=dev),
+                    torch.empty((n, 6, 6), dtype=torch.float64, device=dev),
+                    torch.empty(n, dtype=torch.int64, device=dev), torch.empty(n, dtype=torch.int32, device=dev))
+    need = L.gcvo_eval_batch_workspace_size(n, to.ctypes.data_as(_P), so.ctypes.data_as(_P))
+    holder, wptr, wbytes = workspace(max(need, 256), dev)
+    st = L.gcvo_eval_fgh_batch(n, _ptr(targets), _ptr(tgt_shapes.contiguous()), to.ctypes.data_as(_P), _ptr(sources),
+                               _ptr(src_shapes.contiguous()), so.ctypes.data_as(_P), _ptr(T0),
+                               ells.ctypes.data_as(_P), float(cutoff_scale), float(sigma2), int(precision),
+                               _ptr(out.f), _ptr(out.g), _ptr(out.H), _ptr(out.npairs), _ptr(out.status),
+                               ctypes.c_void_p(wptr), wbytes, _stream_handle(stream))
+    if st != GCVO_OK:
+        raise GcvoError(st, "gcvo_eval_fgh_batch")
+    s = torch.cuda.current_stream() if stream is None else stream
+    holder.record_stream(s)
+    if T0 is not None:
+        T0.record_stream(s)
+    return out
+
+
+def profiled(params, profile: gcvo_profile):
+    """Copy of a parameter set (or list of them) whose calls add their
+    pair-kernel measurement to ``profile``."""
+    def one(p):
+        q = gcvo_params()
+        ctypes.pointer(q)[0] = p
+        q.profile = ctypes.pointer(profile)
+        return q
+    return one(params) if isinstance(params, gcvo_params) else [one(p) for p in params]
 
 
 # ------------------------------------------------------------ warm-start network
@@ -497,16 +616,15 @@ def gcvo_mlp_workspace_size(n_pairs: int, n_points: int) -> int:
 
 def gcvo_mlp_forward(batch: MlpBatch, w_bf16, poses: bool = False, ws=None, stream=None):
     """Network outputs (float32 CUDA [B, 6]) and, with poses=True, the predicted
-    poses exp(xi^) as a float64 numpy [B, 4, 4] array."""
+    poses exp(xi^) as a float64 CUDA tensor [B, 4, 4]."""
     torch = _torch()
     L = load_library()
     B, P = batch.c.n_pairs, batch.c.n_points
     out = torch.empty((B, 6), dtype=torch.float32, device=batch.targets.device)
     holder, wptr, wbytes = ws if ws is not None else workspace(max(gcvo_mlp_workspace_size(B, P), 256),
                                                               batch.targets.device)
-    T = np.zeros((B, 4, 4)) if poses else None
-    st = L.gcvo_mlp_forward(ctypes.byref(batch.c), _ptr(w_bf16), _ptr(out),
-                            T.ctypes.data_as(_P) if T is not None else None, ctypes.c_void_p(wptr), wbytes,
+    T = torch.empty((B, 4, 4), dtype=torch.float64, device=batch.targets.device) if poses else None
+    st = L.gcvo_mlp_forward(ctypes.byref(batch.c), _ptr(w_bf16), _ptr(out), _ptr(T), ctypes.c_void_p(wptr), wbytes,
                             _stream_handle(stream))
     del holder
     if st != GCVO_OK:

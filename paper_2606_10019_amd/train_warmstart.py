@@ -71,7 +71,9 @@ def evaluate(net, specs, refs, log, refine_length_scale=None):
     t_plain = time.perf_counter() - t0
     t0 = time.perf_counter()
     Tw, iw, rec = warmstart.register_warm(net, ps, params, refine_length_scale)
+    Tw = Tw.cpu().numpy()
     t_warm = time.perf_counter() - t0
+    rec["T0"] = rec["T0"].cpu().numpy()
 
     def ok(T, info, R):
         return info["converged"] and rot_deg(T, R) <= 1e-3 and np.linalg.norm(T[:3, 3] - R[:3, 3]) <= 1e-5

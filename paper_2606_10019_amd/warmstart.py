@@ -243,8 +243,9 @@ def train(net: Network, ps: PairSet, labels: np.ndarray, steps: int, batch: int 
 
 # ------------------------------------------------------------------ warm-started registration
 
-def predict(net: Network, ps: PairSet, seed: int = 0) -> np.ndarray:
-    """Predicted registration poses [B, 4, 4] for every pair of the set."""
+def predict(net: Network, ps: PairSet, seed: int = 0):
+    """Predicted registration poses of every pair of the set (float64 CUDA
+    tensor [B, 4, 4]: they stay on the device as the refine's start poses)."""
     rng = np.random.default_rng(seed)
     bi = batch_inputs(ps, np.arange(ps.n), rng)
     _, T = gcvo.gcvo_mlp_forward(bi, net.wb, poses=True)
@@ -260,33 +261,54 @@ def _params_copy(p, **kw):
     return q
 
 
-def objective_at(ps: PairSet, poses, params, length_scales):
-    """f at the given poses (None = identity) with each pair's length scale:
-    one iteration of the solver, whose reported f is the objective at its
-    starting pose."""
-    ep = [_params_copy(p, length_scale=ell, length_scale_min=ell, max_iters=1, max_iters_per_stage=1)
-          for p, ell in zip(params, length_scales)]
-    _, infos = gcvo.gcvo_register_batch(ps.targets, ps.tgt_off, ps.sources, ps.src_off, poses, ep)
-    return np.array([i["f"] for i in infos])
+def objective_at(ps: PairSet, shapes, poses, length_scales, params):
+    """f of every pair at the given poses (None: identity; a float64 CUDA
+    tensor [B, 4, 4] otherwise) with each pair's length scale, from one batched
+    evaluation over the pairs' shapes (a (target, source) pair of
+    gcvo_point_shapes_batch outputs).  Device float64 [B]."""
+    p0 = params[0]
+    return gcvo.gcvo_eval_fgh_batch(ps.targets, shapes[0], ps.tgt_off, ps.sources, shapes[1], ps.src_off, poses,
+                                    length_scales, p0.cutoff_scale, p0.sigma2, p0.precision).f
+
+
+def _subset(ps: PairSet, ids):
+    """The clouds of the chosen pairs, concatenated anew on the device."""
+    import torch
+    t = torch.cat([ps.targets[ps.tgt_off[k]:ps.tgt_off[k + 1]] for k in ids])
+    s = torch.cat([ps.sources[ps.src_off[k]:ps.src_off[k + 1]] for k in ids])
+    to = np.cumsum([0] + [int(ps.tgt_off[k + 1] - ps.tgt_off[k]) for k in ids]).astype(np.int64)
+    so = np.cumsum([0] + [int(ps.src_off[k + 1] - ps.src_off[k]) for k in ids]).astype(np.int64)
+    return t, to, s, so
 
 
 def register_warm(net: Network, ps: PairSet, params, refine_length_scale: float | None = None, seed: int = 0):
     """Warm-started batch registration with the objective fallback.  params:
     one gcvo_params per pair (the plain schedule); refine_length_scale, when
-    given, starts the refine's schedule there instead.  Returns (T [B,4,4],
-    infos, record) where record holds the predictions, which pairs fell back,
-    and the two objectives compared."""
+    given, starts the refine's schedule there instead.  The predicted poses,
+    the refined poses and the objectives stay on the device; the host reads
+    back only the run summaries and two objectives per pair to pick the
+    fallbacks.  Returns (T float64 CUDA [B, 4, 4], infos, record) where record
+    holds the predictions, which pairs fell back, and the two objectives."""
+    import torch
     T0 = predict(net, ps, seed)
     rp = [p if refine_length_scale is None else
           _params_copy(p, length_scale=max(min(refine_length_scale, p.length_scale), p.length_scale_min))
           for p in params]
-    T, infos = gcvo.gcvo_register_batch(ps.targets, ps.tgt_off, ps.sources, ps.src_off, T0, rp)
-    ell0 = [p.length_scale for p in params]
-    f_ref = objective_at(ps, T, params, ell0)
-    f_id = objective_at(ps, None, params, ell0)
-    fall = [k for k in range(ps.n) if not infos[k]["converged"] or f_ref[k] < f_id[k]]
-    for k in fall:
-        tg = ps.targets[ps.tgt_off[k]:ps.tgt_off[k + 1]]
-        sr = ps.sources[ps.src_off[k]:ps.src_off[k + 1]]
-        T[k], infos[k] = gcvo.gcvo_register(tg, sr, None, params[k])
-    return T, infos, dict(T0=T0, fallback=fall, f_refined=f_ref.tolist(), f_identity=f_id.tolist())
+    T, info_dev = gcvo.gcvo_register_batch(ps.targets, ps.tgt_off, ps.sources, ps.src_off, T0, rp, device=True)
+    p0 = params[0]
+    shapes = (gcvo.gcvo_point_shapes_batch(ps.targets, ps.tgt_off, p0.knn, p0.eig_ratio_min),
+              gcvo.gcvo_point_shapes_batch(ps.sources, ps.src_off, p0.knn, p0.eig_ratio_min))
+    ell0 = np.array([p.length_scale for p in params])
+    f_ref = objective_at(ps, shapes, T, ell0, params)
+    f_id = objective_at(ps, shapes, None, ell0, params)
+    infos = gcvo.infos_from_device(info_dev)
+    fr, fi = f_ref.cpu().numpy(), f_id.cpu().numpy()
+    fall = [k for k in range(ps.n) if not infos[k]["converged"] or fr[k] < fi[k]]
+    if fall:
+        t, to, s, so = _subset(ps, fall)
+        Tf, info_f = gcvo.gcvo_register_batch(t, to, s, so, None, [params[k] for k in fall], device=True)
+        idx = torch.as_tensor(fall, device=T.device)
+        T[idx] = Tf
+        for r, k in enumerate(gcvo.infos_from_device(info_f)):
+            infos[fall[r]] = k
+    return T, infos, dict(T0=T0, fallback=fall, f_refined=fr.tolist(), f_identity=fi.tolist())

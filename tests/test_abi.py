@@ -29,9 +29,11 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     # sizes implied by the header's field order on x86-64
-    assert ctypes.sizeof(gcvo.gcvo_params) == 8 * 4 + 8 + 8 * 2 + 8 + 8 * 2 + 8 + 8 + 8 + 8
-    assert ctypes.sizeof(gcvo.gcvo_info) == 4 * 4 + 8 + 8 + 48 + 8 + 4 * 16
-    assert gcvo.load_library().gcvo_abi_version() == 104
+    assert ctypes.sizeof(gcvo.gcvo_params) == 8 * 4 + 8 + 8 * 2 + 8 + 8 * 2 + 8 + 8 + 8 + 8 + 8
+    assert ctypes.sizeof(gcvo.gcvo_info) == 4 * 4 + 8 + 8 + 48 + 8 + 4 * 16 + 4 + 4   # damped, then padding
+    assert ctypes.sizeof(gcvo.gcvo_profile) == 8 * 4
+    assert gcvo.load_library().gcvo_abi_version() == 200
+    assert not gcvo.default_params().profile          # no measurement unless asked for
 
 
 def test_default_params_and_strerror():
@@ -78,6 +80,32 @@ def test_batch_workspace_covers_members():
     off = np.array([0, 1000, 3000, 3500], dtype=np.int64)
     whole = gcvo.gcvo_batch_workspace_size(off, off, p)
     assert whole > gcvo.gcvo_workspace_size(2000, 2000, p)
+    # pairs too small to run still get an output slot: the size is positive
+    tiny = np.array([0, 3, 5], dtype=np.int64)
+    assert gcvo.gcvo_batch_workspace_size(tiny, tiny, p) > 0
+
+
+def test_batched_shapes_and_eval_sizes_and_validation():
+    import numpy as np
+    L = gcvo.load_library()
+    off = np.array([0, 1000, 3000], dtype=np.int64)
+    op = off.ctypes.data_as(ctypes.c_void_p)
+    one = np.array([0, 2000], dtype=np.int64)
+    assert L.gcvo_shapes_batch_workspace_size(2, op) > L.gcvo_shapes_workspace_size(2000)
+    assert L.gcvo_shapes_batch_workspace_size(0, op) == 0
+    assert L.gcvo_shapes_batch_workspace_size(2, None) == 0
+    assert L.gcvo_eval_batch_workspace_size(2, op, op) > 0
+    assert L.gcvo_eval_batch_workspace_size(1, one.ctypes.data_as(ctypes.c_void_p), None) == 0
+    # a cloud with fewer points than knn is refused before any device work
+    small = np.array([0, 1000, 1005], dtype=np.int64)
+    st = L.gcvo_point_shapes_batch(2, ctypes.c_void_p(16), small.ctypes.data_as(ctypes.c_void_p), 10, 0.1,
+                                   ctypes.c_void_p(16), None, 0, None)
+    assert st == gcvo.GCVO_ERR_TOO_FEW_POINTS
+    ell = np.array([0.3, -1.0])
+    st = L.gcvo_eval_fgh_batch(2, ctypes.c_void_p(16), ctypes.c_void_p(16), op, ctypes.c_void_p(16),
+                               ctypes.c_void_p(16), op, None, ell.ctypes.data_as(ctypes.c_void_p), 3.0, 1.0, 0,
+                               None, None, None, None, None, None, 0, None)
+    assert st == gcvo.GCVO_ERR_INVALID                # a non-positive length scale
 
 
 def test_register_rejects_bad_arguments_without_gpu_work():
@@ -131,13 +159,12 @@ def test_labeled_and_isotropic_sizes_and_validation():
     assert 0 < gcvo.gcvo_workspace_size(2000, 2000, iso) < gcvo.gcvo_workspace_size(2000, 2000, p)
     assert L.gcvo_eval_workspace_size_labeled(100, 100, 2) > L.gcvo_eval_workspace_size(100, 100)
     assert L.gcvo_eval_workspace_size_labeled(100, 100, 5) == 0
-    T = np.zeros((1, 16))
-    info = (gcvo.gcvo_info * 1)()
     op = off.ctypes.data_as(ctypes.c_void_p)
     # labelled calls without labels, or with a bad width, fail before any device work
+    # (the pose and info outputs are device pointers the call never touches here)
     for dim, tl in ((2, None), (0, 16), (5, 16)):
         st = L.gcvo_register_batch_labeled(1, ctypes.c_void_p(16), tl, op, ctypes.c_void_p(16), tl, op, dim, None,
-                                           ctypes.byref(p), 1, T.ctypes.data_as(ctypes.c_void_p), info, None, 0,
+                                           ctypes.byref(p), 1, ctypes.c_void_p(16), ctypes.c_void_p(16), None, 0,
                                            None)
         assert st == gcvo.GCVO_ERR_INVALID, dim
     f = ctypes.c_double()

@@ -90,6 +90,8 @@ def test_forward_and_poses_match_oracle():
     pb = problem(1)
     note("mlp forward 5 ragged pairs, P=300")
     out, T = gcvo.gcvo_mlp_forward(gpu_batch(pb), bf16_tensor(pb["w64"]), poses=True)
+    assert T.is_cuda                      # predicted poses stay on the device
+    T = T.cpu().numpy()
     ref = M.forward(pb["w64"], pb["S"], pb["T"])
     err = np.max(np.abs(out.cpu().numpy() - ref))
     note(f"  max |out - oracle| {err:.2e} (scale {np.max(np.abs(ref)):.2f})")

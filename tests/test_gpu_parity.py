@@ -145,6 +145,10 @@ def test_register_config2_full_size_matches_oracle():
          f"err {dr:.2e} deg {dt:.2e} m")
     assert info["converged"]
     assert dr < ROT_GATE_DEG and dt < TRANS_GATE_M
+    # the annealing schedule follows the oracle's stage by stage (a stage test
+    # whose step norm lands within FP32 rounding of its threshold may move by one)
+    assert info["stages"] == len(ref["prod_stage_iters"])
+    assert all(abs(a - b) <= 1 for a, b in zip(info["stage_iters"], ref["prod_stage_iters"]))
 
 
 def test_register_is_bitwise_deterministic():

@@ -60,19 +60,6 @@ def test_newton_reaches_oracle_fixed_point(inst):
         assert abs(info["iters"] - o.iters) <= 1
 
 
-def test_newton_lidar_pair():
-    spec = synth.make_config2(0)
-    Tref, g = ref(spec)
-    note("newton config2 instance 0")
-    T, info = gcvo.gcvo_register(to_dev(spec.target), to_dev(spec.source), None,
-                                 gcvo.params_from_spec(spec, solver=gcvo.GCVO_SOLVER_NEWTON))
-    dr, dt = rot_err_deg(T, Tref), trans_err_m(T, Tref)
-    note(f"  iters {info['iters']} stages {info['stage_iters']} (GN {g['prod_stage_iters']}) err {dr:.2e} deg {dt:.2e} m")
-    assert info["converged"]
-    assert dr < ROT_GATE_DEG and dt < TRANS_GATE_M
-    assert info["iters"] < g["prod_iters"]
-
-
 def test_first_order_fp64_follows_oracle():
     spec = synth.make_config1(0)
     Tref, g = ref(spec)

@@ -60,6 +60,8 @@ def test_register_config3_fp32_and_fp64_match_oracle(inst):
              f"err {dr:.2e} deg {dt:.2e} m")
         assert info["converged"]
         assert dr < ROT_GATE_DEG and dt < TRANS_GATE_M
+        assert info["stages"] == len(ref["prod_stage_iters"])
+        assert all(abs(a - b) <= 2 for a, b in zip(info["stage_iters"], ref["prod_stage_iters"]))
         poses[name] = (T, info)
     # The FP64 path follows the oracle's iterates (a stop test that lands within
     # rounding of its threshold may move one iteration).
