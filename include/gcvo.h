@@ -248,6 +248,25 @@ int gcvo_eval_fgh(const float *tgt_xyz, const float *tgt_shape6, long long n_tgt
                   long long *n_pairs, void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * gcvo_eval_fgh for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid allocation): the same
+ * evaluation, the same kernels and bitwise the same results, with a library
+ * scratch array of GCVO_NOALLOC_SCRATCH_BYTES per GPU in place of the
+ * workspace, so the call allocates nothing (the array is part of the loaded
+ * library; each GPU holds its own copy until the process ends).  Sizes whose
+ * gcvo_eval_workspace_size exceeds the scratch (about 240k points per cloud
+ * at equal sizes) return GCVO_ERR_CAPACITY before any device work.  Every call
+ * on a GPU uses that GPU's one array: calls that overlap on a device (other
+ * threads, other streams) race and must be serialised by the caller.  The call
+ * waits on `stream`, so calls from one thread never overlap.
+ */
+#define GCVO_NOALLOC_SCRATCH_BYTES (64LL << 20)
+int gcvo_eval_fgh_noalloc(const float *tgt_xyz, const float *tgt_shape6, long long n_tgt, const float *src_xyz,
+                          const float *src_shape6, long long n_src, const double *T, double length_scale,
+                          double cutoff, double sigma2, int precision, double *f, double *g, double *H,
+                          long long *n_pairs, void *stream);
+
+/*
  * Labelled pairs (eq. (rkhs_loss)): every point carries a label vector l in
  * R^label_dim (1 <= label_dim <= GCVO_MAX_LABEL_DIM: intensities, colours,
  * semantic class scores, one-hot classes), and each pair's kernel is weighted

@@ -783,6 +783,54 @@ int gcvo_register_batch_labeled(int n_pairs, const float *tgt_xyz, const float *
 
 size_t gcvo_eval_workspace_size(long long n_tgt, long long n_src) { return eval_workspace(n_tgt, n_src, 0); }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------- evaluation without allocation
+
+namespace {
+
+// Device scratch of gcvo_eval_fgh_noalloc: one array per GPU, in place of the
+// caller's workspace.  Host code never passes the array's name to a kernel or
+// a copy (on the host it only stands for the device symbol); it uses the
+// device address resolved once per device below.
+constexpr size_t kScratchBytes = size_t(GCVO_NOALLOC_SCRATCH_BYTES);
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's scratch address (resolved on the first call there).
+int scratch_of_current_device(void **ptr) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return GCVO_ERR_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return GCVO_ERR_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return GCVO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gcvo_eval_fgh_noalloc(const float *tgt_xyz, const float *tgt_shape6, long long n_tgt, const float *src_xyz,
+                          const float *src_shape6, long long n_src, const double *T, double length_scale,
+                          double cutoff, double sigma2, int precision, double *f, double *g, double *H,
+                          long long *n_pairs, void *stream) {
+    if (n_tgt < 0 || n_src < 0) return GCVO_ERR_INVALID;
+    const size_t need = eval_workspace(n_tgt, n_src, 0);
+    if (need == 0 || need > kScratchBytes) return GCVO_ERR_CAPACITY;
+    void *ws = nullptr;
+    const int rc = scratch_of_current_device(&ws);
+    if (rc) return rc;
+    return eval_fgh(tgt_xyz, tgt_shape6, nullptr, n_tgt, src_xyz, src_shape6, nullptr, n_src, 0, T, length_scale,
+                    cutoff, sigma2, precision, f, g, H, n_pairs, ws, kScratchBytes, stream);
+}
 
 int gcvo_eval_fgh(const float *tgt_xyz, const float *tgt_shape6, long long n_tgt, const float *src_xyz,
                   const float *src_shape6, long long n_src, const double *T, double length_scale, double cutoff,

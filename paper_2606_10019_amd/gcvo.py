@@ -44,7 +44,9 @@ EXPORTED = ["gcvo_default_params", "gcvo_workspace_size", "gcvo_register", "gcvo
             "gcvo_mlp_param_count", "gcvo_mlp_workspace_size", "gcvo_mlp_forward", "gcvo_mlp_loss_grad",
             "gcvo_mlp_adam", "gcvo_batch_workspace_size_labeled", "gcvo_register_batch_labeled",
             "gcvo_eval_workspace_size_labeled", "gcvo_eval_fgh_labeled", "gcvo_shapes_batch_workspace_size",
-            "gcvo_point_shapes_batch", "gcvo_eval_batch_workspace_size", "gcvo_eval_fgh_batch"]
+            "gcvo_point_shapes_batch", "gcvo_eval_batch_workspace_size", "gcvo_eval_fgh_batch",
+            "gcvo_eval_fgh_noalloc"]
+GCVO_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 GCVO_MLP_N_PARAMS = 42246
 GCVO_MLP_ROT_SCALE = 0.3
@@ -140,6 +142,8 @@ def load_library() -> ctypes.CDLL:
     L.gcvo_shapes_workspace_size.restype = ctypes.c_size_t
     L.gcvo_point_shapes.argtypes = [_P, ctypes.c_longlong, ctypes.c_int, ctypes.c_double, _P, _P,
                                     ctypes.c_size_t, _P]
+    L.gcvo_eval_fgh_noalloc.argtypes = [_P, _P, ctypes.c_longlong, _P, _P, ctypes.c_longlong, _P, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_int, _P, _P, _P, _P, _P]
     L.gcvo_shapes_batch_workspace_size.argtypes = [ctypes.c_int, _P]
     L.gcvo_shapes_batch_workspace_size.restype = ctypes.c_size_t
     L.gcvo_point_shapes_batch.argtypes = [ctypes.c_int, _P, _P, ctypes.c_int, ctypes.c_double, _P, _P,
@@ -448,6 +452,31 @@ def gcvo_eval_fgh(target, tgt_shape6, source, src_shape6, T, length_scale: float
                   sigma2: float = 1.0, precision: int = GCVO_PRECISION_FP32, ws=None, stream=None) -> EvalResult:
     return _eval_fgh(target, tgt_shape6, None, source, src_shape6, None, T, length_scale, cutoff, sigma2, precision,
                      ws, stream)
+
+
+def gcvo_eval_fgh_noalloc(target, tgt_shape6, source, src_shape6, T, length_scale: float, cutoff: float,
+                          sigma2: float = 1.0, precision: int = GCVO_PRECISION_FP32, stream=None) -> EvalResult:
+    """gcvo_eval_fgh with the library's per-GPU scratch instead of a workspace
+    (no device allocation; sizes beyond GCVO_NOALLOC_SCRATCH_BYTES raise
+    GCVO_ERR_CAPACITY; overlapping calls on one GPU race)."""
+    L = load_library()
+    target = _cloud(target, "target")
+    source = _cloud(source, "source")
+    nt, ns = target.shape[0], source.shape[0]
+    ts = _shape6(tgt_shape6, nt, "tgt_shape6")
+    ss = _shape6(src_shape6, ns, "src_shape6")
+    Tm = _pose(T)
+    f = ctypes.c_double()
+    g = np.zeros(6)
+    H = np.zeros((6, 6))
+    npairs = ctypes.c_longlong()
+    st = L.gcvo_eval_fgh_noalloc(_ptr(target), _ptr(ts), nt, _ptr(source), _ptr(ss), ns, Tm.ctypes.data_as(_P),
+                                 float(length_scale), float(cutoff), float(sigma2), int(precision), ctypes.byref(f),
+                                 g.ctypes.data_as(_P), H.ctypes.data_as(_P), ctypes.byref(npairs),
+                                 _stream_handle(stream))
+    if st != GCVO_OK:
+        raise GcvoError(st, "gcvo_eval_fgh_noalloc")
+    return EvalResult(f.value, g, H, npairs.value)
 
 
 def gcvo_eval_fgh_labeled(target, tgt_shape6, tgt_labels, source, src_shape6, src_labels, T, length_scale: float,
