@@ -41,10 +41,10 @@ from . import gcvo
 HERE = os.path.dirname(os.path.abspath(__file__))
 WEIGHTS = os.path.join(HERE, "weights", "warmstart_lidar.npz")
 N_POINTS = 1024
-INPUT_SCALE = 20.0
+INPUT_SCALE = 40.0
 MAX_YAW_DEG = 15.0
 MAX_TRANS_M = 3.0
-CROP_M = 40.0
+CROP_M = 80.0
 
 SHAPES = [(64, 3), (64,), (128, 64), (128,), (128, 256), (128,), (6, 128), (6,)]
 
