@@ -152,15 +152,28 @@ def objects_leg(gcvo, synth, golden, dev, rot_err_deg, trans_err_m, n_pairs=256)
     prof = gcvo.gcvo_profile()
     gcvo.gcvo_register_batch(tgt, to, src, so, None, gcvo.profiled(params, prof), ws=ws)
     rl = roofline(prof.to_dict())
+    # the same pairs registered one call each (same kernels; poses bitwise equal)
+    sws = gcvo.workspace(max(gcvo.gcvo_workspace_size(len(s.target), len(s.source), p)
+                             for s, p in zip(specs, params)), dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    single = [gcvo.gcvo_register(tgt[int(to[k]):int(to[k + 1])], src[int(so[k]):int(so[k + 1])], None, params[k],
+                                 ws=sws) for k in range(n_pairs)]
+    torch.cuda.synchronize()
+    ds = time.perf_counter() - t0
+    same = sum(1 for k in range(n_pairs) if np.array_equal(single[k][0], T[k]))
     out = {"workload": f"object_pairs_{n_pairs}_1k_to_50k_points", "pairs": n_pairs,
            "source_points": int(so[-1]), "seconds_per_batch": dt, "converged": converged,
            "registrations_per_s_converged": converged / dt, "oracle_sample": sample,
            "oracle_sample_in_gate": in_gate, "oracle_sample_sizes": sizes,
            "mean_iterations": float(np.mean([i["iters"] for i in infos])),
-           "iterations_at_cap": sum(1 for i in infos if not i["converged"]), "roofline": rl}
-    print(f"[bench] objects: {dt:.2f} s for {n_pairs} pairs, {converged} converged, oracle sample "
-          f"{in_gate}/{sample} in gate; pair kernel {rl['avg_launch_us']:.1f} us/launch, frac {rl['frac']:.4f}",
-          file=sys.stderr, flush=True)
+           "iterations_at_cap": sum(1 for i in infos if not i["converged"]), "roofline": rl,
+           "single_calls": {"seconds": ds, "registrations_per_s_converged": converged / ds,
+                            "poses_bitwise_equal_to_batch": same},
+           "batch_over_single": ds / dt}
+    print(f"[bench] objects: {dt:.2f} s for {n_pairs} pairs ({ds:.2f} s as single calls), {converged} converged, "
+          f"oracle sample {in_gate}/{sample} in gate; pair kernel {rl['avg_launch_us']:.1f} us/launch, "
+          f"frac {rl['frac']:.4f}", file=sys.stderr, flush=True)
     return out
 
 
@@ -490,9 +503,11 @@ def main():
         b_elapsed = time.perf_counter() - tb
         b_pass = sum(1 for T, infos in b_out for i in range(N_INSTANCES) if infos[i]["converged"]
                      and rot_err_deg(T[i], refs[i]) <= 1e-3 and trans_err_m(T[i], refs[i]) <= 1e-5)
+        bprof = gcvo.gcvo_profile()
+        gcvo.gcvo_register_batch(tgt_cat, to, src_cat, so, None, gcvo.profiled(params, bprof), ws=bws)
         batch = {"pairs_per_call": N_INSTANCES, "calls": b_calls, "registrations_per_s": b_pass / b_elapsed,
                  "registrations_in_gate": b_pass, "registrations_total": b_calls * N_INSTANCES,
-                 "ms_per_call": 1e3 * b_elapsed / b_calls}
+                 "ms_per_call": 1e3 * b_elapsed / b_calls, "roofline": roofline(bprof.to_dict())}
         print(f"[bench] batched: {b_calls} calls x {N_INSTANCES} pairs in {b_elapsed:.3f} s, {b_pass} within the "
               "gate", file=sys.stderr, flush=True)
 

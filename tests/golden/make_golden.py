@@ -77,12 +77,43 @@ def c5_eval_references(data, n_pairs):
         write(data)
 
 
+def c4_large(data, instances):
+    """Large object pairs of the batch (about 10k points; the oracle's grid
+    search makes them affordable).  The reference continues the production run
+    from its stopping pose at the final length scale to ||xi||_1 < 1e-12: the
+    same iterates as a reference run from the start, whose annealed stages
+    repeat the production run's, without recomputing the coarse stages (about
+    10^8 pairs per iteration here)."""
+    for i in instances:
+        spec = synth.make_config4(i)
+        t0 = time.time()
+        prod = O.register_spec(spec)
+        entry = dict(config=4, instance=i, digest=spec.digest(), n_target=len(spec.target),
+                     n_source=len(spec.source), params=spec.params(), prod_iters=prod.iters,
+                     prod_stage_iters=prod.stage_iters, prod_converged=prod.converged,
+                     T_prod=prod.T.reshape(-1).tolist(), ref_start="production pose, final length scale")
+        if prod.converged:
+            ref = O.register_spec(spec, prod.T, length_scale=spec.length_scale_min, tol=1e-12, max_iters=300)
+            entry.update(T_ref=ref.T.reshape(-1).tolist(), ref_iters=prod.iters + ref.iters,
+                         ref_converged=ref.converged, f_ref=ref.f, pairs_last=ref.pairs_last,
+                         truth_rot_deg=rot_err_deg(ref.T, spec.T_true),
+                         truth_trans_m=float(np.linalg.norm(ref.T[:3, 3] - spec.T_true[:3, 3])))
+        else:
+            entry.update(T_ref=prod.T.reshape(-1).tolist(), ref_iters=prod.iters, ref_converged=False)
+        data[spec.name] = entry
+        print(f"{spec.name}: n={len(spec.target)} iters={prod.iters} stages={prod.stage_iters} "
+              f"converged={prod.converged} ({time.time() - t0:.1f} s)", flush=True)
+        write(data)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--configs", type=int, nargs="*", default=[1, 2])
     ap.add_argument("--variants", action="store_true", help="write the LiDAR variant entries only")
     ap.add_argument("--c5-eval", type=int, default=0, metavar="N",
                     help="write oracle references for the first N held-out large-motion pairs only")
+    ap.add_argument("--c4-large", type=int, nargs="*", default=[], metavar="I",
+                    help="write oracle references for these (large) object pairs of the batch only")
     args = ap.parse_args()
     data = {}
     if os.path.exists(OUT):
@@ -92,6 +123,9 @@ def main():
                       "synthetic pairs; written by tests/golden/make_golden.py from oracle/ only.")
     if args.c5_eval:
         c5_eval_references(data, args.c5_eval)
+        return
+    if args.c4_large:
+        c4_large(data, args.c4_large)
         return
     if args.variants:
         for i in INSTANCES[2]:
