@@ -185,6 +185,12 @@ void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &p
         P.knn = I.p.knn;
         P.rho = I.p.eig_ratio_min;
         P.cutoff_scale = (mode == Mode::Eval) ? I.eval_cutoff / I.eval_ell : I.p.cutoff_scale;
+        for (int s = 0; s < nst[k]; ++s) {
+            const double l = P.ell[s];
+            P.cut[s] = P.cutoff_scale * l;
+            P.kexp[s] = -1.4426950408889634 / (l * l);
+            P.k2[s] = 2.0 / (l * l);
+        }
         P.sigma2 = I.p.sigma2;
         P.tol = I.p.tol;
         P.stage_tol = I.p.stage_tol;

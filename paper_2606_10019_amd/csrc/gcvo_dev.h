@@ -98,6 +98,10 @@ struct PairDev {
     int iso;                          // 1: every shape is the identity (eig_ratio_min >= 1; no kNN)
     // solver parameters
     double ell[kMaxStages];
+    // per-stage constants of the pair kernel, from ell in FP64 on the host (the
+    // same correctly rounded values the device would compute): the cutoff
+    // cutoff_scale * ell, -log2(e) / ell^2 and 2 / ell^2
+    double cut[kMaxStages], kexp[kMaxStages], k2[kMaxStages];
     int n_stages;
     int knn;
     double rho, cutoff_scale, sigma2, tol, stage_tol;

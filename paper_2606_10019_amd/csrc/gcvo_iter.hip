@@ -768,12 +768,30 @@ __device__ __forceinline__ int finish_line(const StepIn &R, State &St, const dou
 // source points (sorted order), kGroupLanes lanes each.  Every point lists the
 // contiguous x-rows of target cells that meet its cutoff ball; its lanes walk
 // that list with stride kGroupLanes through a (row, offset) cursor, so no lane
-// idles at row ends.  The 16 partial sums of a point are combined with xor
-// shuffles.
+// idles at row ends.  A group is one 16-lane DPP row, so its 16 partial sums
+// are combined with DPP lane permutations inside the VALU instructions: the
+// row mirrored (lane i with lane 15 - i), each half mirrored (i with 7 - i),
+// then neighbours and pairs of a quad swapped.  Each step adds two equal-sized
+// disjoint sets of lanes, so after four steps every lane holds the row's sum
+// (bitwise the same in all 16 lanes: each addition is commutative).
+template <int Ctrl>
+__device__ __forceinline__ float dpp_row(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), Ctrl, 0xF, 0xF, true));
+}
+template <int Ctrl>
+__device__ __forceinline__ double dpp_row(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, Ctrl, 0xF, 0xF, true);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), Ctrl, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+static_assert(kGroupLanes == 16, "a group is one DPP row");
 template <typename Real>
 __device__ __forceinline__ void group_sum(Real &v) {
-#pragma unroll
-    for (int off = kGroupLanes / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    v += dpp_row<0x140>(v);   // row_mirror
+    v += dpp_row<0x141>(v);   // row_half_mirror
+    v += dpp_row<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_row<0x4E>(v);    // quad_perm [2, 3, 0, 1]
 }
 
 template <typename Real, int Mode, bool kLab>
@@ -795,7 +813,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     const int ns = P.n_s;
     typedef const __attribute__((address_space(1))) float *GFloat;
     const GFloat src = (GFloat)P.s_sorted;
-    const double cutoff_scale = P.cutoff_scale;
     void *const partials = P.partials;
     const float4 *const slab = kLab ? P.s_lab : nullptr;
     double dir[6] = {};
@@ -812,7 +829,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     tie_s(done, c2);
     tie_s(done, ns);
     tie_s(done, src);
-    tie_s(done, cutoff_scale);
     tie_s(done, partials);
     if constexpr (kLab) tie_s(done, slab);
     if constexpr (Mode == kModeLine) {
@@ -822,7 +838,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     if ((done != 0) | (phase != (Mode == kModeLine ? 1 : 0))) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int grp = lane / kGroupLanes, q = lane % kGroupLanes;
-    const double ell = P.ell[stage];
+    const double rc = P.cut[stage], kexp_d = P.kexp[stage], k2_d = P.k2[stage];
     const Grid G = P.t_grid[stage];
     typedef const __attribute__((address_space(1))) int *GInt;
     const GInt cells = (GInt)P.t_cells[stage];
@@ -830,6 +846,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     // Target records through a global-address-space pointer: global (not
     // flat) loads, which do not wait on LDS traffic.
     const GRec4 trec = (GRec4)(P.t_sorted[stage]);
+    typedef const vf4 __attribute__((address_space(1))) *GLab;
+    const GLab tlab = kLab ? (GLab)(P.t_lab[stage]) : (GLab)nullptr;
     const double cc[3] = {c0, c1, c2};
 
     // Recentred pose T' = C^{-1} T C: R' = R, t' = R c + t - c.
@@ -840,30 +858,32 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         for (int k = 0; k < 3; ++k) td[r] += Rd[3 * r + k] * cc[k];
     }
 
-    const int j = task.block * kPointsPerBlock + wave * kGroupsPerWave + grp;
-    const bool valid = j < ns;
-    // The source point is read on every lane (lanes past the end read point 0:
-    // a launched block's pair has at least one), so that its loads go out
-    // with the stage's fields instead of behind a branch; lanes past the end
-    // then take y = 0 and S' = 0 as before and walk no rows.
-    const int jc = valid ? j : 0;
-    float sv[9];   // coordinates (FP64 path: the original ones), then the 6 shape entries
+    // The block's source points are transformed once, by wave 0 (point l on
+    // lanes l, l + 16, l + 32, l + 48), and handed to their groups through LDS:
+    // the other waves would repeat the same FP64 work for four points each.
+    // Points past the end are read as point 0 (a launched block's pair has at
+    // least one) and then given y = 0 and S' = 0; their groups walk no rows.
+    __shared__ double sh_y[kPointsPerBlock][3];
+    __shared__ Real sh_sp[kPointsPerBlock][6];
+    if (wave == 0) {
+        const int pt = lane & (kPointsPerBlock - 1);
+        const int jt = task.block * kPointsPerBlock + pt;
+        const int jc = jt < ns ? jt : 0;
+        float sv[9];   // coordinates (FP64 path: the original ones), then the 6 shape entries
 #pragma unroll
-    for (int a = 0; a < 3; ++a) sv[a] = src[(kExact ? 9 + a : a) * ns + jc];
+        for (int a = 0; a < 3; ++a) sv[a] = src[(kExact ? 9 + a : a) * ns + jc];
 #pragma unroll
-    for (int a = 0; a < 6; ++a) sv[3 + a] = src[(3 + a) * ns + jc];
-    // The stage's fields are read only later (the cell table and records
-    // inside the row loop); tying them and the source point to the lane's
-    // valid flag makes all these loads complete together.
-    int vkey = valid;
-    asm("" : "+v"(vkey)
-        : "v"(sv[0]), "v"(sv[1]), "v"(sv[2]), "v"(sv[3]), "v"(sv[4]), "v"(sv[5]), "v"(sv[6]), "v"(sv[7]),
-          "v"(sv[8]), "s"(cells), "s"(trec), "s"(ell), "s"(G.lo[0]), "s"(G.lo[1]), "s"(G.lo[2]), "s"(G.h),
-          "s"(G.inv_h), "s"(G.n[0]), "s"(G.n[1]), "s"(G.n[2]), "s"(G.inv_hx));
-    const bool lane_valid = vkey != 0;
-    double y0, y1, y2;
-    Real p00, p01, p02, p11, p12, p22;
-    {
+        for (int a = 0; a < 6; ++a) sv[3 + a] = src[(3 + a) * ns + jc];
+        // The stage's fields are read only after the barrier (the cell table
+        // and records inside the row loop); tying them to the source point
+        // makes all these loads complete together.
+        int vkey = jt < ns;
+        asm("" : "+v"(vkey)
+            : "v"(sv[0]), "v"(sv[1]), "v"(sv[2]), "v"(sv[3]), "v"(sv[4]), "v"(sv[5]), "v"(sv[6]), "v"(sv[7]),
+              "v"(sv[8]), "s"(cells), "s"(trec), "s"(rc), "s"(G.lo[0]), "s"(G.lo[1]), "s"(G.lo[2]), "s"(G.h),
+              "s"(G.inv_h), "s"(G.n[0]), "s"(G.n[1]), "s"(G.n[2]), "s"(G.inv_hx), "s"(kexp_d), "s"(k2_d),
+              "s"(tlab));
+        const bool pv = vkey != 0;
         double zx, zy, zz;
         if (kExact) {
             zx = ((double)sv[0] - c0) - td[0];
@@ -875,9 +895,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             zz = (double)sv[2] - td[2];
         }
         // y = R^T (z - t)
-        y0 = Rd[0] * zx + Rd[3] * zy + Rd[6] * zz;
-        y1 = Rd[1] * zx + Rd[4] * zy + Rd[7] * zz;
-        y2 = Rd[2] * zx + Rd[5] * zy + Rd[8] * zz;
+        const double ty0 = Rd[0] * zx + Rd[3] * zy + Rd[6] * zz;
+        const double ty1 = Rd[1] * zx + Rd[4] * zy + Rd[7] * zz;
+        const double ty2 = Rd[2] * zx + Rd[5] * zy + Rd[8] * zz;
         // S' = R^T S R
         const double S[3][3] = {{sv[3], sv[4], sv[5]}, {sv[4], sv[6], sv[7]}, {sv[5], sv[7], sv[8]}};
         double SR[3][3], Sp[3][3];
@@ -885,13 +905,28 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             for (int b = 0; b < 3; ++b) SR[a][b] = S[a][0] * Rd[b] + S[a][1] * Rd[3 + b] + S[a][2] * Rd[6 + b];
         for (int a = 0; a < 3; ++a)
             for (int b = a; b < 3; ++b) Sp[a][b] = Rd[a] * SR[0][b] + Rd[3 + a] * SR[1][b] + Rd[6 + a] * SR[2][b];
-        p00 = lane_valid ? (Real)Sp[0][0] : (Real)0; p01 = lane_valid ? (Real)Sp[0][1] : (Real)0;
-        p02 = lane_valid ? (Real)Sp[0][2] : (Real)0; p11 = lane_valid ? (Real)Sp[1][1] : (Real)0;
-        p12 = lane_valid ? (Real)Sp[1][2] : (Real)0; p22 = lane_valid ? (Real)Sp[2][2] : (Real)0;
-        if (!lane_valid) y0 = y1 = y2 = 0.0;
+        if (lane < kPointsPerBlock) {
+            sh_y[pt][0] = pv ? ty0 : 0.0;
+            sh_y[pt][1] = pv ? ty1 : 0.0;
+            sh_y[pt][2] = pv ? ty2 : 0.0;
+            sh_sp[pt][0] = pv ? (Real)Sp[0][0] : (Real)0;
+            sh_sp[pt][1] = pv ? (Real)Sp[0][1] : (Real)0;
+            sh_sp[pt][2] = pv ? (Real)Sp[0][2] : (Real)0;
+            sh_sp[pt][3] = pv ? (Real)Sp[1][1] : (Real)0;
+            sh_sp[pt][4] = pv ? (Real)Sp[1][2] : (Real)0;
+            sh_sp[pt][5] = pv ? (Real)Sp[2][2] : (Real)0;
+        }
+    } else {
+        // the other waves request the stage's fields before they wait
+        pin_s(cells); pin_s(trec); pin_s(rc);
+        pin_s(G.lo[0]); pin_s(G.lo[1]); pin_s(G.lo[2]); pin_s(G.h); pin_s(G.inv_h);
+        pin_s(G.n[0]); pin_s(G.n[1]); pin_s(G.n[2]); pin_s(G.inv_hx);
+        pin_s(kexp_d); pin_s(k2_d); pin_s(tlab);
     }
-    const Real yx = (Real)y0, yy = (Real)y1, yz = (Real)y2;
-    // label vector of the source point (zero-padded to 4)
+    const int slot = wave * kGroupsPerWave + grp;
+    const int j = task.block * kPointsPerBlock + slot;
+    const bool lane_valid = j < ns;
+    // label vector of the source point (zero-padded to 4), requested before the barrier
     vf4 lz = {0.0f, 0.0f, 0.0f, 0.0f};
     if constexpr (kLab) {
         if (lane_valid) {
@@ -899,12 +934,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             lz = vf4{l.x, l.y, l.z, l.w};
         }
     }
-    typedef const vf4 __attribute__((address_space(1))) *GLab;
-    const GLab tlab = kLab ? (GLab)(P.t_lab[stage]) : (GLab)nullptr;
-    const double rc = cutoff_scale * ell;
+    __syncthreads();
+    const double y0 = sh_y[slot][0], y1 = sh_y[slot][1], y2 = sh_y[slot][2];
+    const Real p00 = sh_sp[slot][0], p01 = sh_sp[slot][1], p02 = sh_sp[slot][2];
+    const Real p11 = sh_sp[slot][3], p12 = sh_sp[slot][4], p22 = sh_sp[slot][5];
+    const Real yx = (Real)y0, yy = (Real)y1, yz = (Real)y2;
     const Real rc2 = (Real)(rc * rc);
-    const Real kexp = (Real)(-1.4426950408889634 / (ell * ell));   // f = exp2(q * inv_det * kexp)
-    const Real k2 = (Real)(2.0 / (ell * ell));
+    const Real kexp = (Real)kexp_d;   // f = exp2(q * inv_det * kexp)
+    const Real k2 = (Real)k2_d;
     LineDir<Real> ld = {};
     if constexpr (Mode == kModeLine) {
         // Direction in the recentred frame: w' = w, v' = v - c x w.
@@ -940,10 +977,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         const int nrows = (nyr > 0) ? nyr * (z_hi - z_lo + 1) : 0;
         int (*rs_t)[kMaxRows] = sh_rs[wave];
         int (*rl_t)[kMaxRows] = sh_rl[wave];
+        // Row t of the list is (cy, cz) = (y_lo + t mod nyr, z_lo + t div nyr).  The
+        // quotient comes from an FP32 product with 1/nyr (t and nyr are small: at
+        // most ~5 cells either side of the point), which is off by at most one
+        // and corrected, in place of an integer division.
+        const float inv_nyr = nyr > 0 ? __builtin_amdgcn_rcpf((float)nyr) : 0.0f;
         for (int r0 = 0; r0 < nrows; r0 += kMaxRows) {
             const int nb = min(kMaxRows, nrows - r0);
             for (int r = q; r < nb; r += kGroupLanes) {
-                const int cy = y_lo + (r0 + r) % nyr, cz = z_lo + (r0 + r) / nyr;
+                const int t = r0 + r;
+                int zi = (int)((float)t * inv_nyr);
+                zi -= (zi * nyr > t) ? 1 : 0;
+                zi += ((zi + 1) * nyr <= t) ? 1 : 0;
+                const int cy = y_lo + (t - zi * nyr), cz = z_lo + zi;
                 // distance (cell units) from the point to the row's y-z square
                 const float dy = fmaxf(0.0f, fmaxf((float)cy - gy, gy - (float)(cy + 1)));
                 const float dz = fmaxf(0.0f, fmaxf((float)cz - gz, gz - (float)(cz + 1)));
@@ -1027,25 +1073,67 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         }
     }
 
-    // Finish the source point (lane 0 of its group): the pass's sums, recentred frame.
+    // Each group's sums go to LDS (lane 0 of the group); after the barrier wave 0
+    // finishes all the block's points, one lane per point, in the recentred frame.
+    constexpr int NR = (Mode == kModeLine || Mode == kModeIso) ? 5 : Mode == kModeExact ? 16 : 10;
+    __shared__ Real sh_raw[kPointsPerBlock][NR];
     __shared__ Real sh_pts[kPointsPerBlock][NS];
     __shared__ unsigned sh_cnt[kBlock / 64];
     if (q == 0) {
+        Real r[NR];
+        r[0] = s.F;
+        if constexpr (Mode == kModeLine) {
+            r[1] = s.L1; r[2] = s.L2; r[3] = s.L3; r[4] = s.L4;
+        } else {
+            r[1] = s.A0; r[2] = s.A1; r[3] = s.A2; r[4] = s.B00;
+            if constexpr (Mode != kModeIso) {
+                r[5] = s.B01; r[6] = s.B02; r[7] = s.B11; r[8] = s.B12; r[9] = s.B22;
+            }
+            if constexpr (Mode == kModeExact) {
+                r[10] = s.Q00; r[11] = s.Q01; r[12] = s.Q02; r[13] = s.Q11; r[14] = s.Q12; r[15] = s.Q22;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NR; ++k) sh_raw[slot][k] = r[k];
+    }
+    cnt = wave_sum(cnt);
+    if (lane == 0) sh_cnt[wave] = cnt;
+    __syncthreads();
+    if (wave != 0) return;
+    if (lane < kPointsPerBlock) {
+        const int pt = lane;
+        const bool pv = task.block * kPointsPerBlock + pt < ns;
+        PairSums<Real> t = {};
+        t.F = sh_raw[pt][0];
+        if constexpr (Mode == kModeLine) {
+            t.L1 = sh_raw[pt][1]; t.L2 = sh_raw[pt][2]; t.L3 = sh_raw[pt][3]; t.L4 = sh_raw[pt][4];
+        } else {
+            t.A0 = sh_raw[pt][1]; t.A1 = sh_raw[pt][2]; t.A2 = sh_raw[pt][3]; t.B00 = sh_raw[pt][4];
+            if constexpr (Mode != kModeIso) {
+                t.B01 = sh_raw[pt][5]; t.B02 = sh_raw[pt][6]; t.B11 = sh_raw[pt][7];
+                t.B12 = sh_raw[pt][8]; t.B22 = sh_raw[pt][9];
+            }
+            if constexpr (Mode == kModeExact) {
+                t.Q00 = sh_raw[pt][10]; t.Q01 = sh_raw[pt][11]; t.Q02 = sh_raw[pt][12];
+                t.Q11 = sh_raw[pt][13]; t.Q12 = sh_raw[pt][14]; t.Q22 = sh_raw[pt][15];
+            }
+        }
+        const Real yx = (Real)sh_y[pt][0], yy = (Real)sh_y[pt][1], yz = (Real)sh_y[pt][2];
         Real v[NS];
         if constexpr (Mode == kModeLine) {
-            v[0] = lane_valid ? s.F : (Real)0;
-            v[1] = lane_valid ? s.L1 : (Real)0;
-            v[2] = lane_valid ? s.L2 : (Real)0;
-            v[3] = lane_valid ? s.L3 : (Real)0;
-            v[4] = lane_valid ? s.L4 : (Real)0;
+            v[0] = pv ? t.F : (Real)0;
+            v[1] = pv ? t.L1 : (Real)0;
+            v[2] = pv ? t.L2 : (Real)0;
+            v[3] = pv ? t.L3 : (Real)0;
+            v[4] = pv ? t.L4 : (Real)0;
         } else {
-            const Real kk = lane_valid ? k2 : (Real)0;
-            const Real a0 = kk * s.A0, a1 = kk * s.A1, a2 = kk * s.A2;
-            const Real b00 = kk * s.B00;
-            const Real b01 = (Mode == kModeIso) ? (Real)0 : kk * s.B01, b02 = (Mode == kModeIso) ? (Real)0 : kk * s.B02;
-            const Real b11 = (Mode == kModeIso) ? b00 : kk * s.B11, b12 = (Mode == kModeIso) ? (Real)0 : kk * s.B12;
-            const Real b22 = (Mode == kModeIso) ? b00 : kk * s.B22;
-            v[0] = lane_valid ? s.F : (Real)0;
+            const Real kk = pv ? k2 : (Real)0;
+            const Real a0 = kk * t.A0, a1 = kk * t.A1, a2 = kk * t.A2;
+            const Real b00 = kk * t.B00;
+            const Real b01 = (Mode == kModeIso) ? (Real)0 : kk * t.B01, b02 = (Mode == kModeIso) ? (Real)0 : kk * t.B02;
+            const Real b11 = (Mode == kModeIso) ? b00 : kk * t.B11, b12 = (Mode == kModeIso) ? (Real)0 : kk * t.B12;
+            const Real b22 = (Mode == kModeIso) ? b00 : kk * t.B22;
+            v[0] = pv ? t.F : (Real)0;
             // g_w = -y x a, g_v = -a
             v[1] = -(yy * a2 - yz * a1);
             v[2] = -(yz * a0 - yx * a2);
@@ -1066,9 +1154,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             if constexpr (Mode == kModeExact) {
                 // T1 = J^T Q J = [[-Y Q Y, Y Q], [-Q Y, Q]], Q = (2/ell^2)^2 * sum (f/det^2) u' u'^T
                 const Real k4 = kk * kk;
-                const Real Qm[3][3] = {{k4 * s.Q00, k4 * s.Q01, k4 * s.Q02},
-                                       {k4 * s.Q01, k4 * s.Q11, k4 * s.Q12},
-                                       {k4 * s.Q02, k4 * s.Q12, k4 * s.Q22}};
+                const Real Qm[3][3] = {{k4 * t.Q00, k4 * t.Q01, k4 * t.Q02},
+                                       {k4 * t.Q01, k4 * t.Q11, k4 * t.Q12},
+                                       {k4 * t.Q02, k4 * t.Q12, k4 * t.Q22}};
                 Real N[3][3];
                 for (int r = 0; r < 3; ++r)
                     for (int c = 0; c < 3; ++c) N[r][c] = Y[r][0] * Qm[0][c] + Y[r][1] * Qm[1][c] + Y[r][2] * Qm[2][c];
@@ -1085,13 +1173,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                     for (int c = 0; c < 3; ++c) v[kNumSums + 21 + 3 * r + c] = yv[r] * av[c];
             }
         }
-        const int slot = wave * kGroupsPerWave + grp;
 #pragma unroll
-        for (int k = 0; k < NS; ++k) sh_pts[slot][k] = v[k];
+        for (int k = 0; k < NS; ++k) sh_pts[pt][k] = v[k];
     }
-    cnt = wave_sum(cnt);
-    if (lane == 0) sh_cnt[wave] = cnt;
-    __syncthreads();
+    // LDS operations of one wave complete in order: the sums below read what
+    // the point lanes wrote.
+    __builtin_amdgcn_wave_barrier();
     Real *part = reinterpret_cast<Real *>(partials) + (size_t)task.block * kPartialStride;
     if (tid < NS) {
         Real acc = 0;
