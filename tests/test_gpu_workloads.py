@@ -73,8 +73,8 @@ def c4_sample():
 
 
 def test_register_batch_object_sample_matches_oracle():
-    """Object pairs of uneven sizes (1086 to 2972 points) with per-pair length
-    scales, registered together by one batch call."""
+    """Object pairs of uneven sizes (the oracle-checked sample: 1.1k to 30k
+    points) with per-pair length scales, registered together by one batch call."""
     ids = c4_sample()
     assert len(ids) >= 8
     specs = [synth.make_config4(i) for i in ids]
