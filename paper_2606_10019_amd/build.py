@@ -1,8 +1,9 @@
 """Build the gfx950 HIP library ``libgcvo.so`` in-tree with hipcc.
 
 Every translation unit is compiled as HIP for gfx950 only, at -O3, with the
-packed-FP32 target feature switched off (scalar VALU FP32 throughout), then
-linked into one shared library next to this file.
+packed-FP32 target feature switched off (scalar VALU FP32 throughout) and
+kernel arguments preloaded into SGPRs, then linked into one shared library
+next to this file.
 """
 from __future__ import annotations
 
@@ -23,6 +24,10 @@ ARCH = "gfx950"
 HIP_FLAGS = [
     "-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # Kernel arguments preloaded into SGPRs at wave launch (gfx950): the small
+    # per-iteration kernels start without a load of their own arguments.  The
+    # code object keeps the loading prologue for firmware that does not preload.
+    "-mllvm", "-amdgpu-kernarg-preload-count=16",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-result",
     "-I", os.path.join(ROOT, "include"),
 ]
