@@ -53,7 +53,8 @@ sys.path.insert(0, ROOT)
 # and WRITE_SIZE, calibrated on a plain copy); reported only while the kernel
 # sources are the ones the counters were taken with.
 HBM_PROFILE = os.path.join(ROOT, "profiles", "k_iterate_lidar_pair_64x1024_hbm.txt")
-KERNEL_SOURCES = ["gcvo_api.cpp", "gcvo_dev.h", "gcvo_iter.hip", "gcvo_prep.hip"]
+# the library sources and the build script (its flags shape the code object)
+KERNEL_SOURCES = ["csrc/gcvo_api.cpp", "csrc/gcvo_dev.h", "csrc/gcvo_iter.hip", "csrc/gcvo_prep.hip", "build.py"]
 FLOP_PER_PAIR = 76
 FLOP_PER_SOURCE_POINT = 230
 FP32_VALU_PEAK_TFLOPS = 157.3
@@ -67,8 +68,8 @@ def measured_traffic(cell_fraction):
     except OSError:
         return None
     vals = dict(line.split(":", 1) for line in text.splitlines() if ":" in line and not line.startswith("#"))
-    csrc = os.path.join(ROOT, "paper_2606_10019_amd", "csrc")
-    digest = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read() for f in KERNEL_SOURCES)).hexdigest()
+    pkg = os.path.join(ROOT, "paper_2606_10019_amd")
+    digest = hashlib.sha256(b"".join(open(os.path.join(pkg, f), "rb").read() for f in KERNEL_SOURCES)).hexdigest()
     if vals.get("sources_sha256", "").strip() != digest:
         return None
     if [float(v) for v in vals.get("cell_fraction", "").split()] != list(cell_fraction):
