@@ -127,38 +127,6 @@ struct Plan {
     gcvo_profile *profile = nullptr;   // measurement of the call, or null
 };
 
-// Workgroups are dealt to the XCDs in turn (workgroup i of a launch runs on XCD
-// i mod kXcds), and each XCD has an L2 of its own.  The pair kernel's tasks
-// for one pair's n blocks (Morton order) are laid out so that each XCD serves
-// contiguous chunks of about n / 64 blocks, chunk c on XCD c mod kXcds: a
-// chunk's blocks share most target records in that XCD's L2, and the chunks of
-// one XCD still spread over the whole cloud.  `first` is the launch index of
-// the pair's first task.  The block index, not the task's position, decides
-// where a block's partial goes and in which order partials are added, so the
-// layout changes no result.
-constexpr int kXcds = 8;
-void deal_blocks(int pair, int n, int first, BlockTask *out) {
-    if (n <= 0) return;
-    const int chunk = std::max(1, (n + 8 * kXcds - 1) / (8 * kXcds));
-    std::vector<std::vector<int>> by_xcd(kXcds);
-    for (int b = 0; b < n; ++b) by_xcd[(b / chunk) % kXcds].push_back(b);
-    std::vector<size_t> next(kXcds, 0);
-    for (int j = 0; j < n; ++j) {
-        int x = (first + j) % kXcds;
-        if (next[x] == by_xcd[x].size()) {   // this XCD's blocks are dealt: take from the fullest list
-            int best = -1;
-            size_t left = 0;
-            for (int y = 0; y < kXcds; ++y)
-                if (by_xcd[y].size() - next[y] > left) {
-                    left = by_xcd[y].size() - next[y];
-                    best = y;
-                }
-            x = best;
-        }
-        out[j] = BlockTask{pair, by_xcd[x][next[x]++]};
-    }
-}
-
 // Lays out (base == nullptr: sizes) every device array of a batch.
 void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &pl) {
     Arena A(base);
@@ -314,8 +282,10 @@ void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &p
                 if (base) pl.jobs[job] = Js;
                 ++job;
             }
-            if (base) deal_blocks(k, P.n_blocks, task, pl.tasks.data() + task);
-            task += P.n_blocks;
+            for (int b = 0; b < P.n_blocks; ++b) {
+                if (base) pl.tasks[task] = BlockTask{k, b};
+                ++task;
+            }
         }
         if (base) pl.pairs[k] = P;
     }

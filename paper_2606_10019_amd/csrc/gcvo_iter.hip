@@ -798,7 +798,9 @@ template <typename Real, int Mode, bool kLab>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_iterate(PairDev *pairs,
                                                                                           const BlockTask *tasks) {
     constexpr int NS = ModeInfo<Mode>::sums;
-    const BlockTask task = tasks[blockIdx.x];
+    // A launch over one pair passes no task table: block b serves that pair's
+    // block b, and the kernel's first dependent load goes away.
+    const BlockTask task = tasks ? tasks[blockIdx.x] : BlockTask{0, (int)blockIdx.x};
     PairDev &P = pairs[task.pair];
     State &St = P.st;
     // Everything that does not depend on the stage goes out in one batch ahead
@@ -1325,6 +1327,7 @@ __global__ __launch_bounds__(64) void k_step(PairDev *pairs, int *host_done) {
 template <typename Real, int Mode, int Kind, bool kLab>
 static void launch_pass(PairDev *pairs, int n_pairs, BlockTask *tasks, int n_tasks, int *host_done, hipStream_t s,
                         hipEvent_t *&ev) {
+    if (n_pairs == 1) tasks = nullptr;   // block b is block b of pair 0
     if (ev) {
         // events attached to the dispatch itself: they time the kernel, not the queue
         hipExtLaunchKernelGGL((k_iterate<Real, Mode, kLab>), dim3(n_tasks), dim3(kBlock), 0, s, ev[0], ev[1], 0u,
