@@ -60,6 +60,7 @@ FLOP_PER_SOURCE_POINT = 230
 FP32_VALU_PEAK_TFLOPS = 157.3
 N_INSTANCES = 4
 TUNE_CANDIDATES = ((0.5, 0.125), (0.5, 0.25), (0.5, 0.5), (0.7, 0.125), (0.7, 0.25), (1.0, 0.25))   # (y-z, x)
+OBJECT_TUNE_CANDIDATES = ((0.25, 0.1), (0.35, 0.125), (0.5, 0.125))
 
 
 def measured_traffic(cell_fraction):
@@ -124,6 +125,7 @@ def objects_leg(gcvo, synth, golden, dev, rot_err_deg, trans_err_m, n_pairs=256,
     pairs with a stored oracle fixed point are gated, the rest reported as
     converged; the batch is then repeated with the pair kernel measured."""
     import torch
+    from paper_2606_10019_amd import autotune
     t0 = time.perf_counter()
     specs = [synth.make_config4(i) for i in range(n_pairs)]
     print(f"[bench] objects: generated {n_pairs} pairs ({sum(len(s.source) for s in specs)} source points) in "
@@ -132,7 +134,19 @@ def objects_leg(gcvo, synth, golden, dev, rot_err_deg, trans_err_m, n_pairs=256,
     src = torch.from_numpy(np.concatenate([s.source for s in specs])).to(dev)
     to = np.cumsum([0] + [len(s.target) for s in specs])
     so = np.cumsum([0] + [len(s.source) for s in specs])
-    params = [gcvo.params_from_spec(s) for s in specs]
+    # cell shape tuned (untimed) on every 8th pair: dense small surfaces prefer
+    # smaller cells than the LiDAR scenes
+    tune_ids = list(range(0, n_pairs, 8))
+    tt = torch.from_numpy(np.concatenate([specs[k].target for k in tune_ids])).to(dev)
+    ts = torch.from_numpy(np.concatenate([specs[k].source for k in tune_ids])).to(dev)
+    tto = np.cumsum([0] + [len(specs[k].target) for k in tune_ids])
+    tso = np.cumsum([0] + [len(specs[k].source) for k in tune_ids])
+    best, tune, _ = autotune.autotune_cell_fraction(tt, tto, ts, tso, [gcvo.params_from_spec(specs[k]) for k in tune_ids],
+                                                    candidates=OBJECT_TUNE_CANDIDATES, reps=1)
+    del tt, ts
+    print(f"[bench] objects: cell-size autotune on {len(tune_ids)} pairs (ms per call): "
+          f"{json.dumps({f'{a},{b}': v for (a, b), v in tune.items()})} -> {best}", file=sys.stderr, flush=True)
+    params = [gcvo.params_from_spec(s, cell_fraction=best[0], cell_fraction_x=best[1]) for s in specs]
     ws = gcvo.workspace(gcvo.gcvo_batch_workspace_size(to, so, params), dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -166,7 +180,9 @@ def objects_leg(gcvo, synth, golden, dev, rot_err_deg, trans_err_m, n_pairs=256,
         ds = time.perf_counter() - t0
         same = sum(1 for k in range(n_pairs) if np.array_equal(single[k][0], T[k]))
     out = {"workload": f"object_pairs_{n_pairs}_1k_to_50k_points", "pairs": n_pairs,
-           "source_points": int(so[-1]), "seconds_per_batch": dt, "converged": converged,
+           "source_points": int(so[-1]), "cell_fraction": list(best),
+           "cell_fraction_tuning_ms": {f"{a},{b}": v for (a, b), v in tune.items()},
+           "seconds_per_batch": dt, "converged": converged,
            "registrations_per_s_converged": converged / dt, "oracle_sample": sample,
            "oracle_sample_in_gate": in_gate, "oracle_sample_sizes": sizes,
            "mean_iterations": float(np.mean([i["iters"] for i in infos])),
