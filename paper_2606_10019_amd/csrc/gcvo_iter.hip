@@ -26,8 +26,9 @@
 //               the exact frozen-covariance Hessian of the exact-Hessian solver;
 //   kModeLine   the quartic line-search coefficients along a unit direction
 //               (first-order solver, App. "Line search", re-derived).
-// Sums are reduced per point (xor shuffles) and per block in the pair-term
-// precision and written as one block partial.
+// Sums are reduced per point (DPP row permutations over the point's 16 lanes)
+// and per block in the pair-term precision and written as one block partial;
+// the FP64 transform and the per-point finish run once per block, on wave 0.
 //
 // Reduction (k_reduce): kReduceSplit blocks per pair sum the block partials
 // with compensated per-lane sums and FP64 slices.  Step (k_step): one lane per
