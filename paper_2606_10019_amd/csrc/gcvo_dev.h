@@ -162,6 +162,28 @@ struct BlockTask {   // one block of the pair kernel: a pair and a 256-point sli
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// DPP lane permutations within a 16-lane row (one point's group of lanes):
+// the row mirrored (lane i with 15 - i), each half-row mirrored (i with 7 - i),
+// neighbours of a quad swapped, pairs of a quad swapped.  Applied in this order,
+// each step combines two equal-sized disjoint sets of lanes, so after the four
+// steps every lane of the row has combined all 16 values.
+constexpr int kDppRowMirror = 0x140, kDppRowHalfMirror = 0x141, kDppQuadSwap1 = 0xB1, kDppQuadSwap2 = 0x4E;
+static_assert(kGroupLanes == 16, "a group of lanes is one DPP row");
+template <int Ctrl>
+__device__ __forceinline__ unsigned dpp_row(unsigned v) {
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, Ctrl, 0xF, 0xF, true);
+}
+template <int Ctrl>
+__device__ __forceinline__ float dpp_row(float v) {
+    return __builtin_bit_cast(float, dpp_row<Ctrl>(__builtin_bit_cast(unsigned, v)));
+}
+template <int Ctrl>
+__device__ __forceinline__ double dpp_row(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = dpp_row<Ctrl>((unsigned)b), hi = dpp_row<Ctrl>((unsigned)(b >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll

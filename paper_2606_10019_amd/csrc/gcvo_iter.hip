@@ -775,24 +775,12 @@ __device__ __forceinline__ int finish_line(const StepIn &R, State &St, const dou
 // then neighbours and pairs of a quad swapped.  Each step adds two equal-sized
 // disjoint sets of lanes, so after four steps every lane holds the row's sum
 // (bitwise the same in all 16 lanes: each addition is commutative).
-template <int Ctrl>
-__device__ __forceinline__ float dpp_row(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), Ctrl, 0xF, 0xF, true));
-}
-template <int Ctrl>
-__device__ __forceinline__ double dpp_row(double v) {
-    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, Ctrl, 0xF, 0xF, true);
-    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), Ctrl, 0xF, 0xF, true);
-    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
-}
-static_assert(kGroupLanes == 16, "a group is one DPP row");
 template <typename Real>
 __device__ __forceinline__ void group_sum(Real &v) {
-    v += dpp_row<0x140>(v);   // row_mirror
-    v += dpp_row<0x141>(v);   // row_half_mirror
-    v += dpp_row<0xB1>(v);    // quad_perm [1, 0, 3, 2]
-    v += dpp_row<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_row<kDppRowMirror>(v);
+    v += dpp_row<kDppRowHalfMirror>(v);
+    v += dpp_row<kDppQuadSwap1>(v);
+    v += dpp_row<kDppQuadSwap2>(v);
 }
 
 template <typename Real, int Mode, bool kLab>

@@ -600,20 +600,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
                 __builtin_amdgcn_wave_barrier();
             }
         }
-        // Merge: K rounds of a lexicographic group minimum over the lists' heads.
+        // Merge: K rounds of a lexicographic group minimum over the lists' heads,
+        // by DPP row permutations (a minimum is exact, so every lane of the
+        // group ends with the same head).
+        auto take_min = [](double &d, uint32_t &c, double od, uint32_t oc) {
+            if (nb_less(od, oc, d, c)) {
+                d = od;
+                c = oc;
+            }
+        };
 #pragma unroll
         for (int m = 0; m < K; ++m) {
             double d = bd[0];
             uint32_t c = bq[0];
-#pragma unroll
-            for (int off = kGroupLanes / 2; off >= 1; off >>= 1) {
-                const double od = __shfl_xor(d, off, 64);
-                const uint32_t oc = __shfl_xor(c, off, 64);
-                if (nb_less(od, oc, d, c)) {
-                    d = od;
-                    c = oc;
-                }
-            }
+            take_min(d, c, dpp_row<kDppRowMirror>(d), dpp_row<kDppRowMirror>((unsigned)c));
+            take_min(d, c, dpp_row<kDppRowHalfMirror>(d), dpp_row<kDppRowHalfMirror>((unsigned)c));
+            take_min(d, c, dpp_row<kDppQuadSwap1>(d), dpp_row<kDppQuadSwap1>((unsigned)c));
+            take_min(d, c, dpp_row<kDppQuadSwap2>(d), dpp_row<kDppQuadSwap2>((unsigned)c));
             if (!done) {
                 md[m] = d;
                 mq[m] = c;
