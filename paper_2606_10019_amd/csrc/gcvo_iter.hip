@@ -1048,6 +1048,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     }
 
     // Combine the 16 lanes of each point.
+    group_sum(cnt);
     group_sum(s.F);
     if constexpr (Mode == kModeLine) {
         group_sum(s.L1); group_sum(s.L2); group_sum(s.L3); group_sum(s.L4);
@@ -1069,7 +1070,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     constexpr int NR = (Mode == kModeLine || Mode == kModeIso) ? 5 : Mode == kModeExact ? 16 : 10;
     __shared__ Real sh_raw[kPointsPerBlock][NR];
     __shared__ Real sh_pts[kPointsPerBlock][NS];
-    __shared__ unsigned sh_cnt[kBlock / 64];
+    __shared__ unsigned sh_cnt[kPointsPerBlock];   // pairs within the cutoff, per group
     if (q == 0) {
         Real r[NR];
         r[0] = s.F;
@@ -1086,9 +1087,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         }
 #pragma unroll
         for (int k = 0; k < NR; ++k) sh_raw[slot][k] = r[k];
+        sh_cnt[slot] = cnt;
     }
-    cnt = wave_sum(cnt);
-    if (lane == 0) sh_cnt[wave] = cnt;
     __syncthreads();
     if (wave != 0) return;
     if (lane < kPointsPerBlock) {
@@ -1178,7 +1178,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     }
     if (tid == NS) {
         unsigned long long c = 0;
-        for (int w = 0; w < kBlock / 64; ++w) c += sh_cnt[w];
+        for (int g = 0; g < kPointsPerBlock; ++g) c += sh_cnt[g];
         *reinterpret_cast<unsigned long long *>(part + NS + (NS & 1) * (sizeof(Real) == 4)) = c;
     }
 }
