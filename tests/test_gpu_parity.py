@@ -60,6 +60,17 @@ def test_point_shapes_match_oracle(c1):
     np.testing.assert_allclose(S.T, SX, atol=1e-6)
 
 
+@pytest.mark.parametrize("knn", [2, 3, 5, 7, 16])
+def test_point_shapes_other_neighbour_counts(c1, knn):
+    """Each neighbour count is its own kernel instantiation (register lists of
+    K candidates per lane, K merge rounds across the point's 16 lanes)."""
+    spec = c1[0]
+    note(f"point_shapes config1 target, knn {knn}")
+    S = gcvo.gcvo_point_shapes(to_dev(spec.target), knn, spec.eig_ratio_min).cpu().numpy()
+    ref = O.point_shapes(spec.target.astype(np.float64), knn, spec.eig_ratio_min)
+    np.testing.assert_allclose(S.T, ref, atol=1e-6)
+
+
 def test_point_shapes_ragged_and_duplicates():
     rng = np.random.default_rng(3)
     P = rng.normal(size=(1037, 3)).astype(np.float32)
