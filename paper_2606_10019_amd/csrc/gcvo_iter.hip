@@ -857,6 +857,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     __shared__ double sh_y[kPointsPerBlock][3];
     __shared__ Real sh_sp[kPointsPerBlock][6];
     if (wave == 0) {
+        __builtin_amdgcn_s_setprio(2);   // the block's other waves wait for this transform
         const int pt = lane & (kPointsPerBlock - 1);
         const int jt = task.block * kPointsPerBlock + pt;
         const int jc = jt < ns ? jt : 0;
@@ -907,6 +908,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             sh_sp[pt][4] = pv ? (Real)Sp[1][2] : (Real)0;
             sh_sp[pt][5] = pv ? (Real)Sp[2][2] : (Real)0;
         }
+        __builtin_amdgcn_s_setprio(0);
     } else {
         // the other waves request the stage's fields before they wait
         pin_s(cells); pin_s(trec); pin_s(rc);
