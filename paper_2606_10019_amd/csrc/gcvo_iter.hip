@@ -975,8 +975,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         // most ~5 cells either side of the point), which is off by at most one
         // and corrected, in place of an integer division.
         const float inv_nyr = nyr > 0 ? __builtin_amdgcn_rcpf((float)nyr) : 0.0f;
+        // Walks are long only where the cutoff spans many cells along a row (the
+        // coarse stages); the shorter ones skip the priority below, and so does
+        // the FP64 kernel, whose launches it lengthens.
+        const bool long_rows = sizeof(Real) == 4 && rcm * G.inv_hx >= 4.0f;
         for (int r0 = 0; r0 < nrows; r0 += kMaxRows) {
             const int nb = min(kMaxRows, nrows - r0);
+            unsigned mylen = 0;   // candidates on this lane's rows of the chunk
             for (int r = q; r < nb; r += kGroupLanes) {
                 const int t = r0 + r;
                 int zi = (int)((float)t * inv_nyr);
@@ -999,8 +1004,21 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 }
                 rs_t[grp][r] = b;
                 rl_t[grp][r] = len;
+                mylen += (unsigned)len;
             }
             __builtin_amdgcn_wave_barrier();
+            if (r0 == 0 && long_rows) {
+                // Issue priority from the longest walk of the wave's groups: a launch
+                // ends with its longest waves, so on a shared SIMD they go first
+                // (longest-first scheduling; the sums do not depend on it).  The
+                // group is one DPP row, all of it active here (nrows is the
+                // group's); the ballots make each test a scalar branch of the wave.
+                group_sum(mylen);
+                const unsigned steps = (mylen + kGroupLanes - 1) / kGroupLanes;
+                if (__ballot(steps >= 40) != 0ull) __builtin_amdgcn_s_setprio(3);
+                else if (__ballot(steps >= 28) != 0ull) __builtin_amdgcn_s_setprio(2);
+                else if (__ballot(steps >= 16) != 0ull) __builtin_amdgcn_s_setprio(1);
+            }
             int r = 0, o = q, rs = rs_t[grp][0], rl = rl_t[grp][0];
             while (r < nb && o >= rl) {
                 o -= rl;
@@ -1047,6 +1065,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             }
             __builtin_amdgcn_wave_barrier();
         }
+        if constexpr (sizeof(Real) == 4) __builtin_amdgcn_s_setprio(0);
     }
 
     // Combine the 16 lanes of each point.
