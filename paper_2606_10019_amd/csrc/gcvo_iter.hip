@@ -63,6 +63,18 @@ struct Fast<double> {
 // All 6x6 algebra below is fully unrolled with compile-time indices so that it
 // stays in registers (one lane per pair runs it).
 
+// 1/x from the hardware estimate refined by two Newton-Raphson steps
+// (r <- r + r (1 - x r), each squaring the relative error): within an ulp or so
+// of the rounded quotient for normal x whose reciprocal is normal, in about a
+// third of the instructions of an IEEE division.
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 // Solve A x = b (6x6) by Gaussian elimination with partial pivoting on the
 // augmented matrix M = [A | b] (rows swapped in place; b in column 6, so that
 // the swaps of b stay in registers like those of A); false when a pivot is
@@ -101,7 +113,7 @@ __device__ __forceinline__ bool solve6(double M[6][7], double x[6], double tiny)
                 }
             }
         }
-        const double inv = 1.0 / M[k][k];
+        const double inv = rcp_nr(M[k][k]);
         invd[k] = inv;
 #pragma unroll
         for (int r = k + 1; r < 6; ++r) {
@@ -120,6 +132,90 @@ __device__ __forceinline__ bool solve6(double M[6][7], double x[6], double tiny)
     return true;
 }
 
+// 3x3 adjugate (adj(M) M = det(M) I); returns det(M).
+__device__ __forceinline__ double adj3(const double m[3][3], double a[3][3]) {
+    a[0][0] = m[1][1] * m[2][2] - m[1][2] * m[2][1];
+    a[0][1] = m[0][2] * m[2][1] - m[0][1] * m[2][2];
+    a[0][2] = m[0][1] * m[1][2] - m[0][2] * m[1][1];
+    a[1][0] = m[1][2] * m[2][0] - m[1][0] * m[2][2];
+    a[1][1] = m[0][0] * m[2][2] - m[0][2] * m[2][0];
+    a[1][2] = m[0][2] * m[1][0] - m[0][0] * m[1][2];
+    a[2][0] = m[1][0] * m[2][1] - m[1][1] * m[2][0];
+    a[2][1] = m[0][1] * m[2][0] - m[0][0] * m[2][1];
+    a[2][2] = m[0][0] * m[1][1] - m[0][1] * m[1][0];
+    return m[0][0] * a[0][0] + m[0][1] * a[1][0] + m[0][2] * a[2][0];
+}
+
+// Maximum absolute row sum of a 3x3 matrix.
+__device__ __forceinline__ double norm_inf3(const double m[3][3]) {
+    return fmax(fmax(fabs(m[0][0]) + fabs(m[0][1]) + fabs(m[0][2]), fabs(m[1][0]) + fabs(m[1][1]) + fabs(m[1][2])),
+                fabs(m[2][0]) + fabs(m[2][1]) + fabs(m[2][2]));
+}
+
+// Solve H x = -g through the Schur complement of the lower-right 3x3 block, for
+// a well-conditioned H only.  With H = [[A, B], [C, D]] in 3x3 blocks, Di = D^-1,
+// E = B Di and S = A - E C:  x1 = S^-1 (r1 - E r2), x2 = Di (r2 - C x1), r = -g.
+// From the block form of H^-1,
+//   ||H^-1||_inf <= (1 + ||Di|| ||C||) (1 + ||E||) ||S^-1|| + ||Di||,
+// and every pivot of the partial-pivoting elimination of H (H = P L U with
+// |l_ij| <= 1) has |u_kk| >= 1 / (6 ||H^-1||_inf).  So when that bound times
+// max|H| is at most kBlockCond, every pivot of solve6 exceeds its threshold
+// 1e-12 max|H| by a factor of 16 or more: both methods take the same branch and
+// their solutions differ by rounding only.  Returns false (x untouched) unless
+// the bound holds (also for singular D or S and non-finite entries).  Some 200
+// operations without branches, against ~600 with pivot search and row swaps.
+constexpr double kBlockCond = 1e10;
+__device__ __forceinline__ bool solve6_blocks(const double H[6][6], const double g[6], double x[6]) {
+    double A[3][3], B[3][3], C[3][3], D[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            A[r][c] = H[r][c];
+            B[r][c] = H[r][3 + c];
+            C[r][c] = H[3 + r][c];
+            D[r][c] = H[3 + r][3 + c];
+        }
+    double rmax[6];
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+        rmax[r] = fmax(fmax(fmax(fabs(H[r][0]), fabs(H[r][1])), fmax(fabs(H[r][2]), fabs(H[r][3]))),
+                       fmax(fabs(H[r][4]), fabs(H[r][5])));
+    const double amax = fmax(fmax(rmax[0], rmax[1]), fmax(fmax(rmax[2], rmax[3]), fmax(rmax[4], rmax[5])));
+    double Da[3][3], Di[3][3], E[3][3], S[3][3], Sa[3][3];
+    const double iD = rcp_nr(adj3(D, Da));
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Di[r][c] = Da[r][c] * iD;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) E[r][c] = B[r][0] * Di[0][c] + B[r][1] * Di[1][c] + B[r][2] * Di[2][c];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) S[r][c] = A[r][c] - (E[r][0] * C[0][c] + E[r][1] * C[1][c] + E[r][2] * C[2][c]);
+    const double iS = rcp_nr(adj3(S, Sa));
+    const double nDi = norm_inf3(Di);
+    const double bound = ((1.0 + nDi * norm_inf3(C)) * (1.0 + norm_inf3(E)) * (norm_inf3(Sa) * fabs(iS)) + nDi) * amax;
+    if (!(bound <= kBlockCond)) return false;
+    const double r1[3] = {-g[0], -g[1], -g[2]}, r2[3] = {-g[3], -g[4], -g[5]};
+    double t[3], x1[3], u[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) t[r] = r1[r] - (E[r][0] * r2[0] + E[r][1] * r2[1] + E[r][2] * r2[2]);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) x1[r] = (Sa[r][0] * t[0] + Sa[r][1] * t[1] + Sa[r][2] * t[2]) * iS;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) u[r] = r2[r] - (C[r][0] * x1[0] + C[r][1] * x1[1] + C[r][2] * x1[2]);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        x[r] = x1[r];
+        x[3 + r] = Di[r][0] * u[0] + Di[r][1] * u[1] + Di[r][2] * u[2];
+    }
+    return true;
+}
+
 // Damped Gauss-Newton step (reading of the damping the paper leaves open):
 // plain H first; if singular or not an ascent direction, H_main shifted by
 // -lambda * ||diag H_main||_2 with lambda = 1e-6 * 10^m, m = 0..6.
@@ -134,16 +230,22 @@ __device__ __forceinline__ int damped_step(const double H[6][6], const double Hm
         for (int a = 0; a < 6; ++a) xi[a] = 0.0;
         return 0;
     }
-    {   // plain H (its own copy of the solve, so that H's registers serve as
-        // the working matrix without a select between H and H_main)
-        double A[6][7], x[6];
+    {   // plain H: the block solve where it is well conditioned, else the
+        // pivoting elimination (its own copy of the solve, so that H's registers
+        // serve as the working matrix without a select between H and H_main)
+        double x[6];
+        bool solved = solve6_blocks(H, g, x);
+        if (!solved) {
+            double A[6][7];
 #pragma unroll
-        for (int r = 0; r < 6; ++r) {
+            for (int r = 0; r < 6; ++r) {
 #pragma unroll
-            for (int c = 0; c < 6; ++c) A[r][c] = H[r][c];
-            A[r][6] = -g[r];
+                for (int c = 0; c < 6; ++c) A[r][c] = H[r][c];
+                A[r][6] = -g[r];
+            }
+            solved = solve6(A, x, 1e-12);
         }
-        if (solve6(A, x, 1e-12)) {
+        if (solved) {
             double gx = 0.0;
 #pragma unroll
             for (int a = 0; a < 6; ++a) gx += g[a] * x[a];
@@ -191,17 +293,29 @@ __device__ __forceinline__ void twist_exp(const double xi[6], double E[4][4]) {
         a = 1.0 - th2 / 6.0;
         b = 0.5 - th2 / 24.0;
     }
-    double sn = 0.0, ch = 1.0;
+    double sn = 0.0, ch = 1.0, ith = 0.0;
     if (th >= 1e-5) {
-        sincos(0.5 * th, &sn, &ch);
-        const double sh = sn / (0.5 * th);
-        a = 2.0 * sn * ch / th;
+        const double h = 0.5 * th;
+        if (h <= 0.25) {
+            // Taylor series of sin h and cos h, truncated where the next term is
+            // below 1e-19 of the sum for h <= 1/4 (coefficients 1/n!)
+            const double h2 = h * h;
+            sn = h * (1.0 + h2 * (-1.0 / 6 + h2 * (1.0 / 120 + h2 * (-1.0 / 5040 + h2 * (1.0 / 362880 +
+                 h2 * (-1.0 / 39916800 + h2 * (1.0 / 6227020800.0)))))));
+            ch = 1.0 + h2 * (-1.0 / 2 + h2 * (1.0 / 24 + h2 * (-1.0 / 720 + h2 * (1.0 / 40320 +
+                 h2 * (-1.0 / 3628800 + h2 * (1.0 / 479001600.0))))));
+        } else {
+            sincos(h, &sn, &ch);
+        }
+        ith = rcp_nr(th);
+        const double sh = 2.0 * sn * ith;   // sin(th/2) / (th/2)
+        a = 2.0 * sn * ch * ith;
         b = 0.5 * sh * sh;
     }
     if (th < 1e-2)
         c = (1.0 / 6.0) - th2 * (1.0 / 120.0) + th2 * th2 * (1.0 / 5040.0);
     else
-        c = (th - 2.0 * sn * ch) / (th2 * th);
+        c = (th - 2.0 * sn * ch) * (ith * ith * ith);
     // W = w^, W^2 = w w^T - th2 I
     const double W[3][3] = {{0.0, -wz, wy}, {wz, 0.0, -wx}, {-wy, wx, 0.0}};
     const double w[3] = {wx, wy, wz};
@@ -459,16 +573,19 @@ __device__ __forceinline__ void pin_step_in(const StepIn &R) {
     pin_s(R.eval_only);
 }
 
-// Record the evaluation (f, g, H) of the current pass.
+// Record the evaluation (f, g, H) of the current pass; H only for evaluation
+// calls, the one reader of it (a registration reports f, g and the pair count).
 __device__ __forceinline__ void record_eval(const StepIn &R, State &St, double f, const double g[6],
                                             const double H[6][6], unsigned long long tot_pairs) {
     St.f = f;
 #pragma unroll
     for (int a = 0; a < 6; ++a) St.g[a] = g[a];
+    if (R.eval_only) {
 #pragma unroll
-    for (int r = 0; r < 6; ++r)
+        for (int r = 0; r < 6; ++r)
 #pragma unroll
-        for (int c = 0; c < 6; ++c) St.H[6 * r + c] = H[r][c];
+            for (int c = 0; c < 6; ++c) St.H[6 * r + c] = H[r][c];
+    }
     St.pairs_last = (long long)tot_pairs;
     if (R.iter_pairs && R.iter < R.max_iters) R.iter_pairs[R.iter] = (long long)tot_pairs;
 }
@@ -1286,11 +1403,19 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(PairDev *pairs) {
     }
 }
 
+// A double held by lane k of the wave, read by every lane (k uniform).
+__device__ __forceinline__ double lane_read(double v, int k) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, k);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), k);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // The FP64 step of one pair, on one lane (its registers are not shared with
 // any wide kernel).  Every lane first requests its column of the reduction
 // splits (the sums, then the pair count in column NS), and the step's reads of
 // the descriptor and state go out with them, ahead of the done/phase test:
-// one memory round trip, after which the step reads only registers and LDS.
+// one memory round trip, after which the step reads only registers.
 // The splits are added in a fixed order, one column per lane.  Step kinds:
 // 0 Gauss-Newton, 1 Newton, 2 first-order direction (after a gradient pass),
 // 3 first-order line step.  At the last pass of a chunk of iterations the host
@@ -1319,14 +1444,12 @@ __global__ __launch_bounds__(64) void k_step(PairDev *pairs, int *host_done) {
         if (host_done && lane == 0) host_done[blockIdx.x] = done;
         return;
     }
-    __shared__ double sh_tot[NS + 1];
-    if (lane <= NS) sh_tot[lane] = acc;
-    __syncthreads();
-    if (lane != 0) return;
+    // the column sums to the first lane by lane reads (no LDS round trip)
     double tot[NS];
 #pragma unroll
-    for (int k = 0; k < NS; ++k) tot[k] = sh_tot[k];
-    const unsigned long long c = (unsigned long long)sh_tot[NS];
+    for (int k = 0; k < NS; ++k) tot[k] = lane_read(acc, k);
+    const unsigned long long c = (unsigned long long)lane_read(acc, NS);
+    if (lane != 0) return;
     int now_done;
     if constexpr (Kind == 0 || Kind == 1) now_done = finish_iteration(R, St, tot, c, Kind == 1);
     else if constexpr (Kind == 2) now_done = finish_direction(R, St, tot, c);
