@@ -486,43 +486,41 @@ __global__ __launch_bounds__(kBlock) void k_knn_pts(SortJob *jobs, const PairDev
     J.pts[pos] = make_float4(J.x[c], J.y[c], J.z[c], __uint_as_float(c));
 }
 
-// kNN with kGroupLanes lanes per point: the group lists the x-rows of grid
-// cells meeting a ball of radius r around the point, every lane keeps the K
-// best candidates it sees within r (FP64 squared distances, ties to the smaller
+constexpr int kKnnMaxAttempts = 40;   // radius attempts 1.5 h 2^a, a < 40
+
+// Lexicographic (distance, index) minimum of a lane's candidate and another's.
+__device__ __forceinline__ void take_min(double &d, uint32_t &c, double od, uint32_t oc) {
+    if (nb_less(od, oc, d, c)) {
+        d = od;
+        c = oc;
+    }
+}
+
+// The K nearest neighbours of (fx, fy, fz) with kGroupLanes lanes per point
+// (lane q of group grp of the wave): the group lists the x-rows of grid cells
+// meeting a ball of radius r around the point, every lane keeps the K best
+// candidates it sees within r (FP64 squared distances, ties to the smaller
 // index), and the 16 lists are merged by K rounds of a group minimum.  If fewer
-// than K points lie within r, r doubles and the point is scanned again; the
-// K-th merged distance never exceeds r, so no closer point was skipped.
-// Register budget of five waves per SIMD (96 VGPRs, no spills; 112 VGPRs and
-// four waves otherwise): 11 % shorter on a LiDAR cloud pair; six waves spill.
+// than K points lie within r, r doubles (exactly) and the point is scanned
+// again; the K-th merged distance never exceeds r, so no closer point was
+// skipped.  Returns whether the K nearest were found; md/mq then hold them in
+// order on every lane of the group.  All lanes of the wave take part (the loop
+// ends when every group is done).
 template <int K>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_knn(SortJob *jobs,
-                                                                                     const PairDev *pairs) {
-    const SortJob &J = jobs[blockIdx.y];
-    if (!J.want_shapes || pairs[J.pair].nonfinite) return;
-    const int n = J.n;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int grp = lane / kGroupLanes, q = lane % kGroupLanes;
-    const int pos = (blockIdx.x * (kBlock / 64) + wave) * kGroupsPerWave + grp;
-    if ((blockIdx.x * (kBlock / 64) + wave) * kGroupsPerWave >= n) return;   // whole wave idle
-    const bool valid = pos < n;
-    const double rho = pairs[J.pair].rho;
-    const Grid G = *J.grid;
-    const uint32_t p = valid ? J.idx[pos] : 0u;
-    const float fx = J.x[p], fy = J.y[p], fz = J.z[p];
+__device__ __forceinline__ bool knn_search(const SortJob &J, const Grid &G, int wave, int grp, int q, bool active,
+                                           float fx, float fy, float fz, double md[K], uint32_t mq[K]) {
+    constexpr int L = kGroupLanes;
+    __shared__ int sh_rs[kBlock / 64][kGroupsPerWave][kMaxRows], sh_rl[kBlock / 64][kGroupsPerWave][kMaxRows];
+    int *rs_t = sh_rs[wave][grp];
+    int *rl_t = sh_rl[wave][grp];
     const double px = fx, py = fy, pz = fz;
     // kNN grids are isotropic (inv_hx == inv_h)
     const float gx = (fx - G.lo[0]) * G.inv_h, gy = (fy - G.lo[1]) * G.inv_h, gz = (fz - G.lo[2]) * G.inv_h;
     const int *cs = J.cell_start;
     const float4 *pts = J.pts;
-    __shared__ int sh_rs[kBlock / 64][kGroupsPerWave][kMaxRows], sh_rl[kBlock / 64][kGroupsPerWave][kMaxRows];
-    int (*rs_t)[kMaxRows] = sh_rs[wave];
-    int (*rl_t)[kMaxRows] = sh_rl[wave];
-
-    double md[K];    // merged K nearest (identical on the group's lanes)
-    uint32_t mq[K];
-    bool done = !valid;
+    bool done = !active;
     double rad = 1.5 * (double)G.h;
-    for (int attempt = 0; attempt < 40; ++attempt) {
+    for (int attempt = 0; attempt < kKnnMaxAttempts; ++attempt) {
         double bd[K];
         uint32_t bq[K];
 #pragma unroll
@@ -540,31 +538,44 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
             const int nrows = (nyr > 0) ? nyr * (z_hi - z_lo + 1) : 0;
             for (int r0 = 0; r0 < nrows; r0 += kMaxRows) {
                 const int nb = min(kMaxRows, nrows - r0);
-                for (int r = q; r < nb; r += kGroupLanes) {
-                    const int cy = y_lo + (r0 + r) % nyr, cz = z_lo + (r0 + r) / nyr;
-                    const float dy = fmaxf(0.0f, fmaxf((float)cy - gy, gy - (float)(cy + 1)));
-                    const float dz = fmaxf(0.0f, fmaxf((float)cz - gz, gz - (float)(cz + 1)));
-                    const float rem = rh * rh - dy * dy - dz * dz;
+                // The table keeps the non-empty rows only, in row order (their
+                // position from a ballot of the group's lanes): the cursor below
+                // then never steps through empty rows one LDS read at a time, and
+                // every lane still sees the same candidates in the same order.
+                int cnt = 0;
+                for (int r1 = 0; r1 < nb; r1 += L) {
+                    const int r = r1 + q;
                     int b = 0, len = 0;
-                    if (rem >= 0.0f) {
-                        const float ext = sqrtf(rem);
-                        const int x_lo = max(0, (int)floorf(gx - ext)), x_hi = min(G.n[0] - 1, (int)floorf(gx + ext));
-                        if (x_lo <= x_hi) {
-                            const int row = G.n[0] * (cy + G.n[1] * cz);
-                            b = cs[row + x_lo];
-                            len = cs[row + x_hi + 1] - b;
+                    if (r < nb) {
+                        const int cy = y_lo + (r0 + r) % nyr, cz = z_lo + (r0 + r) / nyr;
+                        const float dy = fmaxf(0.0f, fmaxf((float)cy - gy, gy - (float)(cy + 1)));
+                        const float dz = fmaxf(0.0f, fmaxf((float)cz - gz, gz - (float)(cz + 1)));
+                        const float rem = rh * rh - dy * dy - dz * dz;
+                        if (rem >= 0.0f) {
+                            const float ext = sqrtf(rem);
+                            const int x_lo = max(0, (int)floorf(gx - ext)), x_hi = min(G.n[0] - 1, (int)floorf(gx + ext));
+                            if (x_lo <= x_hi) {
+                                const int row = G.n[0] * (cy + G.n[1] * cz);
+                                b = cs[row + x_lo];
+                                len = cs[row + x_hi + 1] - b;
+                            }
                         }
                     }
-                    rs_t[grp][r] = b;
-                    rl_t[grp][r] = len;
+                    const unsigned long long m = (__ballot(len > 0) >> (grp * L)) & ((1ull << L) - 1);
+                    if (len > 0) {
+                        const int at = cnt + __popcll(m & ((1ull << q) - 1));
+                        rs_t[at] = b;
+                        rl_t[at] = len;
+                    }
+                    cnt += __popcll(m);
                 }
-                __builtin_amdgcn_wave_barrier();
-                int r = 0, o = q, rs = rs_t[grp][0], rl = rl_t[grp][0];
-                while (r < nb && o >= rl) {
+                __builtin_amdgcn_wave_barrier();   // LDS operations of one wave complete in order
+                int r = 0, o = q, rs = rs_t[0], rl = rl_t[0];
+                while (r < cnt && o >= rl) {
                     o -= rl;
-                    if (++r < nb) { rs = rs_t[grp][r]; rl = rl_t[grp][r]; }
+                    if (++r < cnt) { rs = rs_t[r]; rl = rl_t[r]; }
                 }
-                while (r < nb) {
+                while (r < cnt) {
                     const float4 pc = pts[rs + o];
                     const uint32_t c = __float_as_uint(pc.w);
                     // Exact differences of float32 values in FP64, products and sums
@@ -591,10 +602,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
                             bq[0] = c;
                         }
                     }
-                    o += kGroupLanes;
-                    while (r < nb && o >= rl) {
+                    o += L;
+                    while (r < cnt && o >= rl) {
                         o -= rl;
-                        if (++r < nb) { rs = rs_t[grp][r]; rl = rl_t[grp][r]; }
+                        if (++r < cnt) { rs = rs_t[r]; rl = rl_t[r]; }
                     }
                 }
                 __builtin_amdgcn_wave_barrier();
@@ -603,12 +614,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
         // Merge: K rounds of a lexicographic group minimum over the lists' heads,
         // by DPP row permutations (a minimum is exact, so every lane of the
         // group ends with the same head).
-        auto take_min = [](double &d, uint32_t &c, double od, uint32_t oc) {
-            if (nb_less(od, oc, d, c)) {
-                d = od;
-                c = oc;
-            }
-        };
 #pragma unroll
         for (int m = 0; m < K; ++m) {
             double d = bd[0];
@@ -637,9 +642,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
         }
         if (__all(done)) break;
     }
-    if (!valid || q != 0 || !done) return;
+    return active && done;
+}
 
-    // Covariance about p (eq. (covariance)), FP64, by the group's first lane.
+// Shape of point p from its K nearest neighbours (one lane): covariance about p
+// (eq. (covariance)) in FP64, cyclic Jacobi, and Remark 1's floor of the
+// eigenvalue ratios at rho.
+template <int K>
+__device__ __forceinline__ void knn_shape(const SortJob &J, double rho, uint32_t p, double px, double py, double pz,
+                                          const uint32_t mq[K]) {
     double a[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
 #pragma unroll
     for (int m = 0; m < K; ++m) {
@@ -674,8 +685,34 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
             S[3] += w[m] * u1 * u1; S[4] += w[m] * u1 * u2; S[5] += w[m] * u2 * u2;
         }
     }
+    const int n = J.n;
 #pragma unroll
     for (int e = 0; e < 6; ++e) J.shape_out[(size_t)e * n + p] = (float)S[e];
+}
+
+// kNN shapes of a job's points, kGroupLanes lanes per point.
+// Register budget of five waves per SIMD (96 VGPRs, no spills; 112 VGPRs and
+// four waves otherwise): 11 % shorter on a LiDAR cloud pair; six waves spill.
+template <int K>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_knn(SortJob *jobs,
+                                                                                     const PairDev *pairs) {
+    const SortJob &J = jobs[blockIdx.y];
+    if (!J.want_shapes || pairs[J.pair].nonfinite) return;
+    const int n = J.n;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int grp = lane / kGroupLanes, q = lane % kGroupLanes;
+    const int pos = (blockIdx.x * (kBlock / 64) + wave) * kGroupsPerWave + grp;
+    if ((blockIdx.x * (kBlock / 64) + wave) * kGroupsPerWave >= n) return;   // whole wave idle
+    const bool valid = pos < n;
+    const double rho = pairs[J.pair].rho;
+    const Grid G = *J.grid;
+    const uint32_t p = valid ? J.idx[pos] : 0u;
+    const float fx = J.x[p], fy = J.y[p], fz = J.z[p];
+    double md[K];    // merged K nearest (identical on the group's lanes)
+    uint32_t mq[K];
+    const bool done = knn_search<K>(J, G, wave, grp, q, valid, fx, fy, fz, md, mq);
+    if (!valid || q != 0 || !done) return;
+    knn_shape<K>(J, rho, p, fx, fy, fz, mq);
 }
 
 // ------------------------------------------------------------------ k_gather
