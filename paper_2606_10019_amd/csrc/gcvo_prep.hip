@@ -325,18 +325,29 @@ __global__ __launch_bounds__(256) void k_sort_up(SortJob *jobs, int shift, int p
 
 __global__ __launch_bounds__(256) void k_sort_scan(SortJob *jobs) {
     constexpr int kChunk = 16;   // tile counts in flight per thread
+    constexpr int kHeld = 64;    // jobs of up to kHeld tiles keep their row in registers
     const SortJob &J = jobs[blockIdx.x];
     const int ntile = (J.n + kSortTile - 1) / kSortTile;
     const int d = threadIdx.x, lane = d & 63, wave = d >> 6;
     unsigned *row = J.tile_counts + (size_t)d * ntile;
-    // total of digit d over the tiles (kChunk independent loads at a time)
+    const bool held = ntile <= kHeld;
+    // total of digit d over the tiles: a held row in one round trip, a longer
+    // one kChunk independent loads at a time
     unsigned run = 0;
-    for (int t0 = 0; t0 < ntile; t0 += kChunk) {
-        unsigned v[kChunk];
+    unsigned h[kHeld];
+    if (held) {
 #pragma unroll
-        for (int u = 0; u < kChunk; ++u) v[u] = (t0 + u < ntile) ? row[t0 + u] : 0u;
+        for (int u = 0; u < kHeld; ++u) h[u] = (u < ntile) ? row[u] : 0u;
 #pragma unroll
-        for (int u = 0; u < kChunk; ++u) run += v[u];
+        for (int u = 0; u < kHeld; ++u) run += h[u];
+    } else {
+        for (int t0 = 0; t0 < ntile; t0 += kChunk) {
+            unsigned v[kChunk];
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) v[u] = (t0 + u < ntile) ? row[t0 + u] : 0u;
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) run += v[u];
+        }
     }
     // exclusive scan of the 256 digit totals
     unsigned inc = run;
@@ -352,6 +363,14 @@ __global__ __launch_bounds__(256) void k_sort_scan(SortJob *jobs) {
     for (int w = 0; w < wave; ++w) before += wsum[w];
     // tile t of digit d starts at the digit's base plus the counts of tiles < t
     unsigned acc = before + inc - run;
+    if (held) {
+#pragma unroll
+        for (int u = 0; u < kHeld; ++u) {
+            if (u < ntile) row[u] = acc;
+            acc += h[u];
+        }
+        return;
+    }
     for (int t0 = 0; t0 < ntile; t0 += kChunk) {
         unsigned v[kChunk];
 #pragma unroll
@@ -377,14 +396,24 @@ __global__ __launch_bounds__(256) void k_sort_down(SortJob *jobs, int shift, int
     __shared__ unsigned wcnt[4][256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    constexpr int kRounds = kSortTile / 256;
+    // the tile's keys and indices are requested at once, with its offsets
+    uint32_t keys[kRounds], ids[kRounds];
+#pragma unroll
+    for (int round = 0; round < kRounds; ++round) {
+        const int i = tile * kSortTile + round * 256 + tid;
+        keys[round] = i < J.n ? kin[i] : 0u;
+        ids[round] = i < J.n ? iin[i] : 0u;
+    }
     base_d[tid] = J.tile_counts[(size_t)tid * ntile + tile];
     for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
     __syncthreads();
-    for (int round = 0; round < kSortTile / 256; ++round) {
+#pragma unroll
+    for (int round = 0; round < kRounds; ++round) {
         const int i = tile * kSortTile + round * 256 + tid;
         const bool valid = i < J.n;
-        const uint32_t key = valid ? kin[i] : 0u;
-        const uint32_t id = valid ? iin[i] : 0u;
+        const uint32_t key = keys[round];
+        const uint32_t id = ids[round];
         const unsigned d = valid ? ((key >> shift) & 255u) : 256u;
         unsigned long long same = ~0ull;
 #pragma unroll
