@@ -44,10 +44,11 @@
  * *_workspace_size function returns, aligned to 256 bytes; the library never
  * allocates device memory in these calls and never frees caller memory.
  * The one piece of state the library keeps across calls is a per-device pool
- * of small pinned host buffers (two ints per pair of a call) in which the
- * device reports completion to the polling host; a buffer returns to the pool
- * when the stream has passed the last work that writes it, and the pool is
- * guarded by a mutex, so calls from several threads are safe.
+ * of small pinned host buffers (two ints per pair of a call, plus the pairs'
+ * final states for calls that return them to the host) in which the device
+ * reports completion to the polling host; a buffer returns to the pool when
+ * the stream has passed the last work that writes it, and the pool is guarded
+ * by a mutex, so calls from several threads are safe.
  *
  * Streams.  `stream` is a hipStream_t (NULL = the default stream).  All device
  * work is enqueued on it.  gcvo_register and gcvo_eval_fgh are complete when

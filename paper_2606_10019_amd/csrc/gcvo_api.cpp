@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -293,7 +294,8 @@ void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &p
 }
 
 // Pinned host buffers for the completion flags the device writes (two slots
-// of one int per pair), pooled per device.  Each buffer carries an event
+// of one int per pair) and, for calls that report to the host, each pair's
+// final state up to its reduction splits, pooled per device.  Each buffer carries an event
 // recorded after the last work of the call that used it: it is handed out
 // again only once that event has completed, so the tail of one call's no-op
 // launches can never write into the next call's flags.  Buffers stay in the
@@ -409,10 +411,21 @@ int profile_collect(Plan &pl, int launched, int solver, const std::vector<hipEve
 // Enqueues the iterations chunk by chunk until every pair is done (or
 // max_iters).  With wait, or when the call is measured, it returns after the
 // stream has finished them; otherwise the last chunk may still be queued.
-int run_iterations(Plan &pl, int max_iters, int precision, int solver, hipStream_t s, bool wait) {
+// Bytes of a pair's state the host reads back: everything before the
+// reduction splits (pose, last evaluation, counters, stage record).
+constexpr size_t kReportBytes = offsetof(State, sub);
+static_assert(kReportBytes % 8 == 0, "the report keeps the state's 8-byte alignment");
+
+// With `report` (np States, host), the pairs' final states are copied there:
+// enqueued right after the iterations into the pinned buffer, so that one
+// synchronisation covers the iterations still in flight and the copy.
+int run_iterations(Plan &pl, int max_iters, int precision, int solver, hipStream_t s, bool wait,
+                   State *report = nullptr) {
     const int np = (int)pl.pairs.size();
     if (np == 0) return GCVO_OK;
-    FlagBuf *fb = g_flag_pool.acquire(2 * np);
+    const int report_at = 2 * np;   // ints after the flags: 8 bytes per pair, so the report stays 8-byte aligned
+    const int n_ints = report ? report_at + (int)(kReportBytes / sizeof(int)) * np : 2 * np;
+    FlagBuf *fb = g_flag_pool.acquire(n_ints);
     if (!fb) return GCVO_ERR_HIP;
     int *flags = fb->p;
     hipEvent_t ev[2];
@@ -464,7 +477,14 @@ int run_iterations(Plan &pl, int max_iters, int precision, int solver, hipStream
         }
         slot = other;
     }
-    if ((wait || pl.profile) && hipStreamSynchronize(s) != hipSuccess) rc = GCVO_ERR_HIP;
+    char *rep_buf = reinterpret_cast<char *>(fb->p + report_at);
+    if (report && rc == GCVO_OK &&
+        hipMemcpy2DAsync(rep_buf, kReportBytes, &pl.d_pairs[0].st, sizeof(PairDev), kReportBytes, np,
+                         hipMemcpyDeviceToHost, s) != hipSuccess)
+        rc = GCVO_ERR_HIP;
+    if ((wait || pl.profile || report) && hipStreamSynchronize(s) != hipSuccess) rc = GCVO_ERR_HIP;
+    if (report && rc == GCVO_OK)
+        for (int k = 0; k < np; ++k) std::memcpy(&report[k], rep_buf + kReportBytes * (size_t)k, kReportBytes);
     if (g_flag_pool.release(fb, s) != hipSuccess) rc = GCVO_ERR_HIP;
     hipEventDestroy(ev[0]);
     hipEventDestroy(ev[1]);
@@ -503,13 +523,10 @@ int register_many(Mode mode, std::vector<PairInput> &in, double *T_out, gcvo_inf
     build_plan(ws, mode, in, pl);
     int rc = upload_and_prepare(pl, shared_knn, s);
     if (rc) return rc;
-    rc = run_iterations(pl, max_iters, precision, solver, s, true);
-    if (rc) return rc;
     const int np = (int)in.size();
     std::vector<State> st(np);
-    for (int k = 0; k < np; ++k)
-        HIP_OK(hipMemcpyAsync(&st[k], &pl.d_pairs[k].st, sizeof(State), hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
+    rc = run_iterations(pl, max_iters, precision, solver, s, true, st.data());
+    if (rc) return rc;
     int first_err = GCVO_OK;
     for (int k = 0; k < np; ++k) {
         if (st[k].status == GCVO_OK) std::memcpy(T_out + 16 * (size_t)k, st[k].T, 16 * sizeof(double));
