@@ -351,17 +351,37 @@ FlagPool g_flag_pool;
     } while (0)
 
 int upload_and_prepare(Plan &pl, int knn, hipStream_t s) {
-    // descriptors are contiguous from d_pairs; copy the host vectors into place
-    std::vector<char> blob(pl.desc_bytes, 0);
+    // Descriptors are contiguous from d_pairs: the host vectors are laid out
+    // in a pinned pool buffer and copied in one transfer (a single pair's
+    // launches read no task table, so its blob stops before the table).
     char *d0 = reinterpret_cast<char *>(pl.d_pairs);
-    std::memcpy(blob.data(), pl.pairs.data(), pl.pairs.size() * sizeof(PairDev));
-    std::memcpy(blob.data() + (reinterpret_cast<char *>(pl.d_jobs) - d0), pl.jobs.data(),
-                pl.jobs.size() * sizeof(SortJob));
-    std::memcpy(blob.data() + (reinterpret_cast<char *>(pl.d_tasks) - d0), pl.tasks.data(),
-                pl.tasks.size() * sizeof(BlockTask));
-    std::memcpy(blob.data() + (reinterpret_cast<char *>(pl.d_out) - d0), pl.out.data(),
-                pl.out.size() * sizeof(OutSlot));
-    HIP_OK(hipMemcpyAsync(d0, blob.data(), pl.desc_bytes, hipMemcpyHostToDevice, s));
+    const size_t task_at = reinterpret_cast<char *>(pl.d_tasks) - d0;
+    const bool whole = pl.pairs.size() != 1 || !pl.out.empty();
+    const size_t bytes = whole ? pl.desc_bytes : task_at;
+    // Blobs of up to kPinnedBlob bytes go through the pinned pool; larger ones
+    // (batches of many pairs: mostly task table) through pageable memory, so
+    // that the pool keeps small buffers only.
+    constexpr size_t kPinnedBlob = 256 << 10;
+    std::vector<char> pageable;
+    FlagBuf *fb = nullptr;
+    char *blob;
+    if (bytes <= kPinnedBlob) {
+        fb = g_flag_pool.acquire((int)((bytes + sizeof(int) - 1) / sizeof(int)));
+        if (!fb) return GCVO_ERR_HIP;
+        blob = reinterpret_cast<char *>(fb->p);
+    } else {
+        pageable.resize(bytes);
+        blob = pageable.data();
+    }
+    std::memset(blob, 0, bytes);
+    std::memcpy(blob, pl.pairs.data(), pl.pairs.size() * sizeof(PairDev));
+    std::memcpy(blob + (reinterpret_cast<char *>(pl.d_jobs) - d0), pl.jobs.data(), pl.jobs.size() * sizeof(SortJob));
+    if (whole) {
+        std::memcpy(blob + task_at, pl.tasks.data(), pl.tasks.size() * sizeof(BlockTask));
+        std::memcpy(blob + (reinterpret_cast<char *>(pl.d_out) - d0), pl.out.data(), pl.out.size() * sizeof(OutSlot));
+    }
+    const hipError_t ce = hipMemcpyAsync(d0, blob, bytes, hipMemcpyHostToDevice, s);
+    if ((fb && g_flag_pool.release(fb, s) != hipSuccess) || ce != hipSuccess) return GCVO_ERR_HIP;
     if (pl.pairs.empty()) return GCVO_OK;
     const int n_jobs = (int)pl.jobs.size();
     HIP_OK(launch_prepare(pl.d_pairs, (int)pl.pairs.size(), pl.max_n, pl.d_jobs, n_jobs, pl.max_job_n, pl.max_cells,
