@@ -350,10 +350,13 @@ FlagPool g_flag_pool;
         if ((expr) != hipSuccess) return GCVO_ERR_HIP;      \
     } while (0)
 
-int upload_and_prepare(Plan &pl, int knn, hipStream_t s) {
+// pinned: the blob may be staged in the pinned pool (registrations); the
+// evaluation calls, the no-allocation one among them, pass false and never
+// touch the pool.
+int upload_and_prepare(Plan &pl, int knn, hipStream_t s, bool pinned) {
     // Descriptors are contiguous from d_pairs: the host vectors are laid out
-    // in a pinned pool buffer and copied in one transfer (a single pair's
-    // launches read no task table, so its blob stops before the table).
+    // in one buffer and copied in one transfer (a single pair's launches read
+    // no task table, so its blob stops before the table).
     char *d0 = reinterpret_cast<char *>(pl.d_pairs);
     const size_t task_at = reinterpret_cast<char *>(pl.d_tasks) - d0;
     const bool whole = pl.pairs.size() != 1 || !pl.out.empty();
@@ -365,7 +368,7 @@ int upload_and_prepare(Plan &pl, int knn, hipStream_t s) {
     std::vector<char> pageable;
     FlagBuf *fb = nullptr;
     char *blob;
-    if (bytes <= kPinnedBlob) {
+    if (pinned && bytes <= kPinnedBlob) {
         fb = g_flag_pool.acquire((int)((bytes + sizeof(int) - 1) / sizeof(int)));
         if (!fb) return GCVO_ERR_HIP;
         blob = reinterpret_cast<char *>(fb->p);
@@ -541,7 +544,7 @@ int register_many(Mode mode, std::vector<PairInput> &in, double *T_out, gcvo_inf
     Plan pl;
     pl.profile = profile;
     build_plan(ws, mode, in, pl);
-    int rc = upload_and_prepare(pl, shared_knn, s);
+    int rc = upload_and_prepare(pl, shared_knn, s, true);
     if (rc) return rc;
     const int np = (int)in.size();
     std::vector<State> st(np);
@@ -714,7 +717,7 @@ int register_batch(int n_pairs, const float *tgt_xyz, const float *tgt_label, co
     pl.out = B.out;
     pl.profile = p[0].profile;
     build_plan(workspace, Mode::Register, B.run, pl);
-    rc = upload_and_prepare(pl, p[0].knn, s);
+    rc = upload_and_prepare(pl, p[0].knn, s, true);
     if (rc) return rc;
     rc = run_iterations(pl, max_it, p[0].precision, p[0].solver, s, false);
     if (rc) return rc;
@@ -777,7 +780,7 @@ int eval_fgh(const float *tgt_xyz, const float *tgt_shape6, const float *tgt_lab
     if (!ws_ok(workspace, workspace_bytes, sizing.bytes)) return GCVO_ERR_WORKSPACE;
     Plan pl;
     build_plan(workspace, Mode::Eval, in, pl);
-    int rc = upload_and_prepare(pl, 0, s);
+    int rc = upload_and_prepare(pl, 0, s, false);
     if (rc) return rc;
     HIP_OK(launch_iterations(pl.d_pairs, 1, pl.d_tasks, (int)pl.tasks.size(), 1, precision, GCVO_SOLVER_GN,
                              pl.labels, false, nullptr, s));
@@ -982,7 +985,7 @@ int gcvo_point_shapes_batch(int n_clouds, const float *xyz, const long long *off
     if (!ws_ok(workspace, workspace_bytes, sizing.bytes)) return GCVO_ERR_WORKSPACE;
     Plan pl;
     build_plan(workspace, Mode::Shapes, in, pl);
-    return upload_and_prepare(pl, knn, s);
+    return upload_and_prepare(pl, knn, s, true);
 }
 
 size_t gcvo_eval_batch_workspace_size(int n_pairs, const long long *tgt_off, const long long *src_off) {
@@ -1018,7 +1021,7 @@ int gcvo_eval_fgh_batch(int n_pairs, const float *tgt_xyz, const float *tgt_shap
     Plan pl;
     pl.out = out;
     build_plan(workspace, Mode::Eval, in, pl);
-    rc = upload_and_prepare(pl, 0, s);
+    rc = upload_and_prepare(pl, 0, s, false);
     if (rc) return rc;
     if (!in.empty())
         HIP_OK(launch_iterations(pl.d_pairs, (int)in.size(), pl.d_tasks, (int)pl.tasks.size(), 1, precision,
@@ -1058,7 +1061,7 @@ int gcvo_point_shapes(const float *xyz, long long n, int knn, double rho, float 
     if (!ws_ok(workspace, workspace_bytes, sizing.bytes)) return GCVO_ERR_WORKSPACE;
     Plan pl;
     build_plan(workspace, Mode::Shapes, in, pl);
-    return upload_and_prepare(pl, knn, s);
+    return upload_and_prepare(pl, knn, s, true);
 }
 
 }  // extern "C"
