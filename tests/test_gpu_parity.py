@@ -81,6 +81,21 @@ def test_point_shapes_ragged_and_duplicates():
     np.testing.assert_allclose(S.T, ref, atol=1e-6)
 
 
+def test_point_shapes_sparse_outliers():
+    """A dense flat patch (3001 points in a few grid cells: long candidate walks)
+    and 37 isolated points up to ~80 m out, whose 10th neighbour lies 13-94 m
+    away: their search doubles its radius three to six times over cell rows that
+    are almost all empty (the row table keeps the non-empty ones only)."""
+    rng = np.random.default_rng(11)
+    patch = rng.normal(scale=[2.0, 2.0, 0.05], size=(3001, 3))
+    far = rng.uniform(-80, 80, size=(37, 3)) * np.array([1.0, 1.0, 0.3])
+    P = np.concatenate([patch, far]).astype(np.float32)
+    note("point_shapes dense patch with 37 far outliers")
+    S = gcvo.gcvo_point_shapes(to_dev(P), 10, 0.2).cpu().numpy()
+    ref = O.point_shapes(P.astype(np.float64), 10, 0.2)
+    np.testing.assert_allclose(S.T, ref, atol=1e-6)
+
+
 def _eval_both(spec, SX, SZ, T, ell, precision):
     SXf, SZf = SX.astype(np.float32), SZ.astype(np.float32)
     g = gcvo.gcvo_eval_fgh(to_dev(spec.target), to_dev(SXf.T), to_dev(spec.source), to_dev(SZf.T), T, ell,
