@@ -45,24 +45,6 @@
 
 namespace gcvo {
 
-template <typename R>
-struct Fast;
-template <>
-struct Fast<float> {
-    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-    static __device__ __forceinline__ float exp2(float x) { return __builtin_amdgcn_exp2f(x); }
-};
-template <>
-struct Fast<double> {
-    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
-    static __device__ __forceinline__ double exp2(double x) { return ::exp2(x); }
-};
-
-// ------------------------------------------------------------------ FP64 step
-//
-// All 6x6 algebra below is fully unrolled with compile-time indices so that it
-// stays in registers (one lane per pair runs it).
-
 // 1/x from the hardware estimate refined by two Newton-Raphson steps
 // (r <- r + r (1 - x r), each squaring the relative error): within an ulp or so
 // of the rounded quotient for normal x whose reciprocal is normal, in about a
@@ -74,6 +56,24 @@ __device__ __forceinline__ double rcp_nr(double x) {
     e = fma(-x, r, 1.0);
     return fma(r, e, r);
 }
+
+template <typename R>
+struct Fast;
+template <>
+struct Fast<float> {
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+};
+template <>
+struct Fast<double> {
+    static __device__ __forceinline__ double rcp(double x) { return rcp_nr(x); }   // det > 0 for pairs
+    static __device__ __forceinline__ double exp2(double x) { return ::exp2(x); }
+};
+
+// ------------------------------------------------------------------ FP64 step
+//
+// All 6x6 algebra below is fully unrolled with compile-time indices so that it
+// stays in registers (one lane per pair runs it).
 
 // Solve A x = b (6x6) by Gaussian elimination with partial pivoting on the
 // augmented matrix M = [A | b] (rows swapped in place; b in column 6, so that
