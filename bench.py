@@ -403,7 +403,7 @@ def variants_leg(gcvo, synth, golden, specs, clouds, rot_err_deg, trans_err_m, d
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true", help="skip the RGB-D FP32/FP64 precision leg")
