@@ -244,8 +244,8 @@ void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &p
             pl.max_cells = std::max(pl.max_cells, max_cells);
             return J;
         };
-        // cell tables: at most 16 cells per point (keys stay below 2^30, the radix
-        // sort's 4 passes)
+        // cell tables: at most 16 cells per point (keys stay below 2^30, four radix
+        // passes; below 2^24, three passes, for clouds of up to ~1M points)
         const int knn_cells_t = (int)std::min<long long>(16LL * nt + 64, (1 << 30) - 1);
         const int knn_cells_s = (int)std::min<long long>(16LL * ns + 64, (1 << 30) - 1);
         const int stage_cells = knn_cells_t;

@@ -42,7 +42,7 @@ struct Grid {
     float inv_h;
     int n[3];
     int ncells;
-    int key_bits;   // bits needed to hold ncells - 1 (radix passes = ceil(bits / 8))
+    int key_bits;   // bits needed to hold ncells - 1 (24 for a Morton grid)
     float hx;       // cell edge along x (pair grids may use finer x cells; h otherwise)
     float inv_hx;
 };
@@ -62,7 +62,7 @@ struct SortJob {
     int pair;                 // owning pair
     int kind;                 // kJobKnnTarget, kJobKnnSource or kJobStage + stage
     int want_shapes;          // kNN jobs: 1 = compute shapes into shape_out
-    int morton;               // 1: key = 30-bit Morton code of the 1024^3 grid cell (no cell table)
+    int morton;               // 1: key = 24-bit Morton code of the 256^3 grid cell (no cell table)
     float *shape_out;         // SoA [6][n], original point order
     float4 *pts;              // kNN jobs: {x, y, z, point index bits} in sorted order
 };

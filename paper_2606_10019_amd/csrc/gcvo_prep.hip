@@ -217,19 +217,19 @@ __global__ __launch_bounds__(32) void k_setup(PairDev *pairs) {
         if (P.job_knn_s)
             make_grid(*P.job_knn_s->grid, P.lo_s, P.hi_s, knn_cell(P.lo_s, P.hi_s, P.n_s), P.job_knn_s->max_cells);
     } else if (t == 3) {
-        if (P.job_order_s) {   // 1024 cells along the longest axis; keys are Morton codes
+        if (P.job_order_s) {   // 256 cells along the longest axis; keys are Morton codes
             Grid &M = *P.job_order_s->grid;
             double emax = 0.0;
             for (int d = 0; d < 3; ++d) emax = fmax(emax, (double)P.hi_s[d] - (double)P.lo_s[d]);
-            const double h = (isfinite(emax) && emax > 0.0) ? emax / 1023.5 : 1.0;
+            const double h = (isfinite(emax) && emax > 0.0) ? emax / 255.5 : 1.0;
             for (int d = 0; d < 3; ++d) {
                 M.lo[d] = isfinite(P.lo_s[d]) ? P.lo_s[d] : 0.0f;
-                M.n[d] = 1024;
+                M.n[d] = 256;
             }
             M.h = M.hx = (float)h;
             M.inv_h = M.inv_hx = (float)(1.0 / h);
             M.ncells = 0;
-            M.key_bits = 30;
+            M.key_bits = 24;
         }
     } else if (t - 4 < P.n_stages) {
         // Stage grids over the recentred target.  float(x - c) is monotone in
@@ -271,7 +271,9 @@ __device__ __forceinline__ int cell_coord(float p, float lo, float inv_h, int n)
     return c < 0 ? 0 : (c >= n ? n - 1 : c);
 }
 
-__global__ __launch_bounds__(kBlock) void k_keys(SortJob *jobs) {
+// The keys go to keys_tmp when the sort runs an odd number of passes, so that
+// its last pass leaves them in keys.
+__global__ __launch_bounds__(kBlock) void k_keys(SortJob *jobs, int to_tmp) {
     const SortJob &J = jobs[blockIdx.y];
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= J.n) return;
@@ -281,14 +283,14 @@ __global__ __launch_bounds__(kBlock) void k_keys(SortJob *jobs) {
     int cz = cell_coord(J.z[i], G.lo[2], G.inv_h, G.n[2]);
     if (J.morton) {
         uint32_t key = 0;
-        for (int b = 9; b >= 0; --b)
+        for (int b = 7; b >= 0; --b)
             key = (key << 3) | ((((uint32_t)cz >> b) & 1u) << 2) | ((((uint32_t)cy >> b) & 1u) << 1) |
                   (((uint32_t)cx >> b) & 1u);
-        J.keys[i] = key;
+        (to_tmp ? J.keys_tmp : J.keys)[i] = key;
     } else {
-        J.keys[i] = (uint32_t)(cx + G.n[0] * (cy + G.n[1] * cz));
+        (to_tmp ? J.keys_tmp : J.keys)[i] = (uint32_t)(cx + G.n[0] * (cy + G.n[1] * cz));
     }
-    J.idx[i] = (uint32_t)i;
+    (to_tmp ? J.idx_tmp : J.idx)[i] = (uint32_t)i;
 }
 
 // ------------------------------------------------------------------ radix sort
@@ -305,12 +307,12 @@ __global__ __launch_bounds__(kBlock) void k_keys(SortJob *jobs) {
 
 constexpr int kSortTile = 1024;
 
-__global__ __launch_bounds__(256) void k_sort_up(SortJob *jobs, int shift, int pass) {
+__global__ __launch_bounds__(256) void k_sort_up(SortJob *jobs, int shift, int in_tmp) {
     const SortJob &J = jobs[blockIdx.y];
     const int ntile = (J.n + kSortTile - 1) / kSortTile;
     const int tile = blockIdx.x;
     if (tile >= ntile) return;
-    const uint32_t *kin = (pass & 1) ? J.keys_tmp : J.keys;
+    const uint32_t *kin = in_tmp ? J.keys_tmp : J.keys;
     __shared__ unsigned hist[256];
     hist[threadIdx.x] = 0;
     __syncthreads();
@@ -383,15 +385,15 @@ __global__ __launch_bounds__(256) void k_sort_scan(SortJob *jobs) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_sort_down(SortJob *jobs, int shift, int pass) {
+__global__ __launch_bounds__(256) void k_sort_down(SortJob *jobs, int shift, int in_tmp) {
     const SortJob &J = jobs[blockIdx.y];
     const int ntile = (J.n + kSortTile - 1) / kSortTile;
     const int tile = blockIdx.x;
     if (tile >= ntile) return;
-    const uint32_t *kin = (pass & 1) ? J.keys_tmp : J.keys;
-    const uint32_t *iin = (pass & 1) ? J.idx_tmp : J.idx;
-    uint32_t *kout = (pass & 1) ? J.keys : J.keys_tmp;
-    uint32_t *iout = (pass & 1) ? J.idx : J.idx_tmp;
+    const uint32_t *kin = in_tmp ? J.keys_tmp : J.keys;
+    const uint32_t *iin = in_tmp ? J.idx_tmp : J.idx;
+    uint32_t *kout = in_tmp ? J.keys : J.keys_tmp;
+    uint32_t *iout = in_tmp ? J.idx : J.idx_tmp;
     __shared__ unsigned base_d[256];    // next free slot of each digit for this tile
     __shared__ unsigned wcnt[4][256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -871,14 +873,18 @@ hipError_t launch_prepare(PairDev *pairs, int n_pairs, int max_n, SortJob *jobs,
     if (bx > 0) hipLaunchKernelGGL(k_soa, dim3(bx, 2 * n_pairs), dim3(kBlock), 0, s, pairs);
     const int jx = (max_job_n + kBlock - 1) / kBlock;
     if (n_jobs > 0 && jx > 0) {
-        hipLaunchKernelGGL(k_keys, dim3(jx, n_jobs), dim3(kBlock), 0, s, jobs);
-        // Every job's keys fit in 30 bits: 4 passes (a job with fewer key bits
-        // sorts stably on zero digits in its last passes).
+        // Cell keys are below max_cells and Morton keys below 2^24: three 8-bit
+        // passes while every cell table has at most 2^24 cells, four otherwise
+        // (a job with fewer key bits sorts stably on zero digits in its last
+        // passes).  The passes alternate between the two buffers and end in keys.
+        const int passes = max_cells <= (1 << 24) ? 3 : 4;
+        hipLaunchKernelGGL(k_keys, dim3(jx, n_jobs), dim3(kBlock), 0, s, jobs, passes & 1);
         const int tiles = (max_job_n + kSortTile - 1) / kSortTile;
-        for (int pass = 0; pass < 4; ++pass) {
-            hipLaunchKernelGGL(k_sort_up, dim3(tiles, n_jobs), dim3(256), 0, s, jobs, 8 * pass, pass);
+        for (int pass = 0; pass < passes; ++pass) {
+            const int in_tmp = (passes - pass) & 1;
+            hipLaunchKernelGGL(k_sort_up, dim3(tiles, n_jobs), dim3(256), 0, s, jobs, 8 * pass, in_tmp);
             hipLaunchKernelGGL(k_sort_scan, dim3(n_jobs), dim3(256), 0, s, jobs);
-            hipLaunchKernelGGL(k_sort_down, dim3(tiles, n_jobs), dim3(256), 0, s, jobs, 8 * pass, pass);
+            hipLaunchKernelGGL(k_sort_down, dim3(tiles, n_jobs), dim3(256), 0, s, jobs, 8 * pass, in_tmp);
         }
         hipLaunchKernelGGL(k_cells, dim3((max_cells + kBlock) / kBlock, n_jobs), dim3(kBlock), 0, s, jobs);
         if (knn > 0) {
