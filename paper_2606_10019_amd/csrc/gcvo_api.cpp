@@ -203,6 +203,7 @@ void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &p
         P.cell_fraction_x = I.p.cell_fraction_x;
         std::memcpy(P.T_init, I.T0, sizeof P.T_init);
         P.T_init_dev = I.T0_dev;
+        P.stat_part = A.take<double>(2 * kStatBlocks * kStatVals);
         P.t_orig = A.take<float>(3 * (size_t)nt);
         P.s_orig = A.take<float>(3 * (size_t)ns);
         P.t_rec = A.take<float>(3 * (size_t)nt);

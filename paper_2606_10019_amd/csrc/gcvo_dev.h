@@ -15,7 +15,8 @@
 namespace gcvo {
 
 constexpr int kBlock = 256;           // threads of point-parallel kernels (4 waves)
-constexpr int kSortThreads = 1024;    // threads of the one-block-per-job radix sort
+constexpr int kStatBlocks = 16;      // bounds kernel: blocks per cloud
+constexpr int kStatVals = 10;        // per bounds block: 3 FP64 sums, 3 minima, 3 maxima, non-finite flag
 constexpr int kMaxStages = GCVO_MAX_STAGES;
 constexpr int kMaxKnn = GCVO_MAX_KNN;
 constexpr int kNumSums = 28;          // f, g (6), upper triangle of H_main (21)
@@ -58,7 +59,7 @@ struct SortJob {
     Grid *grid;               // written by the setup kernel
     uint32_t *keys, *keys_tmp, *idx, *idx_tmp;   // idx: sorted position -> point index
     int *cell_start;
-    unsigned *tile_counts;    // radix sort scratch: [256][ceil(n / 1024)] digit counts, then offsets
+    unsigned *tile_counts;    // radix sort scratch: [ceil(n / 1024)][256] digit counts per tile, then offsets
     int pair;                 // owning pair
     int kind;                 // kJobKnnTarget, kJobKnnSource or kJobStage + stage
     int want_shapes;          // kNN jobs: 1 = compute shapes into shape_out
@@ -114,8 +115,7 @@ struct PairDev {
     const double *T_init_dev;         // device [16] start pose (batch calls), checked to be in SE(3); or null: T_init
     // derived on device
     double centre[3];                 // target centroid, subtracted before the FP32 cast
-    double sum_t[3];                  // FP64 coordinate sums of the target
-    float lo_t[3], hi_t[3], lo_s[3], hi_s[3];   // bounding boxes of the original coordinates
+    double *stat_part;                // [2][kStatBlocks][kStatVals] bounds of target and source, per block
     int nonfinite;                    // 1 if any input coordinate is NaN or Inf
     // workspace arrays
     float *t_orig, *s_orig;           // SoA [3][n] original coordinates (kNN grids)
@@ -157,6 +157,18 @@ struct BlockTask {   // one block of the pair kernel: a pair and a 256-point sli
     int pair;
     int block;       // block index within the pair
 };
+
+// Native 4-float vector (float4 is a class whose members expect generic
+// addresses; this type loads and stores through any address space).
+typedef float __attribute__((ext_vector_type(4))) vf4;
+
+// Global-memory view of a generic pointer to device memory: accesses through it
+// are global instructions, not flat ones (a flat access also counts against the
+// counter of LDS and scalar loads, so waiting for it waits for those as well).
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gmem(T *p) {
+    return (__attribute__((address_space(1))) T *)p;
+}
 
 // ---------------------------------------------------------------- wave helpers
 

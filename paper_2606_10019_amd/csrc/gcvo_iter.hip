@@ -346,7 +346,6 @@ struct ModeInfo {
                                                                       : kSumsLine;
 };
 
-typedef float __attribute__((ext_vector_type(4))) vf4;
 typedef const vf4 __attribute__((address_space(1))) *GRec4;
 
 template <typename Real>

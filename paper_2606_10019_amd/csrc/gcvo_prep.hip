@@ -17,11 +17,16 @@
 namespace gcvo {
 
 // ------------------------------------------------------------------ k_stats
+//
+// Bounds of each cloud, kStatBlocks blocks per cloud: block b takes the points
+// b * 256 + tid + m * 256 * kStatBlocks and stores its FP64 coordinate sums,
+// minima, maxima and a non-finite flag; the setup kernel combines the blocks in
+// a fixed order.
 
-__global__ __launch_bounds__(1024) void k_stats(PairDev *pairs) {
-    const int pair = blockIdx.x >> 1, cloud = blockIdx.x & 1;
-    PairDev &P = pairs[pair];
-    const float *xyz = cloud == 0 ? P.tgt_xyz : P.src_xyz;
+__global__ __launch_bounds__(kBlock) void k_stats(PairDev *pairs) {
+    const int cloud = blockIdx.x / kStatBlocks, part = blockIdx.x % kStatBlocks;
+    const PairDev &P = pairs[blockIdx.y];
+    const auto xyz = gmem<const float>(cloud == 0 ? P.tgt_xyz : P.src_xyz);
     const int n = cloud == 0 ? P.n_t : P.n_s;
     const int tid = threadIdx.x;
     double s[3] = {0.0, 0.0, 0.0};
@@ -29,18 +34,18 @@ __global__ __launch_bounds__(1024) void k_stats(PairDev *pairs) {
     int bad = 0;
     // Eight points' loads in flight per trip; they are added in the same order
     // as one at a time.
-    constexpr int kAhead = 8;
-    for (int i0 = tid; i0 < n; i0 += 1024 * kAhead) {
+    constexpr int kAhead = 8, kStride = kBlock * kStatBlocks;
+    for (int i0 = part * kBlock + tid; i0 < n; i0 += kStride * kAhead) {
         float v[kAhead][3];
 #pragma unroll
         for (int u = 0; u < kAhead; ++u) {
-            const int i = i0 + 1024 * u;
+            const int i = i0 + kStride * u;
 #pragma unroll
             for (int d = 0; d < 3; ++d) v[u][d] = (i < n) ? xyz[3 * (size_t)i + d] : 0.0f;
         }
 #pragma unroll
         for (int u = 0; u < kAhead; ++u) {
-            if (i0 + 1024 * u >= n) break;
+            if (i0 + kStride * u >= n) break;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 if (!isfinite(v[u][d])) bad = 1;
@@ -50,9 +55,10 @@ __global__ __launch_bounds__(1024) void k_stats(PairDev *pairs) {
             }
         }
     }
-    __shared__ double sh_s[3][16];
-    __shared__ float sh_lo[3][16], sh_hi[3][16];
-    __shared__ int sh_bad[16];
+    constexpr int kWaves = kBlock / 64;
+    __shared__ double sh_s[3][kWaves];
+    __shared__ float sh_lo[3][kWaves], sh_hi[3][kWaves];
+    __shared__ int sh_bad[kWaves];
     const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -74,7 +80,7 @@ __global__ __launch_bounds__(1024) void k_stats(PairDev *pairs) {
         double ts[3] = {0, 0, 0};
         float tl[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, th[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
         int tb = 0;
-        for (int w = 0; w < 16; ++w) {
+        for (int w = 0; w < kWaves; ++w) {
             for (int d = 0; d < 3; ++d) {
                 ts[d] += sh_s[d][w];
                 tl[d] = fminf(tl[d], sh_lo[d][w]);
@@ -82,17 +88,13 @@ __global__ __launch_bounds__(1024) void k_stats(PairDev *pairs) {
             }
             tb |= sh_bad[w];
         }
+        const auto out = gmem(P.stat_part) + (size_t)blockIdx.x * kStatVals;
         for (int d = 0; d < 3; ++d) {
-            if (cloud == 0) {
-                P.sum_t[d] = ts[d];
-                P.lo_t[d] = tl[d];
-                P.hi_t[d] = th[d];
-            } else {
-                P.lo_s[d] = tl[d];
-                P.hi_s[d] = th[d];
-            }
+            out[d] = ts[d];
+            out[3 + d] = tl[d];
+            out[6 + d] = th[d];
         }
-        if (tb) atomicOr(&P.nonfinite, 1);
+        out[9] = tb;
     }
 }
 
@@ -185,8 +187,30 @@ __device__ bool in_se3(const double T[16]) {
 __global__ __launch_bounds__(32) void k_setup(PairDev *pairs) {
     PairDev &P = pairs[blockIdx.x];
     const int t = threadIdx.x;
+    // The bounds kernel's partials: lane l < kStatBlocks holds the target's block
+    // l, lane kStatBlocks + l the source's.  A butterfly over each half adds
+    // every pair of values in both orders, so all its lanes hold bitwise the
+    // same totals.
+    static_assert(2 * kStatBlocks == 32, "one setup lane per bounds block");
+    double v[kStatVals];
+    for (int k = 0; k < kStatVals; ++k) v[k] = P.stat_part[t * kStatVals + k];
+    for (int off = kStatBlocks / 2; off > 0; off >>= 1) {
+        for (int k = 0; k < kStatVals; ++k) {
+            const double o = __shfl_xor(v[k], off, kStatBlocks);
+            v[k] = k < 3 ? v[k] + o : (k < 6 ? fmin(v[k], o) : fmax(v[k], o));
+        }
+    }
     double c[3];
-    for (int d = 0; d < 3; ++d) c[d] = P.n_t > 0 ? P.sum_t[d] / (double)P.n_t : 0.0;
+    float lo_t[3], hi_t[3], lo_s[3], hi_s[3];
+    for (int d = 0; d < 3; ++d) {
+        const double sum_t = __shfl(v[d], 0);
+        c[d] = P.n_t > 0 ? sum_t / (double)P.n_t : 0.0;
+        lo_t[d] = (float)__shfl(v[3 + d], 0);
+        hi_t[d] = (float)__shfl(v[6 + d], 0);
+        lo_s[d] = (float)__shfl(v[3 + d], kStatBlocks);
+        hi_s[d] = (float)__shfl(v[6 + d], kStatBlocks);
+    }
+    const bool nonfinite = __shfl(v[9], 0) != 0.0 || __shfl(v[9], kStatBlocks) != 0.0;
     if (t == 0) {
         for (int d = 0; d < 3; ++d) P.centre[d] = c[d];
         State &S = P.st;
@@ -207,23 +231,24 @@ __global__ __launch_bounds__(32) void k_setup(PairDev *pairs) {
         S.gnorm = 0.0;
         for (int a = 0; a < 6; ++a) S.dir[a] = 0.0;
         for (int s = 0; s < kMaxStages; ++s) S.stage_iters[s] = 0;
-        const bool bad = P.nonfinite || !pose_ok;
+        if (nonfinite) P.nonfinite = 1;
+        const bool bad = nonfinite || !pose_ok;
         S.status = bad ? GCVO_ERR_INVALID : GCVO_OK;
         S.done = bad ? 1 : 0;
     } else if (t == 1) {
         if (P.job_knn_t)
-            make_grid(*P.job_knn_t->grid, P.lo_t, P.hi_t, knn_cell(P.lo_t, P.hi_t, P.n_t), P.job_knn_t->max_cells);
+            make_grid(*P.job_knn_t->grid, lo_t, hi_t, knn_cell(lo_t, hi_t, P.n_t), P.job_knn_t->max_cells);
     } else if (t == 2) {
         if (P.job_knn_s)
-            make_grid(*P.job_knn_s->grid, P.lo_s, P.hi_s, knn_cell(P.lo_s, P.hi_s, P.n_s), P.job_knn_s->max_cells);
+            make_grid(*P.job_knn_s->grid, lo_s, hi_s, knn_cell(lo_s, hi_s, P.n_s), P.job_knn_s->max_cells);
     } else if (t == 3) {
         if (P.job_order_s) {   // 256 cells along the longest axis; keys are Morton codes
             Grid &M = *P.job_order_s->grid;
             double emax = 0.0;
-            for (int d = 0; d < 3; ++d) emax = fmax(emax, (double)P.hi_s[d] - (double)P.lo_s[d]);
+            for (int d = 0; d < 3; ++d) emax = fmax(emax, (double)hi_s[d] - (double)lo_s[d]);
             const double h = (isfinite(emax) && emax > 0.0) ? emax / 255.5 : 1.0;
             for (int d = 0; d < 3; ++d) {
-                M.lo[d] = isfinite(P.lo_s[d]) ? P.lo_s[d] : 0.0f;
+                M.lo[d] = isfinite(lo_s[d]) ? lo_s[d] : 0.0f;
                 M.n[d] = 256;
             }
             M.h = M.hx = (float)h;
@@ -237,8 +262,8 @@ __global__ __launch_bounds__(32) void k_setup(PairDev *pairs) {
         const int s = t - 4;
         float lo[3], hi[3];
         for (int d = 0; d < 3; ++d) {
-            lo[d] = (float)((double)P.lo_t[d] - c[d]);
-            hi[d] = (float)((double)P.hi_t[d] - c[d]);
+            lo[d] = (float)((double)lo_t[d] - c[d]);
+            hi[d] = (float)((double)hi_t[d] - c[d]);
         }
         make_grid(P.t_grid[s], lo, hi, P.cell_fraction * P.cutoff_scale * P.ell[s], P.job_stage0[s].max_cells,
                   P.cell_fraction_x / P.cell_fraction);
@@ -253,13 +278,13 @@ __global__ __launch_bounds__(kBlock) void k_soa(PairDev *pairs) {
     const int n = cloud == 0 ? P.n_t : P.n_s;
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    const float *xyz = cloud == 0 ? P.tgt_xyz : P.src_xyz;
+    const auto xyz = gmem<const float>(cloud == 0 ? P.tgt_xyz : P.src_xyz);
     float *orig = cloud == 0 ? P.t_orig : P.s_orig;
-    float *rec = cloud == 0 ? P.t_rec : P.s_rec;
+    const auto rec = gmem(cloud == 0 ? P.t_rec : P.s_rec);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         float v = xyz[3 * (size_t)i + d];
-        if (orig) orig[(size_t)d * n + i] = v;
+        if (orig) gmem(orig)[(size_t)d * n + i] = v;
         rec[(size_t)d * n + i] = (float)((double)v - P.centre[d]);
     }
 }
@@ -278,19 +303,19 @@ __global__ __launch_bounds__(kBlock) void k_keys(SortJob *jobs, int to_tmp) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= J.n) return;
     const Grid G = *J.grid;
-    int cx = cell_coord(J.x[i], G.lo[0], G.inv_hx, G.n[0]);
-    int cy = cell_coord(J.y[i], G.lo[1], G.inv_h, G.n[1]);
-    int cz = cell_coord(J.z[i], G.lo[2], G.inv_h, G.n[2]);
+    int cx = cell_coord(gmem<const float>(J.x)[i], G.lo[0], G.inv_hx, G.n[0]);
+    int cy = cell_coord(gmem<const float>(J.y)[i], G.lo[1], G.inv_h, G.n[1]);
+    int cz = cell_coord(gmem<const float>(J.z)[i], G.lo[2], G.inv_h, G.n[2]);
     if (J.morton) {
         uint32_t key = 0;
         for (int b = 7; b >= 0; --b)
             key = (key << 3) | ((((uint32_t)cz >> b) & 1u) << 2) | ((((uint32_t)cy >> b) & 1u) << 1) |
                   (((uint32_t)cx >> b) & 1u);
-        (to_tmp ? J.keys_tmp : J.keys)[i] = key;
+        gmem(to_tmp ? J.keys_tmp : J.keys)[i] = key;
     } else {
-        (to_tmp ? J.keys_tmp : J.keys)[i] = (uint32_t)(cx + G.n[0] * (cy + G.n[1] * cz));
+        gmem(to_tmp ? J.keys_tmp : J.keys)[i] = (uint32_t)(cx + G.n[0] * (cy + G.n[1] * cz));
     }
-    (to_tmp ? J.idx_tmp : J.idx)[i] = (uint32_t)i;
+    gmem(to_tmp ? J.idx_tmp : J.idx)[i] = (uint32_t)i;
 }
 
 // ------------------------------------------------------------------ radix sort
@@ -312,7 +337,7 @@ __global__ __launch_bounds__(256) void k_sort_up(SortJob *jobs, int shift, int i
     const int ntile = (J.n + kSortTile - 1) / kSortTile;
     const int tile = blockIdx.x;
     if (tile >= ntile) return;
-    const uint32_t *kin = in_tmp ? J.keys_tmp : J.keys;
+    const auto kin = gmem<const uint32_t>(in_tmp ? J.keys_tmp : J.keys);
     __shared__ unsigned hist[256];
     hist[threadIdx.x] = 0;
     __syncthreads();
@@ -322,7 +347,7 @@ __global__ __launch_bounds__(256) void k_sort_up(SortJob *jobs, int shift, int i
         if (i < J.n) atomicAdd(&hist[(kin[i] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    J.tile_counts[(size_t)threadIdx.x * ntile + tile] = hist[threadIdx.x];
+    gmem(J.tile_counts)[(size_t)tile * 256 + threadIdx.x] = hist[threadIdx.x];
 }
 
 __global__ __launch_bounds__(256) void k_sort_scan(SortJob *jobs) {
@@ -331,7 +356,9 @@ __global__ __launch_bounds__(256) void k_sort_scan(SortJob *jobs) {
     const SortJob &J = jobs[blockIdx.x];
     const int ntile = (J.n + kSortTile - 1) / kSortTile;
     const int d = threadIdx.x, lane = d & 63, wave = d >> 6;
-    unsigned *row = J.tile_counts + (size_t)d * ntile;
+    // digit d of tile t at tc[t * 256 + d]: a wave's 64 digits of one tile are
+    // one contiguous 256-byte access
+    const auto tc = gmem(J.tile_counts) + d;
     const bool held = ntile <= kHeld;
     // total of digit d over the tiles: a held row in one round trip, a longer
     // one kChunk independent loads at a time
@@ -339,14 +366,14 @@ __global__ __launch_bounds__(256) void k_sort_scan(SortJob *jobs) {
     unsigned h[kHeld];
     if (held) {
 #pragma unroll
-        for (int u = 0; u < kHeld; ++u) h[u] = (u < ntile) ? row[u] : 0u;
+        for (int u = 0; u < kHeld; ++u) h[u] = (u < ntile) ? tc[(size_t)u * 256] : 0u;
 #pragma unroll
         for (int u = 0; u < kHeld; ++u) run += h[u];
     } else {
         for (int t0 = 0; t0 < ntile; t0 += kChunk) {
             unsigned v[kChunk];
 #pragma unroll
-            for (int u = 0; u < kChunk; ++u) v[u] = (t0 + u < ntile) ? row[t0 + u] : 0u;
+            for (int u = 0; u < kChunk; ++u) v[u] = (t0 + u < ntile) ? tc[(size_t)(t0 + u) * 256] : 0u;
 #pragma unroll
             for (int u = 0; u < kChunk; ++u) run += v[u];
         }
@@ -368,7 +395,7 @@ __global__ __launch_bounds__(256) void k_sort_scan(SortJob *jobs) {
     if (held) {
 #pragma unroll
         for (int u = 0; u < kHeld; ++u) {
-            if (u < ntile) row[u] = acc;
+            if (u < ntile) tc[(size_t)u * 256] = acc;
             acc += h[u];
         }
         return;
@@ -376,10 +403,10 @@ __global__ __launch_bounds__(256) void k_sort_scan(SortJob *jobs) {
     for (int t0 = 0; t0 < ntile; t0 += kChunk) {
         unsigned v[kChunk];
 #pragma unroll
-        for (int u = 0; u < kChunk; ++u) v[u] = (t0 + u < ntile) ? row[t0 + u] : 0u;
+        for (int u = 0; u < kChunk; ++u) v[u] = (t0 + u < ntile) ? tc[(size_t)(t0 + u) * 256] : 0u;
 #pragma unroll
         for (int u = 0; u < kChunk; ++u) {
-            if (t0 + u < ntile) row[t0 + u] = acc;
+            if (t0 + u < ntile) tc[(size_t)(t0 + u) * 256] = acc;
             acc += v[u];
         }
     }
@@ -390,10 +417,10 @@ __global__ __launch_bounds__(256) void k_sort_down(SortJob *jobs, int shift, int
     const int ntile = (J.n + kSortTile - 1) / kSortTile;
     const int tile = blockIdx.x;
     if (tile >= ntile) return;
-    const uint32_t *kin = in_tmp ? J.keys_tmp : J.keys;
-    const uint32_t *iin = in_tmp ? J.idx_tmp : J.idx;
-    uint32_t *kout = in_tmp ? J.keys : J.keys_tmp;
-    uint32_t *iout = in_tmp ? J.idx : J.idx_tmp;
+    const auto kin = gmem<const uint32_t>(in_tmp ? J.keys_tmp : J.keys);
+    const auto iin = gmem<const uint32_t>(in_tmp ? J.idx_tmp : J.idx);
+    const auto kout = gmem(in_tmp ? J.keys : J.keys_tmp);
+    const auto iout = gmem(in_tmp ? J.idx : J.idx_tmp);
     __shared__ unsigned base_d[256];    // next free slot of each digit for this tile
     __shared__ unsigned wcnt[4][256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -407,7 +434,7 @@ __global__ __launch_bounds__(256) void k_sort_down(SortJob *jobs, int shift, int
         keys[round] = i < J.n ? kin[i] : 0u;
         ids[round] = i < J.n ? iin[i] : 0u;
     }
-    base_d[tid] = J.tile_counts[(size_t)tid * ntile + tile];
+    base_d[tid] = gmem(J.tile_counts)[(size_t)tile * 256 + tid];
     for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
     __syncthreads();
 #pragma unroll
@@ -448,22 +475,68 @@ __global__ __launch_bounds__(256) void k_sort_down(SortJob *jobs, int shift, int
     }
 }
 
-// cell_start[c] = first sorted position whose key is >= c (binary search over
-// the sorted keys, one thread per cell), so cell_start[ncells] = n.
+// cell_start[c] = first sorted position whose key is >= c, for c = 0..ncells.
+// Sorted position i (0 <= i <= n) is that position for the cells after the
+// previous key up to its own key (position 0 from cell 0, position n, one past
+// the end, up to cell ncells), so every cell is written once.  A lane writes a
+// run of up to kShortRun cells itself; a wave writes its lanes' longer runs one
+// after another, its 64 lanes storing consecutive cells; runs longer than
+// kLongRun cells (empty stretches of the grid, up to ~50k cells in a LiDAR
+// scene) are listed in LDS and written by the whole block.
 __global__ __launch_bounds__(kBlock) void k_cells(SortJob *jobs) {
     const SortJob &J = jobs[blockIdx.y];
     if (J.morton || !J.cell_start) return;
     const int n = J.n, ncells = J.grid->ncells;
-    const int c = blockIdx.x * kBlock + threadIdx.x;
-    if (c > ncells) return;
-    const uint32_t *K = J.keys;
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if ((int)K[mid] < c) lo = mid + 1;
-        else hi = mid;
+    if (blockIdx.x * kBlock > n) return;   // the whole block is past the end
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    // global-memory pointers: plain loads and stores, not flat ones
+    typedef const __attribute__((address_space(1))) uint32_t *GKey;
+    typedef __attribute__((address_space(1))) int *GCell;
+    const GKey keys = (GKey)J.keys;
+    const GCell cs = (GCell)J.cell_start;
+    int first = 0, len = 0;     // cells [first, first + len) take position i
+    if (i <= n) {
+        const int prev = i > 0 ? (int)keys[i - 1] : -1;
+        const int cur = i < n ? (int)keys[i] : ncells;
+        first = prev + 1;
+        len = cur - prev;
     }
-    J.cell_start[c] = lo;
+    constexpr int kShortRun = 8, kLongRun = 4 * 64;
+    __shared__ int long_first[kBlock], long_len[kBlock], long_pos[kBlock];
+    __shared__ int n_long;
+    if (threadIdx.x == 0) n_long = 0;
+    __syncthreads();
+    const bool is_long = len > kLongRun;
+    if (is_long) {   // list order is arbitrary: the runs are disjoint
+        const int at = atomicAdd(&n_long, 1);
+        long_first[at] = first;
+        long_len[at] = len;
+        long_pos[at] = i;
+    }
+    if (len <= kShortRun) {
+#pragma unroll
+        for (int c = 0; c < kShortRun; ++c)
+            if (c < len) cs[first + c] = i;
+    }
+    unsigned long long m = __ballot(len > kShortRun && !is_long);
+    while (m) {   // l is the same in every lane: its values come by lane reads
+        const int l = __builtin_ctzll(m);
+        m &= m - 1;
+        const int f = __builtin_amdgcn_readlane(first, l), cnt = __builtin_amdgcn_readlane(len, l);
+        const int pos = i - lane + l;
+        for (int c = lane; c < cnt; c += 64) cs[f + c] = pos;
+    }
+    __syncthreads();
+    const int nl = n_long;
+    for (int r = 0; r < nl; ++r) {
+        const int f = long_first[r], cnt = long_len[r], pos = long_pos[r];
+        for (int c = threadIdx.x; c < cnt; c += 4 * kBlock) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (c + u * kBlock < cnt) cs[f + c + u * kBlock] = pos;
+        }
+    }
 }
 
 // ------------------------------------------------------------------ k_knn
@@ -513,8 +586,9 @@ __global__ __launch_bounds__(kBlock) void k_knn_pts(SortJob *jobs, const PairDev
     if (!J.want_shapes || pairs[J.pair].nonfinite) return;
     const int pos = blockIdx.x * kBlock + threadIdx.x;
     if (pos >= J.n) return;
-    const uint32_t c = J.idx[pos];
-    J.pts[pos] = make_float4(J.x[c], J.y[c], J.z[c], __uint_as_float(c));
+    const uint32_t c = gmem(J.idx)[pos];
+    gmem(reinterpret_cast<vf4 *>(J.pts))[pos] =
+        vf4{gmem<const float>(J.x)[c], gmem<const float>(J.y)[c], gmem<const float>(J.z)[c], __uint_as_float(c)};
 }
 
 constexpr int kKnnMaxAttempts = 40;   // radius attempts 1.5 h 2^a, a < 40
@@ -547,8 +621,8 @@ __device__ __forceinline__ bool knn_search(const SortJob &J, const Grid &G, int 
     const double px = fx, py = fy, pz = fz;
     // kNN grids are isotropic (inv_hx == inv_h)
     const float gx = (fx - G.lo[0]) * G.inv_h, gy = (fy - G.lo[1]) * G.inv_h, gz = (fz - G.lo[2]) * G.inv_h;
-    const int *cs = J.cell_start;
-    const float4 *pts = J.pts;
+    const auto cs = gmem<const int>(J.cell_start);
+    const auto pts = gmem(reinterpret_cast<const vf4 *>(J.pts));
     bool done = !active;
     double rad = 1.5 * (double)G.h;
     for (int attempt = 0; attempt < kKnnMaxAttempts; ++attempt) {
@@ -607,7 +681,7 @@ __device__ __forceinline__ bool knn_search(const SortJob &J, const Grid &G, int 
                     if (++r < cnt) { rs = rs_t[r]; rl = rl_t[r]; }
                 }
                 while (r < cnt) {
-                    const float4 pc = pts[rs + o];
+                    const vf4 pc = pts[rs + o];
                     const uint32_t c = __float_as_uint(pc.w);
                     // Exact differences of float32 values in FP64, products and sums
                     // in written order without contraction: reproducible ranking.
@@ -683,10 +757,11 @@ template <int K>
 __device__ __forceinline__ void knn_shape(const SortJob &J, double rho, uint32_t p, double px, double py, double pz,
                                           const uint32_t mq[K]) {
     double a[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    const auto X = gmem<const float>(J.x), Y = gmem<const float>(J.y), Z = gmem<const float>(J.z);
 #pragma unroll
     for (int m = 0; m < K; ++m) {
         const uint32_t c = mq[m];
-        const double d0 = (double)J.x[c] - px, d1 = (double)J.y[c] - py, d2 = (double)J.z[c] - pz;
+        const double d0 = (double)X[c] - px, d1 = (double)Y[c] - py, d2 = (double)Z[c] - pz;
         a[0][0] += d0 * d0; a[0][1] += d0 * d1; a[0][2] += d0 * d2;
         a[1][1] += d1 * d1; a[1][2] += d1 * d2; a[2][2] += d2 * d2;
     }
@@ -717,8 +792,9 @@ __device__ __forceinline__ void knn_shape(const SortJob &J, double rho, uint32_t
         }
     }
     const int n = J.n;
+    const auto out = gmem(J.shape_out);
 #pragma unroll
-    for (int e = 0; e < 6; ++e) J.shape_out[(size_t)e * n + p] = (float)S[e];
+    for (int e = 0; e < 6; ++e) out[(size_t)e * n + p] = (float)S[e];
 }
 
 // kNN shapes of a job's points, kGroupLanes lanes per point.
@@ -737,8 +813,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     const bool valid = pos < n;
     const double rho = pairs[J.pair].rho;
     const Grid G = *J.grid;
-    const uint32_t p = valid ? J.idx[pos] : 0u;
-    const float fx = J.x[p], fy = J.y[p], fz = J.z[p];
+    const uint32_t p = valid ? gmem(J.idx)[pos] : 0u;
+    const float fx = gmem<const float>(J.x)[p], fy = gmem<const float>(J.y)[p], fz = gmem<const float>(J.z)[p];
     double md[K];    // merged K nearest (identical on the group's lanes)
     uint32_t mq[K];
     const bool done = knn_search<K>(J, G, wave, grp, q, valid, fx, fy, fz, md, mq);
@@ -754,41 +830,41 @@ __global__ __launch_bounds__(kBlock) void k_gather(SortJob *jobs, const PairDev 
     const int pos = blockIdx.x * kBlock + threadIdx.x;
     if (pos >= J.n) return;
     const PairDev &P = pairs[J.pair];
-    const uint32_t p = J.idx[pos];
+    const uint32_t p = gmem(J.idx)[pos];
     const bool src = J.kind == kJobOrderSource;
     const int n = J.n;
-    const float *rec = src ? P.s_rec : P.t_rec;
-    const float *org = src ? P.s_orig : P.t_orig;
-    const float *shp = src ? P.s_shape : P.t_shape;
+    const auto rec = gmem<const float>(src ? P.s_rec : P.t_rec);
+    const auto org = gmem<const float>(src ? P.s_orig : P.t_orig);
+    const auto shp = gmem<const float>(src ? P.s_shape : P.t_shape);
     // shape of point p (the identity for isotropic pairs, whose shapes are not computed)
     float sh[6];
 #pragma unroll
     for (int e = 0; e < 6; ++e) sh[e] = P.iso ? ((e == 0 || e == 3 || e == 5) ? 1.0f : 0.0f) : shp[(size_t)e * n + p];
     // label vector of point p, zero-padded to 4
-    float4 lab = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    vf4 lab = {0.0f, 0.0f, 0.0f, 0.0f};
     if (P.label_dim > 0) {
-        const float *l = (src ? P.src_label : P.tgt_label) + (size_t)P.label_dim * p;
+        const auto l = gmem<const float>(src ? P.src_label : P.tgt_label) + (size_t)P.label_dim * p;
         lab.x = l[0];
         if (P.label_dim > 1) lab.y = l[1];
         if (P.label_dim > 2) lab.z = l[2];
         if (P.label_dim > 3) lab.w = l[3];
     }
     if (src) {   // source: structure of arrays, read once per point and iteration
-        float *out = P.s_sorted;
+        const auto out = gmem(P.s_sorted);
 #pragma unroll
         for (int d = 0; d < 3; ++d) out[(size_t)d * n + pos] = rec[(size_t)d * n + p];
 #pragma unroll
         for (int e = 0; e < 6; ++e) out[(size_t)(3 + e) * n + pos] = sh[e];
 #pragma unroll
         for (int d = 0; d < 3; ++d) out[(size_t)(9 + d) * n + pos] = org[(size_t)d * n + p];
-        if (P.label_dim > 0) P.s_lab[pos] = lab;
+        if (P.label_dim > 0) gmem(reinterpret_cast<vf4 *>(P.s_lab))[pos] = lab;
     } else {     // target: 48-byte records, three float4 loads per candidate
         const int stage = J.kind - kJobStage;
-        float4 *out = reinterpret_cast<float4 *>(P.t_sorted[stage]) + 3 * (size_t)pos;
-        out[0] = make_float4(rec[p], rec[(size_t)n + p], rec[2 * (size_t)n + p], sh[0]);
-        out[1] = make_float4(sh[1], sh[2], sh[3], sh[4]);
-        out[2] = make_float4(sh[5], org[p], org[(size_t)n + p], org[2 * (size_t)n + p]);
-        if (P.label_dim > 0) P.t_lab[stage][pos] = lab;
+        const auto out = gmem(reinterpret_cast<vf4 *>(P.t_sorted[stage])) + 3 * (size_t)pos;
+        out[0] = vf4{rec[p], rec[(size_t)n + p], rec[2 * (size_t)n + p], sh[0]};
+        out[1] = vf4{sh[1], sh[2], sh[3], sh[4]};
+        out[2] = vf4{sh[5], org[p], org[(size_t)n + p], org[2 * (size_t)n + p]};
+        if (P.label_dim > 0) gmem(reinterpret_cast<vf4 *>(P.t_lab[stage]))[pos] = lab;
     }
 }
 
@@ -866,7 +942,7 @@ static void launch_knn(dim3 grid, SortJob *jobs, const PairDev *pairs, hipStream
 
 hipError_t launch_prepare(PairDev *pairs, int n_pairs, int max_n, SortJob *jobs, int n_jobs, int max_job_n,
                           int max_cells, int knn, hipStream_t s) {
-    hipLaunchKernelGGL(k_stats, dim3(2 * n_pairs), dim3(1024), 0, s, pairs);
+    hipLaunchKernelGGL(k_stats, dim3(2 * kStatBlocks, n_pairs), dim3(kBlock), 0, s, pairs);
     static_assert(4 + kMaxStages <= 32, "one setup thread per grid");
     hipLaunchKernelGGL(k_setup, dim3(n_pairs), dim3(32), 0, s, pairs);
     const int bx = (max_n + kBlock - 1) / kBlock;
@@ -886,7 +962,7 @@ hipError_t launch_prepare(PairDev *pairs, int n_pairs, int max_n, SortJob *jobs,
             hipLaunchKernelGGL(k_sort_scan, dim3(n_jobs), dim3(256), 0, s, jobs);
             hipLaunchKernelGGL(k_sort_down, dim3(tiles, n_jobs), dim3(256), 0, s, jobs, 8 * pass, in_tmp);
         }
-        hipLaunchKernelGGL(k_cells, dim3((max_cells + kBlock) / kBlock, n_jobs), dim3(kBlock), 0, s, jobs);
+        hipLaunchKernelGGL(k_cells, dim3((max_job_n + kBlock) / kBlock, n_jobs), dim3(kBlock), 0, s, jobs);
         if (knn > 0) {
             hipLaunchKernelGGL(k_knn_pts, dim3(jx, n_jobs), dim3(kBlock), 0, s, jobs, pairs);
             dim3 g((max_job_n + kPointsPerBlock - 1) / kPointsPerBlock, n_jobs);
