@@ -250,10 +250,14 @@ void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &p
         const int knn_cells_t = (int)std::min<long long>(16LL * nt + 64, (1 << 30) - 1);
         const int knn_cells_s = (int)std::min<long long>(16LL * ns + 64, (1 << 30) - 1);
         const int stage_cells = knn_cells_t;
+        // neighbour lists of the kNN jobs: the shape-only calls' workspace sizes
+        // do not know K, so their plans hold room for the largest
+        const int nbr_k = (mode == Mode::Shapes) ? kMaxKnn : I.p.knn;
         if ((mode == Mode::Register && !iso) || mode == Mode::Shapes) {
             SortJob J = make_job(kJobKnnTarget, nt, P.t_orig, knn_cells_t);
             J.want_shapes = 1;
             J.pts = A.take<float4>((size_t)J.n);
+            J.nbr = A.take<uint32_t>((size_t)J.n * nbr_k);
             J.shape_out = (mode == Mode::Shapes) ? I.shape_out : P.t_shape;
             P.job_knn_t = pl.d_jobs + job;
             if (base) pl.jobs[job] = J;
@@ -263,6 +267,7 @@ void build_plan(void *base, Mode mode, const std::vector<PairInput> &in, Plan &p
             SortJob J = make_job(kJobKnnSource, ns, P.s_orig, knn_cells_s);
             J.want_shapes = 1;
             J.pts = A.take<float4>((size_t)J.n);
+            J.nbr = A.take<uint32_t>((size_t)J.n * nbr_k);
             J.shape_out = P.s_shape;
             P.job_knn_s = pl.d_jobs + job;
             if (base) pl.jobs[job] = J;

@@ -66,6 +66,7 @@ struct SortJob {
     int morton;               // 1: key = 24-bit Morton code of the 256^3 grid cell (no cell table)
     float *shape_out;         // SoA [6][n], original point order
     float4 *pts;              // kNN jobs: {x, y, z, point index bits} in sorted order
+    uint32_t *nbr;            // kNN jobs: [n][knn] neighbour indices in sorted order (first 0xffffffff: none)
 };
 
 constexpr int kJobKnnTarget = 0;    // grid for the target's kNN shapes

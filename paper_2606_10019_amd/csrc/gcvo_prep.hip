@@ -1,12 +1,13 @@
 // Once-per-registration preparation on gfx950:
-//   k_stats    bounding boxes, FP64 centroid sums, finiteness (one block per cloud)
-//   k_setup    grids for every binning job, recentring shift, initial state
+//   k_stats    bounding boxes, FP64 centroid sums, finiteness (16 blocks per cloud)
+//   k_setup    their combination, grids for every binning job, recentring
+//              shift, initial state
 //   k_soa      AoS float32 input -> SoA original and recentred copies
 //   k_keys     linear cell key of every point of every job
 //   k_sort_*   stable multi-block LSD radix sort of (key, index) for all jobs,
 //   k_cells    the cell_start table of each grid
-//   k_knn      n nearest neighbours (FP64 distances, ties to the smaller index),
-//              covariance about the point, cyclic Jacobi, eigenvalue floor
+//   k_knn      n nearest neighbours (FP64 distances, ties to the smaller index)
+//   k_knn_shape  covariance about the point, cyclic Jacobi, eigenvalue floor
 //              (eq. (covariance), Remark 1)
 //   k_gather   sorted SoA arrays (recentred xyz + shape) for the pair kernel
 #include <float.h>
@@ -797,7 +798,8 @@ __device__ __forceinline__ void knn_shape(const SortJob &J, double rho, uint32_t
     for (int e = 0; e < 6; ++e) out[(size_t)e * n + p] = (float)S[e];
 }
 
-// kNN shapes of a job's points, kGroupLanes lanes per point.
+// K nearest neighbours of a job's points, kGroupLanes lanes per point; the
+// group's first lane stores them for the shape kernel.
 // Register budget of five waves per SIMD (96 VGPRs, no spills; 112 VGPRs and
 // four waves otherwise): 11 % shorter on a LiDAR cloud pair; six waves spill.
 template <int K>
@@ -811,15 +813,37 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     const int pos = (blockIdx.x * (kBlock / 64) + wave) * kGroupsPerWave + grp;
     if ((blockIdx.x * (kBlock / 64) + wave) * kGroupsPerWave >= n) return;   // whole wave idle
     const bool valid = pos < n;
-    const double rho = pairs[J.pair].rho;
     const Grid G = *J.grid;
     const uint32_t p = valid ? gmem(J.idx)[pos] : 0u;
     const float fx = gmem<const float>(J.x)[p], fy = gmem<const float>(J.y)[p], fz = gmem<const float>(J.z)[p];
     double md[K];    // merged K nearest (identical on the group's lanes)
     uint32_t mq[K];
     const bool done = knn_search<K>(J, G, wave, grp, q, valid, fx, fy, fz, md, mq);
-    if (!valid || q != 0 || !done) return;
-    knn_shape<K>(J, rho, p, fx, fy, fz, mq);
+    if (!valid || q != 0) return;
+    const auto nb = gmem(J.nbr) + (size_t)pos * K;
+    if (!done) {
+        nb[0] = 0xffffffffu;
+        return;
+    }
+#pragma unroll
+    for (int m = 0; m < K; ++m) nb[m] = mq[m];
+}
+
+// Shapes of a kNN job's points from their stored neighbours, one point per
+// thread (64 shapes per wave instead of one per 16-lane group).
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_knn_shape(SortJob *jobs, const PairDev *pairs) {
+    const SortJob &J = jobs[blockIdx.y];
+    if (!J.want_shapes || pairs[J.pair].nonfinite) return;
+    const int pos = blockIdx.x * kBlock + threadIdx.x;
+    if (pos >= J.n) return;
+    const auto nb = gmem<const uint32_t>(J.nbr) + (size_t)pos * K;
+    uint32_t mq[K];
+#pragma unroll
+    for (int m = 0; m < K; ++m) mq[m] = nb[m];
+    if (mq[0] == 0xffffffffu) return;
+    const vf4 pt = gmem(reinterpret_cast<const vf4 *>(J.pts))[pos];
+    knn_shape<K>(J, pairs[J.pair].rho, __float_as_uint(pt.w), pt.x, pt.y, pt.z, mq);
 }
 
 // ------------------------------------------------------------------ k_gather
@@ -936,8 +960,9 @@ hipError_t launch_eval_outputs(const PairDev *pairs, const OutSlot *slots, int n
 // ------------------------------------------------------------------ launcher
 
 template <int K>
-static void launch_knn(dim3 grid, SortJob *jobs, const PairDev *pairs, hipStream_t s) {
+static void launch_knn(dim3 grid, dim3 grid_pts, SortJob *jobs, const PairDev *pairs, hipStream_t s) {
     hipLaunchKernelGGL(k_knn<K>, grid, dim3(kBlock), 0, s, jobs, pairs);
+    hipLaunchKernelGGL(k_knn_shape<K>, grid_pts, dim3(kBlock), 0, s, jobs, pairs);
 }
 
 hipError_t launch_prepare(PairDev *pairs, int n_pairs, int max_n, SortJob *jobs, int n_jobs, int max_job_n,
@@ -965,23 +990,23 @@ hipError_t launch_prepare(PairDev *pairs, int n_pairs, int max_n, SortJob *jobs,
         hipLaunchKernelGGL(k_cells, dim3((max_job_n + kBlock) / kBlock, n_jobs), dim3(kBlock), 0, s, jobs);
         if (knn > 0) {
             hipLaunchKernelGGL(k_knn_pts, dim3(jx, n_jobs), dim3(kBlock), 0, s, jobs, pairs);
-            dim3 g((max_job_n + kPointsPerBlock - 1) / kPointsPerBlock, n_jobs);
+            dim3 g((max_job_n + kPointsPerBlock - 1) / kPointsPerBlock, n_jobs), gp(jx, n_jobs);
             switch (knn) {
-                case 2: launch_knn<2>(g, jobs, pairs, s); break;
-                case 3: launch_knn<3>(g, jobs, pairs, s); break;
-                case 4: launch_knn<4>(g, jobs, pairs, s); break;
-                case 5: launch_knn<5>(g, jobs, pairs, s); break;
-                case 6: launch_knn<6>(g, jobs, pairs, s); break;
-                case 7: launch_knn<7>(g, jobs, pairs, s); break;
-                case 8: launch_knn<8>(g, jobs, pairs, s); break;
-                case 9: launch_knn<9>(g, jobs, pairs, s); break;
-                case 10: launch_knn<10>(g, jobs, pairs, s); break;
-                case 11: launch_knn<11>(g, jobs, pairs, s); break;
-                case 12: launch_knn<12>(g, jobs, pairs, s); break;
-                case 13: launch_knn<13>(g, jobs, pairs, s); break;
-                case 14: launch_knn<14>(g, jobs, pairs, s); break;
-                case 15: launch_knn<15>(g, jobs, pairs, s); break;
-                case 16: launch_knn<16>(g, jobs, pairs, s); break;
+                case 2: launch_knn<2>(g, gp, jobs, pairs, s); break;
+                case 3: launch_knn<3>(g, gp, jobs, pairs, s); break;
+                case 4: launch_knn<4>(g, gp, jobs, pairs, s); break;
+                case 5: launch_knn<5>(g, gp, jobs, pairs, s); break;
+                case 6: launch_knn<6>(g, gp, jobs, pairs, s); break;
+                case 7: launch_knn<7>(g, gp, jobs, pairs, s); break;
+                case 8: launch_knn<8>(g, gp, jobs, pairs, s); break;
+                case 9: launch_knn<9>(g, gp, jobs, pairs, s); break;
+                case 10: launch_knn<10>(g, gp, jobs, pairs, s); break;
+                case 11: launch_knn<11>(g, gp, jobs, pairs, s); break;
+                case 12: launch_knn<12>(g, gp, jobs, pairs, s); break;
+                case 13: launch_knn<13>(g, gp, jobs, pairs, s); break;
+                case 14: launch_knn<14>(g, gp, jobs, pairs, s); break;
+                case 15: launch_knn<15>(g, gp, jobs, pairs, s); break;
+                case 16: launch_knn<16>(g, gp, jobs, pairs, s); break;
                 default: return hipErrorInvalidValue;
             }
         }
