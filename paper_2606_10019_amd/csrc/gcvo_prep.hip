@@ -5,7 +5,8 @@
 //   k_soa      AoS float32 input -> SoA original and recentred copies
 //   k_keys     linear cell key of every point of every job
 //   k_sort_*   stable multi-block LSD radix sort of (key, index) for all jobs,
-//   k_cells    the cell_start table of each grid
+//   k_cells    the cell_start table of each grid (and a kNN job's sorted
+//              point records)
 //   k_knn      n nearest neighbours (FP64 distances, ties to the smaller index)
 //   k_knn_shape  covariance about the point, cyclic Jacobi, eigenvalue floor
 //              (eq. (covariance), Remark 1)
@@ -484,6 +485,9 @@ __global__ __launch_bounds__(256) void k_sort_down(SortJob *jobs, int shift, int
 // after another, its 64 lanes storing consecutive cells; runs longer than
 // kLongRun cells (empty stretches of the grid, up to ~50k cells in a LiDAR
 // scene) are listed in LDS and written by the whole block.
+// A kNN job also gets its sorted point records {x, y, z, index bits} here, so
+// that a candidate of the kNN search is one 16-byte load instead of an index
+// load followed by three coordinate loads.
 __global__ __launch_bounds__(kBlock) void k_cells(SortJob *jobs) {
     const SortJob &J = jobs[blockIdx.y];
     if (J.morton || !J.cell_start) return;
@@ -491,17 +495,19 @@ __global__ __launch_bounds__(kBlock) void k_cells(SortJob *jobs) {
     if (blockIdx.x * kBlock > n) return;   // the whole block is past the end
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * kBlock + threadIdx.x;
-    // global-memory pointers: plain loads and stores, not flat ones
-    typedef const __attribute__((address_space(1))) uint32_t *GKey;
-    typedef __attribute__((address_space(1))) int *GCell;
-    const GKey keys = (GKey)J.keys;
-    const GCell cs = (GCell)J.cell_start;
+    const auto keys = gmem<const uint32_t>(J.keys);
+    const auto cs = gmem(J.cell_start);
     int first = 0, len = 0;     // cells [first, first + len) take position i
     if (i <= n) {
         const int prev = i > 0 ? (int)keys[i - 1] : -1;
         const int cur = i < n ? (int)keys[i] : ncells;
         first = prev + 1;
         len = cur - prev;
+    }
+    if (J.want_shapes && i < n) {
+        const uint32_t c = gmem(J.idx)[i];
+        gmem(reinterpret_cast<vf4 *>(J.pts))[i] =
+            vf4{gmem<const float>(J.x)[c], gmem<const float>(J.y)[c], gmem<const float>(J.z)[c], __uint_as_float(c)};
     }
     constexpr int kShortRun = 8, kLongRun = 4 * 64;
     __shared__ int long_first[kBlock], long_len[kBlock], long_pos[kBlock];
@@ -577,19 +583,6 @@ __device__ void jacobi_cyclic(double a[3][3], double v[3][3]) {
             }
         }
     }
-}
-
-// Sorted point records of a kNN job: {x, y, z, index} at each sorted position,
-// so that a candidate is one 16-byte load instead of an index load followed by
-// three coordinate loads.
-__global__ __launch_bounds__(kBlock) void k_knn_pts(SortJob *jobs, const PairDev *pairs) {
-    const SortJob &J = jobs[blockIdx.y];
-    if (!J.want_shapes || pairs[J.pair].nonfinite) return;
-    const int pos = blockIdx.x * kBlock + threadIdx.x;
-    if (pos >= J.n) return;
-    const uint32_t c = gmem(J.idx)[pos];
-    gmem(reinterpret_cast<vf4 *>(J.pts))[pos] =
-        vf4{gmem<const float>(J.x)[c], gmem<const float>(J.y)[c], gmem<const float>(J.z)[c], __uint_as_float(c)};
 }
 
 constexpr int kKnnMaxAttempts = 40;   // radius attempts 1.5 h 2^a, a < 40
@@ -989,7 +982,6 @@ hipError_t launch_prepare(PairDev *pairs, int n_pairs, int max_n, SortJob *jobs,
         }
         hipLaunchKernelGGL(k_cells, dim3((max_job_n + kBlock) / kBlock, n_jobs), dim3(kBlock), 0, s, jobs);
         if (knn > 0) {
-            hipLaunchKernelGGL(k_knn_pts, dim3(jx, n_jobs), dim3(kBlock), 0, s, jobs, pairs);
             dim3 g((max_job_n + kPointsPerBlock - 1) / kPointsPerBlock, n_jobs), gp(jx, n_jobs);
             switch (knn) {
                 case 2: launch_knn<2>(g, gp, jobs, pairs, s); break;
