@@ -154,7 +154,7 @@ struct OutSlot {
     int status;
 };
 
-struct BlockTask {   // one block of the pair kernel: a pair and a 256-point slice of its source
+struct BlockTask {   // one block of the pair kernel: a pair and a kPointsPerBlock-point slice of its source
     int pair;
     int block;       // block index within the pair
 };
