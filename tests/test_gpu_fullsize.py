@@ -177,6 +177,23 @@ def test_batched_shapes_and_evaluations_equal_single_calls():
     assert abs(b.f[1].item() - o.f) <= tol * o.f
 
 
+def test_batched_shapes_at_the_largest_neighbour_count():
+    """The shape-only workspace queries take no neighbour count, so a batch at
+    the largest one (GCVO_MAX_KNN = 16, the longest neighbour lists) must fit
+    the queried workspace; its shapes equal single calls bitwise and the
+    oracle's within 1e-6."""
+    specs, tgt, to, _, _ = _c1_pairs()
+    note("point_shapes_batch at knn 16 vs single calls and the oracle")
+    st = gcvo.gcvo_point_shapes_batch(tgt, to, 16, 0.01)
+    torch.cuda.synchronize()
+    for k in range(3):
+        a, b = int(to[k]), int(to[k + 1])
+        assert torch.equal(gcvo.shape_block(st, to, k), gcvo.gcvo_point_shapes(tgt[a:b], 16, 0.01))
+    S = gcvo.shape_block(st, to, 2).cpu().numpy().T.astype(np.float64)
+    ref = O.point_shapes(specs[2].target.astype(np.float64), 16, 0.01)
+    np.testing.assert_allclose(S, ref, atol=1e-6)
+
+
 def test_profile_counts_the_call():
     spec = synth.make_config1(0)
     prof = gcvo.gcvo_profile()
